@@ -1,0 +1,568 @@
+/*
+ * lbm_oracle.c -- plain, slow, FP64 CPU reference of the Lagrangian
+ * (reference-configuration) lattice Boltzmann method for nonlinear solids of
+ * Faust, Schlueter, Mueller & Mueller (2022).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. The HIP product path
+ * never calls it, and it shares no code, header or table with that path.
+ *
+ * It follows Algorithm 1 (Sec. 5) phase by phase, in physical units and with
+ * the lattice velocities C_i = (dX/dt) e_i as printed. Each phase is a plain
+ * loop over all sites that writes a full field before the next phase starts.
+ * Streaming is done by *push* (Sec. 3, eq. (5) read literally).
+ *
+ * Readings where the paper is silent or ambiguous:
+ *  R1  The second-order moment that enters the equilibrium is the
+ *      populations' own second moment Pi = sum_i C_i C_i f_i (Sec. 4 and
+ *      Sec. 5: the LBM itself evolves Pbar through the third equation of the
+ *      chain (19)). The finite-difference Poisson stress Pbar(H) of eq. (15)
+ *      is used only inside the source term (23) and in the traction
+ *      transform of Sec. 6.
+ *  R2  Default time level of the source in the moment step: the
+ *      predictor-corrector of the footnote in Sec. 5 (evaluates 1S at
+ *      t + dt as the Crank-Nicolson footnote of Sec. 4 asks). The literal
+ *      Algorithm 1 level (1S at t) is the "explicit" scheme.
+ *  Q3  c_s and C_s are the same: C_s = sqrt(mu/rho0), and dX/dt = sqrt(3) C_s
+ *      (the time steps printed in Sec. 7 follow from it).
+ *  Q4  The trapezoidal rule (24) carries the factor dt.
+ *  Q7  r in the collision is sum_i f_i; at start r0 = -rho0 div u0 (eq. (18)).
+ *  Q8  Gradient and divergence are radius-1 central differences; the source
+ *      is their composition (radius 2).
+ *  Q11 Walls lie half a spacing outside the first and last node rows.
+ *      Ghost displacement rows for the finite differences: at a wall with a
+ *      momentum (Dirichlet) rule, the quadratic through the wall value and
+ *      the two nearest rows; at a traction (Neumann) wall, constant
+ *      extrapolation of the nearest row. The boundary moments of the
+ *      anti-bounce-back rule (26) -- r_bd, the tangential entry of Pbar* and
+ *      P + Pbar in the traction transform -- are taken at the node row next
+ *      to the wall (zeroth-order extrapolation). Higher-order extrapolation
+ *      of any of them makes the scheme grow without bound near the wall.
+ *  Q12 The anti-bounce-back rule uses r_bd in both places (eq. (26)).
+ *
+ * Layout: every field is structure-of-arrays, component-major, row-major
+ * inside a component: f[i][y][x] with i in the oracle's own D2Q9 order
+ * i = 3*(ey+1) + (ex+1), u[a][y][x], j[a][y][x], P[a][b][y][x] (a,b in {x,y}).
+ *
+ * The x direction is periodic. The y edges are periodic, momentum walls or
+ * traction walls.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_PERIODIC 0
+#define ORACLE_DIRICHLET_J 1
+#define ORACLE_NEUMANN_T 2
+
+typedef struct {
+    int nx, ny;
+    double dx;          /* lattice spacing dX */
+    double rho0;        /* reference density */
+    double lam, mu;     /* Lame parameters of the neo-Hooke law (27) */
+    double tau_over_dt; /* relaxation time tau / dt */
+    double body[2];     /* body force per unit mass b */
+    int scheme;         /* 0: predictor-corrector (R2), 1: explicit (Alg. 1) */
+    int bc_ymin, bc_ymax;        /* ORACLE_* kind of the bottom / top edge */
+    double val_ymin[2], val_ymax[2]; /* j* (Dirichlet) or T* (Neumann) */
+} oracle_params;
+
+/* ---- D2Q9 lattice (Sec. 3): 9 velocities incl. the rest velocity ---- */
+
+static int ex_of(int i) { return i % 3 - 1; }
+static int ey_of(int i) { return i / 3 - 1; }
+static int opposite(int i) { return 8 - i; }
+static double weight(int i)
+{
+    int n = abs(ex_of(i)) + abs(ey_of(i));
+    if (n == 0) return 4.0 / 9.0;
+    if (n == 1) return 1.0 / 9.0;
+    return 1.0 / 36.0;
+}
+
+/* shear-wave speed squared C_s^2 = mu / rho0 (Sec. 4, after eq. (15)) */
+static double cs2(const oracle_params *p) { return p->mu / p->rho0; }
+
+/* dt = dX / (sqrt(3) C_s): the lattice speed is sqrt(3) times C_s (Q3) */
+double oracle_dt(const oracle_params *p)
+{
+    return p->dx / (sqrt(3.0) * sqrt(cs2(p)));
+}
+
+static double lattice_speed(const oracle_params *p) { return p->dx / oracle_dt(p); }
+
+/* ---- constitutive law (Sec. 7, eq. (27)) ----
+ * W = mu/2 (I_C - 2) + lam/4 (J^2 - 1) - lam/2 log J - mu log J, with
+ * C = F^T F, F = I + H. Its derivative is the first Piola-Kirchhoff stress
+ * P = dW/dF = mu (F - F^-T) + lam/2 (J^2 - 1) F^-T.
+ * Tensors are stored row-major: T[0]=T11, T[1]=T12, T[2]=T21, T[3]=T22. */
+void oracle_piola(double lam, double mu, const double H[4], double P[4])
+{
+    double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
+    double J = F11 * F22 - F12 * F21;
+    /* F^-1 = [[F22, -F12], [-F21, F11]] / J, so F^-T = [[F22, -F21], [-F12, F11]] / J */
+    double FiT11 = F22 / J, FiT12 = -F21 / J, FiT21 = -F12 / J, FiT22 = F11 / J;
+    double a = 0.5 * lam * (J * J - 1.0);
+    P[0] = mu * (F11 - FiT11) + a * FiT11;
+    P[1] = mu * (F12 - FiT12) + a * FiT12;
+    P[2] = mu * (F21 - FiT21) + a * FiT21;
+    P[3] = mu * (F22 - FiT22) + a * FiT22;
+}
+
+double oracle_strain_energy(double lam, double mu, const double H[4])
+{
+    double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
+    double J = F11 * F22 - F12 * F21;
+    double IC = F11 * F11 + F12 * F12 + F21 * F21 + F22 * F22; /* tr(F^T F) */
+    return 0.5 * mu * (IC - 2.0) + 0.25 * lam * (J * J - 1.0) - 0.5 * lam * log(J) - mu * log(J);
+}
+
+/* Poisson stress Pbar(H) = -mu (H + H^T + tr H I), eq. (15) */
+void oracle_poisson(double mu, const double H[4], double Pb[4])
+{
+    double tr = H[0] + H[3];
+    Pb[0] = -mu * (H[0] + H[0] + tr);
+    Pb[1] = -mu * (H[1] + H[2]);
+    Pb[2] = -mu * (H[2] + H[1]);
+    Pb[3] = -mu * (H[3] + H[3] + tr);
+}
+
+/* lattice velocity C_i = (dX/dt) e_i */
+void oracle_velocity(const oracle_params *p, int i, double C[2])
+{
+    double c = lattice_speed(p);
+    C[0] = c * ex_of(i);
+    C[1] = c * ey_of(i);
+}
+
+double oracle_weight(int i) { return weight(i); }
+
+/* equilibrium (Sec. 5, eq. (20)):
+ * f_i^eq = w_i ( r + C_i.j / C_s^2
+ *                + (Pb - r C_s^2 I) : (C_i C_i - C_s^2 I) / (2 C_s^4) ) */
+void oracle_equilibrium(const oracle_params *p, double r, const double j[2],
+                        const double Pb[4], double feq[9])
+{
+    double s2 = cs2(p);
+    for (int i = 0; i < 9; ++i) {
+        double C[2];
+        oracle_velocity(p, i, C);
+        double A[4] = {Pb[0] - r * s2, Pb[1], Pb[2], Pb[3] - r * s2};
+        double B[4] = {C[0] * C[0] - s2, C[0] * C[1], C[1] * C[0], C[1] * C[1] - s2};
+        double AB = A[0] * B[0] + A[1] * B[1] + A[2] * B[2] + A[3] * B[3];
+        feq[i] = weight(i) * (r + (C[0] * j[0] + C[1] * j[1]) / s2 + AB / (2.0 * s2 * s2));
+    }
+}
+
+/* source populations (Sec. 5, eq. (22)): psi_i = w_i C_i . 1S / C_s^2 */
+void oracle_source_pop(const oracle_params *p, const double S[2], double psi[9])
+{
+    double s2 = cs2(p);
+    for (int i = 0; i < 9; ++i) {
+        double C[2];
+        oracle_velocity(p, i, C);
+        psi[i] = weight(i) * (C[0] * S[0] + C[1] * S[1]) / s2;
+    }
+}
+
+/* ---- indexing helpers ---- */
+
+static size_t at(const oracle_params *p, int y, int x) { return (size_t)y * p->nx + x; }
+static int wrap(int a, int n) { return ((a % n) + n) % n; }
+static size_t plane(const oracle_params *p) { return (size_t)p->nx * p->ny; }
+
+/* Ghost displacement rows (Q11). ue holds rows -2..ny+1 (ny+4 rows), so row y
+ * of the lattice is row y+2 of ue. t is the time at which u is taken; a
+ * momentum wall with value j* has moved by j* t / rho0 (it starts at rest). */
+static void extend_u(const oracle_params *p, const double *u, double t, double *ue)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t eplane = (size_t)nx * (ny + 4);
+    for (int a = 0; a < 2; ++a) {
+        const double *ua = u + a * plane(p);
+        double *ea = ue + a * eplane;
+        for (int y = 0; y < ny; ++y)
+            memcpy(ea + (size_t)(y + 2) * nx, ua + (size_t)y * nx, sizeof(double) * nx);
+        for (int x = 0; x < nx; ++x) {
+            double u0 = ua[at(p, 0, x)], u1 = ua[at(p, 1, x)];
+            double v0 = ua[at(p, ny - 1, x)], v1 = ua[at(p, ny - 2, x)];
+            double *lo1 = ea + (size_t)1 * nx + x, *lo2 = ea + x;           /* rows -1, -2 */
+            double *hi1 = ea + (size_t)(ny + 2) * nx + x, *hi2 = ea + (size_t)(ny + 3) * nx + x; /* ny, ny+1 */
+            /* bottom edge */
+            if (p->bc_ymin == ORACLE_PERIODIC) {
+                *lo1 = ua[at(p, ny - 1, x)];
+                *lo2 = ua[at(p, ny - 2, x)];
+            } else if (p->bc_ymin == ORACLE_DIRICHLET_J) {
+                /* quadratic through (y=-1/2, uw), (0, u0), (1, u1) */
+                double uw = p->val_ymin[a] * t / p->rho0;
+                *lo1 = (8.0 / 3.0) * uw - 2.0 * u0 + u1 / 3.0;
+                *lo2 = 8.0 * uw - 9.0 * u0 + 2.0 * u1;
+            } else {
+                /* traction wall: constant extrapolation of the first row */
+                *lo1 = u0;
+                *lo2 = u0;
+            }
+            /* top edge */
+            if (p->bc_ymax == ORACLE_PERIODIC) {
+                *hi1 = ua[at(p, 0, x)];
+                *hi2 = ua[at(p, 1, x)];
+            } else if (p->bc_ymax == ORACLE_DIRICHLET_J) {
+                double uw = p->val_ymax[a] * t / p->rho0;
+                *hi1 = (8.0 / 3.0) * uw - 2.0 * v0 + v1 / 3.0;
+                *hi2 = 8.0 * uw - 9.0 * v0 + 2.0 * v1;
+            } else {
+                *hi1 = v0;
+                *hi2 = v0;
+            }
+        }
+    }
+}
+
+/* displacement gradient H_ab = d_b u_a by central differences (eq. (10),
+ * Sec. 5), at lattice row y (may be -1 or ny) from the extended field. */
+static void grad_u(const oracle_params *p, const double *ue, int y, int x, double H[4])
+{
+    int nx = p->nx, ny = p->ny;
+    size_t eplane = (size_t)nx * (ny + 4);
+    int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
+    for (int a = 0; a < 2; ++a) {
+        const double *ea = ue + a * eplane;
+        double dudx = (ea[(size_t)(y + 2) * nx + xp] - ea[(size_t)(y + 2) * nx + xm]) / (2.0 * p->dx);
+        double dudy = (ea[(size_t)(y + 3) * nx + x] - ea[(size_t)(y + 1) * nx + x]) / (2.0 * p->dx);
+        H[2 * a + 0] = dudx;
+        H[2 * a + 1] = dudy;
+    }
+}
+
+/* K = P(H) + Pbar(H) on rows -1..ny (ny+2 rows; row y at index y+1). */
+static void stress_sum(const oracle_params *p, const double *ue, double *K)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t kplane = (size_t)nx * (ny + 2);
+#pragma omp parallel for schedule(static)
+    for (int y = -1; y <= ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            double H[4], P[4], Pb[4];
+            grad_u(p, ue, y, x, H);
+            oracle_piola(p->lam, p->mu, H, P);
+            oracle_poisson(p->mu, H, Pb);
+            for (int c = 0; c < 4; ++c) K[c * kplane + (size_t)(y + 1) * nx + x] = P[c] + Pb[c];
+        }
+}
+
+/* 1S_a = rho0 b_a + d_b (P_ab + Pbar_ab), eq. (23), central divergence. */
+static void source_field(const oracle_params *p, const double *K, double *S)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t kplane = (size_t)nx * (ny + 2);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
+            for (int a = 0; a < 2; ++a) {
+                const double *Ka1 = K + (2 * a + 0) * kplane; /* K_a1 */
+                const double *Ka2 = K + (2 * a + 1) * kplane; /* K_a2 */
+                double div = (Ka1[(size_t)(y + 1) * nx + xp] - Ka1[(size_t)(y + 1) * nx + xm]) / (2.0 * p->dx)
+                           + (Ka2[(size_t)(y + 2) * nx + x] - Ka2[(size_t)y * nx + x]) / (2.0 * p->dx);
+                S[a * plane(p) + at(p, y, x)] = p->rho0 * p->body[a] + div;
+            }
+        }
+}
+
+/* source 1S(u) at time t for the whole lattice */
+static void source_of_u(const oracle_params *p, const double *u, double t, double *S)
+{
+    int nx = p->nx, ny = p->ny;
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    double *K = malloc(sizeof(double) * 4 * (size_t)nx * (ny + 2));
+    extend_u(p, u, t, ue);
+    stress_sum(p, ue, K);
+    source_field(p, K, S);
+    free(ue);
+    free(K);
+}
+
+/* zeroth moment r = sum_i f_i and second moment Pi = sum_i C_i C_i f_i */
+static void moments_r_pi(const oracle_params *p, const double *f, size_t s, double *r, double Pi[4])
+{
+    *r = 0.0;
+    Pi[0] = Pi[1] = Pi[2] = Pi[3] = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        double C[2], fi = f[i * plane(p) + s];
+        oracle_velocity(p, i, C);
+        *r += fi;
+        Pi[0] += C[0] * C[0] * fi;
+        Pi[1] += C[0] * C[1] * fi;
+        Pi[2] += C[1] * C[0] * fi;
+        Pi[3] += C[1] * C[1] * fi;
+    }
+}
+
+/* Boundary moments at a traction wall (Sec. 6, eq. (26) and the traction
+ * transform): r_bd and Pbar* for column x. The wall lies half a spacing
+ * beyond row y0; s is the outward normal sign. Every quantity is extrapolated
+ * to the wall at zeroth order, i.e. taken from row y0 (reading Q11). */
+static void traction_wall_moments(const oracle_params *p, const double *f, const double *K,
+                                  int y0, int x, double s, const double T[2],
+                                  double *rbd, double Pstar[4])
+{
+    int nx = p->nx;
+    size_t kplane = (size_t)nx * (p->ny + 2);
+    double r0, Pi0[4], Kw[4];
+    moments_r_pi(p, f, at(p, y0, x), &r0, Pi0);
+    *rbd = r0;
+    for (int c = 0; c < 4; ++c) Kw[c] = K[c * kplane + (size_t)(y0 + 1) * nx + x];
+    /* Pbar N = -T* + (P + Pbar) N with N = (0, s): Pbar_a2 s = -T_a + K_a2 s.
+     * In the wall frame the normal row and column take these values (the
+     * tensor is symmetric); the tangential entry keeps the moment Pi_11. */
+    double q1 = (-T[0] + Kw[1] * s) / s;
+    double q2 = (-T[1] + Kw[3] * s) / s;
+    Pstar[0] = Pi0[0];
+    Pstar[1] = q1;
+    Pstar[2] = q1;
+    Pstar[3] = q2;
+}
+
+/* anti-bounce-back value (eq. (26)) for outgoing direction i */
+static double abb_term(const oracle_params *p, int i, double rbd, const double Pstar[4])
+{
+    double s2 = cs2(p), C[2];
+    oracle_velocity(p, i, C);
+    double A[4] = {Pstar[0] - rbd * s2, Pstar[1], Pstar[2], Pstar[3] - rbd * s2};
+    double B[4] = {C[0] * C[0] - s2, C[0] * C[1], C[1] * C[0], C[1] * C[1] - s2};
+    double AB = A[0] * B[0] + A[1] * B[1] + A[2] * B[2] + A[3] * B[3];
+    return 2.0 * weight(i) * (rbd + AB / (2.0 * s2 * s2));
+}
+
+/* bounce-back correction (eq. (25)) for outgoing direction i */
+static double bb_term(const oracle_params *p, int i, const double jstar[2])
+{
+    double C[2];
+    oracle_velocity(p, i, C);
+    return -2.0 / cs2(p) * weight(i) * (C[0] * jstar[0] + C[1] * jstar[1]);
+}
+
+/* Initialisation (Algorithm 1): r0 = -rho0 div u0 (eq. (18)), j0 = rho0 v0,
+ * Pbar0 = Pbar(H(u0)) (eq. (15)), f = f^eq(r0, j0, Pbar0) (eq. (20)). */
+int oracle_init(const oracle_params *p, const double *u0, const double *v0,
+                double *f, double *u, double *j)
+{
+    int nx = p->nx, ny = p->ny;
+    if (nx < 5 || ny < 5) return -1;
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    extend_u(p, u0, 0.0, ue);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t s = at(p, y, x);
+            double H[4], Pb[4], jj[2], feq[9];
+            grad_u(p, ue, y, x, H);
+            oracle_poisson(p->mu, H, Pb);
+            double r = -p->rho0 * (H[0] + H[3]);
+            jj[0] = p->rho0 * v0[s];
+            jj[1] = p->rho0 * v0[plane(p) + s];
+            oracle_equilibrium(p, r, jj, Pb, feq);
+            for (int i = 0; i < 9; ++i) f[i * plane(p) + s] = feq[i];
+            u[s] = u0[s];
+            u[plane(p) + s] = u0[plane(p) + s];
+            j[s] = jj[0];
+            j[plane(p) + s] = jj[1];
+        }
+    free(ue);
+    return 0;
+}
+
+/* One time step of Algorithm 1 with readings R1/R2. step is the index n of
+ * the state on entry (time t = n dt). */
+static void one_step(const oracle_params *p, double *f, double *u, double *j, long step)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t N = plane(p);
+    double dt = oracle_dt(p), t = step * dt;
+    double omega = 1.0 / p->tau_over_dt; /* dt / tau */
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    double *K = malloc(sizeof(double) * 4 * (size_t)nx * (ny + 2));
+    double *S = malloc(sizeof(double) * 2 * N);
+    double *fcol = malloc(sizeof(double) * 9 * N);
+    double *fnew = malloc(sizeof(double) * 9 * N);
+    double *jf = malloc(sizeof(double) * 2 * N);
+    double *Sp = malloc(sizeof(double) * 2 * N);
+
+    /* 1. stress sum K(u_n) and source 1S_n (eq. (23)) */
+    extend_u(p, u, t, ue);
+    stress_sum(p, ue, K);
+    source_field(p, K, S);
+
+    /* 2. moments of f_n, equilibrium (20), source populations (22), collision (4) */
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t s = at(p, y, x);
+            double r, Pi[4], jj[2] = {j[s], j[N + s]}, SS[2] = {S[s], S[N + s]}, feq[9], psi[9];
+            moments_r_pi(p, f, s, &r, Pi);
+            oracle_equilibrium(p, r, jj, Pi, feq);
+            oracle_source_pop(p, SS, psi);
+            for (int i = 0; i < 9; ++i) {
+                double fi = f[i * N + s];
+                fcol[i * N + s] = fi - omega * (fi - feq[i]) + dt * (1.0 - 0.5 * omega) * psi[i];
+            }
+        }
+
+    /* 3. push streaming (5); links that cross a wall are handled below */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < 9; ++i) {
+        int ex = ex_of(i), ey = ey_of(i);
+        for (int y = 0; y < ny; ++y) {
+            int yt = y + ey;
+            if (yt < 0 || yt >= ny) {
+                int wall_kind = yt < 0 ? p->bc_ymin : p->bc_ymax;
+                if (wall_kind != ORACLE_PERIODIC) continue;
+                yt = wrap(yt, ny);
+            }
+            for (int x = 0; x < nx; ++x)
+                fnew[i * N + at(p, yt, wrap(x + ex, nx))] = fcol[i * N + at(p, y, x)];
+        }
+    }
+
+    /* 4. boundary rules at the walls (Sec. 6, eqs. (25), (26)) */
+    for (int side = 0; side < 2; ++side) {
+        int kind = side == 0 ? p->bc_ymin : p->bc_ymax;
+        if (kind == ORACLE_PERIODIC) continue;
+        int y0 = side == 0 ? 0 : ny - 1;        /* node row next to the wall */
+        int eyout = side == 0 ? -1 : 1;         /* e_y of the links that leave through the wall */
+        const double *val = side == 0 ? p->val_ymin : p->val_ymax;
+        for (int x = 0; x < nx; ++x) {
+            double rbd = 0.0, Pstar[4] = {0, 0, 0, 0};
+            if (kind == ORACLE_NEUMANN_T)
+                traction_wall_moments(p, f, K, y0, x, (double)eyout, val, &rbd, Pstar);
+            for (int i = 0; i < 9; ++i) {
+                if (ey_of(i) != eyout) continue;
+                double fc = fcol[i * N + at(p, y0, x)];
+                double v = kind == ORACLE_DIRICHLET_J ? fc + bb_term(p, i, val)
+                                                      : -fc + abb_term(p, i, rbd, Pstar);
+                fnew[opposite(i) * N + at(p, y0, x)] = v;
+            }
+        }
+    }
+
+    /* 5. first moment of the streamed populations, jf = sum_i C_i f_i */
+#pragma omp parallel for schedule(static)
+    for (size_t s = 0; s < N; ++s) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double C[2];
+            oracle_velocity(p, i, C);
+            a0 += C[0] * fnew[i * N + s];
+            a1 += C[1] * fnew[i * N + s];
+        }
+        jf[s] = a0;
+        jf[N + s] = a1;
+    }
+
+    /* 6. source at the new time level: predictor-corrector (R2) or explicit */
+    if (p->scheme == 0) {
+        double *up = malloc(sizeof(double) * 2 * N);
+        for (int a = 0; a < 2; ++a)
+            for (size_t s = 0; s < N; ++s) {
+                double jp = jf[a * N + s] + 0.5 * dt * S[a * N + s];
+                up[a * N + s] = u[a * N + s] + dt / (2.0 * p->rho0) * (jp + j[a * N + s]);
+            }
+        source_of_u(p, up, t + dt, Sp);
+        free(up);
+    } else {
+        memcpy(Sp, S, sizeof(double) * 2 * N);
+    }
+
+    /* 7. moments with half source (6) and trapezoidal displacement (24) */
+    for (int a = 0; a < 2; ++a)
+        for (size_t s = 0; s < N; ++s) {
+            double jnew = jf[a * N + s] + 0.5 * dt * Sp[a * N + s];
+            u[a * N + s] += dt / (2.0 * p->rho0) * (jnew + j[a * N + s]);
+            j[a * N + s] = jnew;
+        }
+    memcpy(f, fnew, sizeof(double) * 9 * N);
+
+    free(ue);
+    free(K);
+    free(S);
+    free(fcol);
+    free(fnew);
+    free(jf);
+    free(Sp);
+}
+
+int oracle_step(const oracle_params *p, double *f, double *u, double *j, long step0, int nsteps)
+{
+    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5) return -1;
+    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, step0 + n);
+    return 0;
+}
+
+/* Output fields: v = j / rho0 and the first Piola-Kirchhoff stress P(H(u)). */
+int oracle_fields(const oracle_params *p, const double *u, const double *j, double t,
+                  double *v, double *P)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t N = plane(p);
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    extend_u(p, u, t, ue);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t s = at(p, y, x);
+            double H[4], PP[4];
+            grad_u(p, ue, y, x, H);
+            oracle_piola(p->lam, p->mu, H, PP);
+            for (int c = 0; c < 4; ++c) P[c * N + s] = PP[c];
+            v[s] = j[s] / p->rho0;
+            v[N + s] = j[N + s] / p->rho0;
+        }
+    free(ue);
+    return 0;
+}
+
+/* Diagnostics: out[0..1] = sum of j, out[2] = sum of r, out[3] = energy
+ * sum (|j|^2/(2 rho0) + W) dX^2, out[4] = min J, out[5] = max spectral norm of
+ * the Green-Lagrange strain E = (F^T F - I)/2, out[6] = 1 if any value is not
+ * finite or J <= 0. Sums run in plain row-major order. */
+int oracle_diagnostics(const oracle_params *p, const double *f, const double *u,
+                       const double *j, double t, double out[7])
+{
+    int nx = p->nx, ny = p->ny;
+    size_t N = plane(p);
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    extend_u(p, u, t, ue);
+    double sj0 = 0, sj1 = 0, sr = 0, en = 0, minJ = INFINITY, maxE = 0;
+    int bad = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t s = at(p, y, x);
+            double H[4], r = 0.0;
+            grad_u(p, ue, y, x, H);
+            for (int i = 0; i < 9; ++i) r += f[i * N + s];
+            double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
+            double J = F11 * F22 - F12 * F21;
+            double E11 = 0.5 * (F11 * F11 + F21 * F21 - 1.0);
+            double E12 = 0.5 * (F11 * F12 + F21 * F22);
+            double E22 = 0.5 * (F12 * F12 + F22 * F22 - 1.0);
+            double mean = 0.5 * (E11 + E22), dev = sqrt(0.25 * (E11 - E22) * (E11 - E22) + E12 * E12);
+            double En = fmax(fabs(mean + dev), fabs(mean - dev));
+            double jj0 = j[s], jj1 = j[N + s];
+            sj0 += jj0;
+            sj1 += jj1;
+            sr += r;
+            if (!(J > 0.0) || !isfinite(jj0) || !isfinite(jj1) || !isfinite(u[s]) || !isfinite(u[N + s]))
+                bad = 1;
+            else
+                en += ((jj0 * jj0 + jj1 * jj1) / (2.0 * p->rho0) + oracle_strain_energy(p->lam, p->mu, H)) * p->dx * p->dx;
+            if (J < minJ) minJ = J;
+            if (En > maxE) maxE = En;
+        }
+    free(ue);
+    out[0] = sj0;
+    out[1] = sj1;
+    out[2] = sr;
+    out[3] = en;
+    out[4] = minJ;
+    out[5] = maxE;
+    out[6] = bad;
+    return 0;
+}
