@@ -1,0 +1,149 @@
+/*
+ * lbm_solid.h -- C ABI of the MI355X (gfx950) implementation of the
+ * per-time-step lattice update of the Lagrangian lattice Boltzmann method for
+ * nonlinear solids of Faust, Schlueter, Mueller & Mueller (2022).
+ *
+ * One handle holds one plate: a D2Q9 lattice of nx * ny sites in the
+ * reference configuration (Sec. 3), a compressible neo-Hooke material
+ * (Sec. 7, eq. (27)) and per-edge boundary rules (Sec. 6). lbm_step advances
+ * the state by Algorithm 1 (Sec. 5):
+ *   source 1S = rho0 b + div(P(H) + Pbar(H)) by central differences (eq. (23)),
+ *   BGK collision with He forcing (eq. (4)) towards the equilibrium (eq. (20)),
+ *   streaming (eq. (5)), the boundary rules (eqs. (25), (26)), moments with
+ *   the half source (eq. (6)) and the trapezoidal displacement update (eq. (24)).
+ * The second moment that enters the equilibrium is the populations' own
+ * second moment; the source of the moment step is taken at t + dt by a
+ * predictor-corrector (the footnote on stability in Sec. 5), or at t as
+ * printed in Algorithm 1 (LBM_SCHEME_EXPLICIT).
+ *
+ * Units: every value that crosses this ABI is in physical units (lengths in
+ * the unit of dx, rho0, lambda, mu, velocities, stresses). The time step is
+ * fixed by the material: dt = dx / (sqrt(3) sqrt(mu / rho0)) (Sec. 7 prints
+ * it for two spacings).
+ *
+ * Memory: the library never allocates device memory. The caller passes a
+ * device workspace of at least lbm_workspace_bytes() bytes and a HIP stream;
+ * both must outlive the handle. Host arrays are copied during the call that
+ * receives them and stay owned by the caller.
+ *
+ * Errors: every call returns an lbm_status; no exception crosses the ABI.
+ * lbm_last_error() gives a message for the last failing call on a handle.
+ * A handle is not thread-safe; distinct handles on distinct streams may run
+ * concurrently.
+ *
+ * Host field layout: structure of arrays, component-major, x fastest:
+ * u[a][y][x] and v[a][y][x] with a in {x, y}; P[a][b][y][x] row-major
+ * (P11, P12, P21, P22). Node (x, y) sits at X = (x dx, y dx).
+ */
+#ifndef LBM_SOLID_H
+#define LBM_SOLID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_solver lbm_solver;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,         /* invalid argument */
+    LBM_ERR_NOMEM = -2,       /* workspace too small */
+    LBM_ERR_HIP = -3,         /* a HIP runtime call failed */
+    LBM_ERR_STATE = -4,       /* call out of order (e.g. step before set_fields) */
+    LBM_ERR_UNSTABLE = -5,    /* J <= 0 or a non-finite value appeared */
+    LBM_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+} lbm_status;
+
+/* Storage and arithmetic precision.
+ * FP64: populations, displacement, momentum and arithmetic in double.
+ * FP32: all in float.
+ * FP16_STORE / BF16_STORE: populations stored in half / bfloat16, scaled by a
+ *   per-plate power of two chosen at lbm_set_fields; displacement in double,
+ *   momentum in float, arithmetic in float. */
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_STORE = 2, LBM_BF16_STORE = 3 } lbm_precision;
+
+/* Time level of the source in the moment step (Sec. 5). */
+typedef enum { LBM_SCHEME_PC = 0, LBM_SCHEME_EXPLICIT = 1 } lbm_scheme;
+
+typedef enum { LBM_EDGE_XMIN = 0, LBM_EDGE_XMAX = 1, LBM_EDGE_YMIN = 2, LBM_EDGE_YMAX = 3 } lbm_edge;
+
+/* Boundary rules of Sec. 6. Walls lie half a spacing outside the outermost
+ * node row. DIRICHLET_J: bounce-back with wall momentum j* (eq. (25)), value
+ * = j* (2 components). NEUMANN_T: anti-bounce-back with the boundary Poisson
+ * stress built from the traction T* (eq. (26) and the traction transform),
+ * value = T* (2 components). */
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_DIRICHLET_J = 1, LBM_BC_NEUMANN_T = 2 } lbm_bc;
+
+typedef struct {
+    double momentum[2];  /* sum over sites of j = rho0 v */
+    double mass_moment;  /* sum over sites of r = sum_i f_i */
+    double energy;       /* sum (|j|^2 / (2 rho0) + W(F)) dx^2, W of eq. (27) */
+    double min_J;        /* smallest det F */
+    double max_strain;   /* largest spectral norm of E = (F^T F - I) / 2 */
+    int32_t unstable;    /* 1 if J <= 0 or a non-finite value was met */
+    int32_t reserved;
+    int64_t steps;       /* steps done since lbm_set_fields */
+} lbm_diagnostics;
+
+/* Exact device bytes a plate of nx * ny sites needs at precision p
+ * (two copies of the state plus staging and reduction scratch). */
+size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p);
+
+/* Create a handle. nx, ny >= 5; dx > 0. dev_workspace: device memory of
+ * ws_bytes >= lbm_workspace_bytes(nx, ny, p) bytes, 256-byte aligned.
+ * hip_stream: a hipStream_t (NULL = the default stream). */
+lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s,
+                      void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_solver **out);
+
+/* Material (Sec. 7): reference density rho0 > 0, Lame parameters with
+ * mu > 0 and lambda + mu > 0, relaxation time tau as tau/dt > 1/2. */
+lbm_status lbm_set_material(lbm_solver *h, double rho0, double lambda, double mu, double tau_over_dt);
+
+/* Uniform body force per unit mass b (the rho0 b term of eq. (23)). */
+lbm_status lbm_set_body_force(lbm_solver *h, const double b[2]);
+
+/* Boundary rule of one edge. Periodic edges come in pairs. This build
+ * supports periodic x edges only (LBM_ERR_UNSUPPORTED otherwise); the y
+ * edges take any rule. value may be NULL for LBM_BC_PERIODIC. Takes effect
+ * from the next lbm_step (so a load history can be applied step by step). */
+lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double value[2]);
+
+/* Initial displacement u0 and velocity v0 (host, [2][ny][nx], physical
+ * units). Builds f = f^eq(r0, j0, Pbar(H(u0))) with r0 = -rho0 div u0 and
+ * j0 = rho0 v0 (Algorithm 1, initialisation) and resets the step count.
+ * Synchronises the stream. Needs the material to be set first. */
+lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0);
+
+/* Enqueue nsteps time steps on the stream and return at once. */
+lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
+
+/* Read u, v = j / rho0, the first Piola-Kirchhoff stress P(H(u)) and the
+ * diagnostics. Any pointer may be NULL. Synchronises the stream. Returns
+ * LBM_ERR_UNSTABLE (after filling the outputs) if the unstable flag is set. */
+lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_diagnostics *d);
+
+/* Launch shape of the step kernel: threads per block (64, 128 or 256; one
+ * lattice column per thread) and row segments per column strip
+ * (1 <= n_segs <= ny). Results do not depend on it (bitwise); it only
+ * changes speed. lbm_create picks a default; the autotuner overrides it. */
+lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs);
+lbm_status lbm_get_tiling(const lbm_solver *h, int *block, int *n_segs);
+
+/* Time step dt of the handle's material. */
+lbm_status lbm_get_dt(const lbm_solver *h, double *dt);
+
+/* Destroy the handle. Never frees the workspace or the stream. */
+void lbm_destroy(lbm_solver *h);
+
+/* Message of the last failing call on h (or of the last failing
+ * lbm_create if h is NULL). Valid until the next call on h. */
+const char *lbm_last_error(const lbm_solver *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_SOLID_H */

@@ -1,0 +1,261 @@
+// aux_kernels.hpp -- start-up, read-out and diagnostics kernels.
+//
+// These run once per set_fields / read call, not per step; they favour
+// plain per-site code over tiling.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+struct FieldParams {
+    int nx, ny;
+    long long plane;
+    int bc_lo, bc_hi;
+    double uw_lo[2], uw_hi[2];  // wall displacement of momentum walls (lattice units)
+    double lam, mu;             // lattice units
+};
+
+// Displacement at (x, y) in lattice units, with the ghost-row rules of the
+// y walls for y = -1 and y = ny (x periodic, y periodic if bc_lo is).
+template <class TU>
+__device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, int y)
+{
+    const size_t pl = (size_t)p.plane;
+    x = (x % p.nx + p.nx) % p.nx;
+    if (p.bc_lo == BC_PERIODIC) {
+        y = (y % p.ny + p.ny) % p.ny;
+        return (double)u[a * pl + (size_t)y * p.nx + x];
+    }
+    if (y >= 0 && y < p.ny) return (double)u[a * pl + (size_t)y * p.nx + x];
+    if (y < 0) {
+        const double u0 = (double)u[a * pl + x], u1 = (double)u[a * pl + (size_t)p.nx + x];
+        if (p.bc_lo == BC_NEUMANN) return u0;
+        return 8.0 / 3.0 * p.uw_lo[a] - 2.0 * u0 + u1 / 3.0;
+    }
+    const double v0 = (double)u[a * pl + (size_t)(p.ny - 1) * p.nx + x];
+    const double v1 = (double)u[a * pl + (size_t)(p.ny - 2) * p.nx + x];
+    if (p.bc_hi == BC_NEUMANN) return v0;
+    return 8.0 / 3.0 * p.uw_hi[a] - 2.0 * v0 + v1 / 3.0;
+}
+
+template <class TU>
+__device__ inline void grad_at(const TU *u, const FieldParams &p, int x, int y, double H[4])
+{
+    for (int a = 0; a < 2; ++a) {
+        H[2 * a + 0] = 0.5 * (u_at(u, p, a, x + 1, y) - u_at(u, p, a, x - 1, y));
+        H[2 * a + 1] = 0.5 * (u_at(u, p, a, x, y + 1) - u_at(u, p, a, x, y - 1));
+    }
+}
+
+// ---------------------------------------------------------------- start-up
+
+struct InitParams {
+    FieldParams fp;
+    const double *u0;   // staged host input, physical units, [2][ny][nx]
+    const double *v0;
+    void *f, *u, *j;    // state (storage types of the precision)
+    double inv_dx;      // u_L = u / dX
+    double v_to_j;      // j_L = v dt / dX
+    double f_scale;
+    double *maxf;       // per-block max |f| (mode 0)
+    int mode;           // 0: reduce max |f| only, 1: write the state
+};
+
+// f = f^eq(r0, j0, Pbar(H(u0))) with r0 = -div u0, j0 = rho0 v0
+// (Algorithm 1, initialisation; eqs. (15), (18), (20)), lattice units.
+template <class PR>
+__global__ void __launch_bounds__(256) init_kernel(const InitParams p)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    __shared__ double red[256];
+    const FieldParams &fp = p.fp;
+    const size_t pl = (size_t)fp.plane;
+    const long long n = (long long)fp.nx * fp.ny;
+    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+    double m = 0.0;
+    if (s < n) {
+        const int y = (int)(s / fp.nx), x = (int)(s - (long long)y * fp.nx);
+        // u0 in lattice units; the staged array has the same layout as u
+        double H[4];
+        for (int a = 0; a < 2; ++a) {
+            auto U = [&](int xx, int yy) {
+                // reuse the ghost rules on the staged double array (walls at rest at t = 0)
+                FieldParams q = fp;
+                q.uw_lo[0] = q.uw_lo[1] = q.uw_hi[0] = q.uw_hi[1] = 0.0;
+                return u_at(p.u0, q, a, xx, yy) * p.inv_dx;
+            };
+            H[2 * a + 0] = 0.5 * (U(x + 1, y) - U(x - 1, y));
+            H[2 * a + 1] = 0.5 * (U(x, y + 1) - U(x, y - 1));
+        }
+        const double mu = fp.mu;
+        const double tr = H[0] + H[3];
+        const double r = -tr;
+        const double Pxx = -mu * (2.0 * H[0] + tr), Pyy = -mu * (2.0 * H[3] + tr);
+        const double Pxy = -mu * (H[1] + H[2]);
+        const double jx = p.v0[s] * p.v_to_j, jy = p.v0[pl + s] * p.v_to_j;
+        const double axx = Pxx - r / 3.0, ayy = Pyy - r / 3.0, trA = axx + ayy;
+        const double q[9] = {-trA / 3.0,
+                             axx - trA / 3.0,
+                             ayy - trA / 3.0,
+                             axx - trA / 3.0,
+                             ayy - trA / 3.0,
+                             2.0 * (trA / 3.0 + Pxy),
+                             2.0 * (trA / 3.0 - Pxy),
+                             2.0 * (trA / 3.0 + Pxy),
+                             2.0 * (trA / 3.0 - Pxy)};
+        const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        for (int i = 0; i < 9; ++i) {
+            const double fi = w[i] * (r + 3.0 * (ex[i] * jx + ey[i] * jy) + 4.5 * q[i]);
+            m = fmax(m, fabs(fi));
+            if (p.mode == 1) FStore<TF>::store(static_cast<TF *>(p.f), i * pl + s, (typename PR::TC)fi,
+                                               (typename PR::TC)p.f_scale);
+        }
+        if (p.mode == 1) {
+            TU *u = static_cast<TU *>(p.u);
+            TJ *j = static_cast<TJ *>(p.j);
+            u[s] = TU(p.u0[s] * p.inv_dx);
+            u[pl + s] = TU(p.u0[pl + s] * p.inv_dx);
+            j[s] = TJ(jx);
+            j[pl + s] = TJ(jy);
+        }
+    }
+    if (p.mode == 0) {
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) p.maxf[blockIdx.x] = red[0];
+    }
+}
+
+// ---------------------------------------------------------------- read-out
+
+struct ReadParams {
+    FieldParams fp;
+    const void *u, *j;
+    double *out;        // staging: [8][rows][nx] = u (2), v (2), P (4)
+    int y_begin, rows;
+    double dx;          // u = dX u_L
+    double c;           // v = c j_L
+    double stress;      // P = rho0 c^2 P_L
+};
+
+template <class PR>
+__global__ void __launch_bounds__(256) readout_kernel(const ReadParams p)
+{
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    const FieldParams &fp = p.fp;
+    const size_t pl = (size_t)fp.plane;
+    const long long n = (long long)fp.nx * p.rows;
+    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int yl = (int)(s / fp.nx), x = (int)(s - (long long)yl * fp.nx);
+    const int y = p.y_begin + yl;
+    const TU *u = static_cast<const TU *>(p.u);
+    const TJ *j = static_cast<const TJ *>(p.j);
+    const size_t g = (size_t)y * fp.nx + x;
+    double H[4], P[4];
+    grad_at(u, fp, x, y, H);
+    piola<double>(H, fp.lam, fp.mu, P);
+    const size_t cp = (size_t)p.rows * fp.nx;
+    p.out[0 * cp + s] = (double)u[g] * p.dx;
+    p.out[1 * cp + s] = (double)u[pl + g] * p.dx;
+    p.out[2 * cp + s] = (double)j[g] * p.c;
+    p.out[3 * cp + s] = (double)j[pl + g] * p.c;
+    for (int c = 0; c < 4; ++c) p.out[(4 + c) * cp + s] = P[c] * p.stress;
+}
+
+// ---------------------------------------------------------------- diagnostics
+
+struct DiagParams {
+    FieldParams fp;
+    const void *f, *u, *j;
+    double f_inv_scale;
+    double rho0, dx, c, lam_phys, mu_phys;
+    double *partials;   // [gridDim.x][8]
+};
+
+// Per-block partial sums in FP64 with a fixed tree; blocks cover fixed site
+// ranges, so the result does not depend on scheduling.
+template <class PR>
+__global__ void __launch_bounds__(256) diag_kernel(const DiagParams p)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    __shared__ double red[7][256];
+    const FieldParams &fp = p.fp;
+    const size_t pl = (size_t)fp.plane;
+    const long long n = (long long)fp.nx * fp.ny;
+    double acc[7] = {0, 0, 0, 0, 1e300, 0, 0};  // jx, jy, r, energy, minJ, maxE, bad
+    const TF *f = static_cast<const TF *>(p.f);
+    const TU *u = static_cast<const TU *>(p.u);
+    const TJ *j = static_cast<const TJ *>(p.j);
+    for (long long s = (long long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long long)gridDim.x * 256) {
+        const int y = (int)(s / fp.nx), x = (int)(s - (long long)y * fp.nx);
+        double H[4];
+        grad_at(u, fp, x, y, H);
+        double r = 0.0;
+        for (int i = 0; i < 9; ++i) r += (double)FStore<TF>::load(f, i * pl + s, (typename PR::TC)p.f_inv_scale);
+        const double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
+        const double J = F11 * F22 - F12 * F21;
+        const double E11 = 0.5 * (F11 * F11 + F21 * F21 - 1.0);
+        const double E12 = 0.5 * (F11 * F12 + F21 * F22);
+        const double E22 = 0.5 * (F12 * F12 + F22 * F22 - 1.0);
+        const double mean = 0.5 * (E11 + E22);
+        const double dev = sqrt(0.25 * (E11 - E22) * (E11 - E22) + E12 * E12);
+        const double En = fmax(fabs(mean + dev), fabs(mean - dev));
+        const double jx = (double)j[s] * p.rho0 * p.c, jy = (double)j[pl + s] * p.rho0 * p.c;
+        const double ux = (double)u[s], uy = (double)u[pl + s];
+        acc[0] += jx;
+        acc[1] += jy;
+        acc[2] += r * p.rho0;
+        const bool ok = (J > 0.0) && isfinite(jx) && isfinite(jy) && isfinite(ux) && isfinite(uy);
+        if (ok) {
+            const double IC = F11 * F11 + F12 * F12 + F21 * F21 + F22 * F22;
+            const double W = 0.5 * p.mu_phys * (IC - 2.0) + 0.25 * p.lam_phys * (J * J - 1.0) -
+                             0.5 * p.lam_phys * log(J) - p.mu_phys * log(J);
+            acc[3] += ((jx * jx + jy * jy) / (2.0 * p.rho0) + W) * p.dx * p.dx;
+        } else {
+            acc[6] = 1.0;
+        }
+        acc[4] = fmin(acc[4], J);
+        acc[5] = fmax(acc[5], En);
+    }
+    for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+            red[4][threadIdx.x] = fmin(red[4][threadIdx.x], red[4][threadIdx.x + w]);
+            red[5][threadIdx.x] = fmax(red[5][threadIdx.x], red[5][threadIdx.x + w]);
+            red[6][threadIdx.x] = fmax(red[6][threadIdx.x], red[6][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) p.partials[blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Second stage: one block folds the per-block partials in index order.
+__global__ void __launch_bounds__(64) diag_final_kernel(const double *partials, int nblocks, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double acc[7] = {0, 0, 0, 0, 1e300, 0, 0};
+    for (int b = 0; b < nblocks; ++b) {
+        for (int k = 0; k < 4; ++k) acc[k] += partials[b * 8 + k];
+        acc[4] = fmin(acc[4], partials[b * 8 + 4]);
+        acc[5] = fmax(acc[5], partials[b * 8 + 5]);
+        acc[6] = fmax(acc[6], partials[b * 8 + 6]);
+    }
+    for (int k = 0; k < 7; ++k) out[k] = acc[k];
+}
+
+}  // namespace lbm
