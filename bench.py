@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the per-time-step lattice update on one MI355X.
+
+Default workload (the large-strain periodic plate): a 4096 x 4096 D2Q9 grid,
+dX = rho0 = 1, neo-Hooke lam = 0.1, mu = 0.05, tau/dt = 0.8, predictor-
+corrector source, FP32 storage and arithmetic; u0 = 0 and a seeded
+Gaussian-filtered velocity field (sigma = 32 cells, seed 2) scaled to the
+calibrated peak velocity (tests/golden/config2_amplitude.json). A "step" is
+one time step of the whole grid (one launch of the fused step kernel).
+
+Prints one JSON line with MLUPS, the HBM roofline fraction of the step kernel
+(algorithmic bytes per lattice update: the 13-value state read once and
+written once), the FP64 oracle timed on the host cores on a bounded sample,
+and the rel-L2 error of the GPU against that oracle sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (fp64/fp32/fp16-storage) at stated error vs FP64 oracle; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per lattice update: f (9), u (2), j (2) read and written
+BYTES_PER_UPDATE = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
+                    "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ["step_kernel.hpp", "lattice.hpp"]:
+        with open(os.path.join(ROOT, "paper_2208_13769_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def config2_amplitude() -> float:
+    path = os.path.join(ROOT, "tests", "golden", "config2_amplitude.json")
+    with open(path) as fh:
+        return float(json.load(fh)["peak_velocity"])
+
+
+def workload(name: str):
+    from paper_2208_13769_amd import inputs
+
+    if name == "config2":
+        n = 4096
+        u0, v0 = inputs.filtered_random_velocity(n, n, 32.0, 2, config2_amplitude())
+        return dict(nx=n, ny=n, precision="fp32", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
+                    desc="periodic 4096x4096 D2Q9, neo-Hooke lam=0.1 mu=0.05, tau/dt=0.8, "
+                         "predictor-corrector, FP32; v0 Gaussian-filtered (sigma 32 cells, seed 2), "
+                         "peak strain ~0.2 within 200 steps")
+    if name == "fp16-4096":
+        n = 4096
+        u0, v0 = inputs.shear_wave(n, n, 1e-4, n)
+        return dict(nx=n, ny=n, precision="fp16", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
+                    desc="periodic 4096x4096, FP16 populations / FP64 u / FP32 j, shear wave")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_for(precision: str, sites: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"step_{precision}_4096_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_source_hash() or rec.get("sites") != sites:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, steps: int):
+    """FP64 oracle on the same input: `steps` time steps of the full grid."""
+    from oracle import oracle as O
+
+    p = O.Params(nx=wl["nx"], ny=wl["ny"], lam=wl["lam"], mu=wl["mu"], tau_over_dt=wl["tau"])
+    s = O.Solver(p, wl["u0"], wl["v0"])
+    t0 = time.perf_counter()
+    s.step(steps)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    mlups = wl["nx"] * wl["ny"] * steps / el / 1e6
+    u, v, P = s.fields()
+    return dict(value=mlups, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{steps} time steps of the full {wl['nx']}x{wl['ny']} grid from the same seeded input, "
+                       f"FP64, {el:.1f} s"), (u, v, P)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiling", default="auto", help="auto | default | BLOCK,NSEGS")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, run a plain elementwise copy of this many MiB (float32 read + "
+                         "write) three times: its HBM counter readings calibrate the step kernel's")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the single-plate path has no multi-GPU decomposition).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.autotune import best_tiling
+
+    wl = workload(args.workload)
+    nx, ny, prec = wl["nx"], wl["ny"], wl["precision"]
+    s = lbm.Solver(nx, ny, 1.0, prec, "pc")
+    s.set_material(1.0, wl["lam"], wl["mu"], wl["tau"])
+    s.set_fields(wl["u0"], wl["v0"])
+    tiling_source = "default"
+    if args.tiling == "auto":
+        block, segs = best_tiling(s, nx, ny, prec, "pc")
+        s.set_tiling(block, segs)
+        s.set_fields(wl["u0"], wl["v0"])
+        tiling_source = "autotuned"
+    elif args.tiling != "default":
+        block, segs = map(int, args.tiling.split(","))
+        s.set_tiling(block, segs)
+        tiling_source = "given"
+    block, segs = s.tiling()
+
+    stream = s.stream
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=s.device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    _, _, _, diag, status = s.read(want_fields=False)
+
+    sites = nx * ny
+    ms_step = ms / args.steps
+    mlups = sites * args.steps / (ms / 1e3) / 1e6
+    bytes_launch = BYTES_PER_UPDATE[prec] * sites
+    achieved = bytes_launch / (ms_step / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites),
+                "bytes_per_update": BYTES_PER_UPDATE[prec]}
+
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": wl["desc"], "grid": [nx, ny], "sites": sites, "precision": prec, "scheme": "pc",
+                   "tiling": {"block": block, "n_segs": segs, "source": tiling_source},
+                   "wall_s": round(wall, 4)},
+        "roofline": roofline,
+        "run": {"status": int(status), "max_strain": diag.max_strain, "min_J": diag.min_J},
+    }
+
+    if not args.no_cpu_baseline:
+        base, (uo, vo, Po) = cpu_baseline(wl, args.cpu_steps)
+        out["cpu_baseline"] = base
+        # the GPU on the same sample, for the error statement
+        g = lbm.Solver(nx, ny, 1.0, prec, "pc")
+        g.set_material(1.0, wl["lam"], wl["mu"], wl["tau"])
+        g.set_fields(wl["u0"], wl["v0"])
+        g.step(args.cpu_steps)
+        ug, vg, Pg, _, _ = g.read()
+        g.close()
+        out["error_vs_oracle"] = {
+            "steps": args.cpu_steps,
+            "rel_l2_u": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
+            "rel_l2_P": float(np.linalg.norm(Pg - Po) / np.linalg.norm(Po)),
+        }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

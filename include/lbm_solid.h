@@ -125,8 +125,8 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
  * LBM_ERR_UNSTABLE (after filling the outputs) if the unstable flag is set. */
 lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_diagnostics *d);
 
-/* Launch shape of the step kernel: threads per block (64, 128 or 256; one
- * lattice column per thread) and row segments per column strip
+/* Launch shape of the step kernel: threads per block (64, 128, 256 or 512;
+ * one lattice column per thread) and row segments per column strip
  * (1 <= n_segs <= ny). Results do not depend on it (bitwise); it only
  * changes speed. lbm_create picks a default; the autotuner overrides it. */
 lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs);

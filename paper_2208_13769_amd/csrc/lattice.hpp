@@ -41,11 +41,13 @@ struct FStore;
 template <>
 struct FStore<double> {
     __device__ static double load(const double *p, size_t i, double) { return p[i]; }
+    __device__ static double cvt(double v, double) { return v; }
     __device__ static void store(double *p, size_t i, double v, double) { p[i] = v; }
 };
 template <>
 struct FStore<float> {
     __device__ static float load(const float *p, size_t i, float) { return p[i]; }
+    __device__ static float cvt(float v, float) { return v; }
     __device__ static void store(float *p, size_t i, float v, float) { p[i] = v; }
 };
 template <>
@@ -54,6 +56,7 @@ struct FStore<__half> {
     {
         return __half2float(p[i]) * inv_scale;
     }
+    __device__ static float cvt(__half v, float inv_scale) { return __half2float(v) * inv_scale; }
     __device__ static void store(__half *p, size_t i, float v, float scale)
     {
         p[i] = __float2half_rn(v * scale);
@@ -65,6 +68,7 @@ struct FStore<__hip_bfloat16> {
     {
         return __bfloat162float(p[i]) * inv_scale;
     }
+    __device__ static float cvt(__hip_bfloat16 v, float inv_scale) { return __bfloat162float(v) * inv_scale; }
     __device__ static void store(__hip_bfloat16 *p, size_t i, float v, float scale)
     {
         p[i] = __float2bfloat16(v * scale);
@@ -72,6 +76,11 @@ struct FStore<__hip_bfloat16> {
 };
 
 // ---------------------------------------------------------------- material
+
+// Reciprocal: the hardware approximation (about 1 ulp) in float, exact
+// division in double.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Stress sum K = P(H) + Pbar(H) in lattice units for the plane-strain
 // neo-Hooke law (eq. (27)) and the Poisson stress (eq. (15)).
@@ -90,7 +99,7 @@ __device__ __forceinline__ TC stress_sum(const TC H[4], TC lam, TC mu, TC K[4])
     TC tr = H[0] + H[3];
     TC Jm1 = tr + (H[0] * H[3] - H[1] * H[2]);
     TC J = TC(1) + Jm1;
-    TC d = Jm1 * (TC(0.5) * lam * (J + TC(1)) + mu) / J;
+    TC d = Jm1 * (TC(0.5) * lam * (J + TC(1)) + mu) * recip(J);
     TC m2tr = TC(2) * mu * tr;
     K[0] = d * (TC(1) + H[3]) - m2tr;
     K[1] = -d * H[2];

@@ -96,7 +96,7 @@ struct lbm_solver {
     double bcval[4][2] = {};
     double f_scale = 1.0;
     int64_t steps = 0;
-    int block = 256, strip_w = 0, n_strips = 0, n_segs = 0;
+    int block = 256, strip_w = 0, n_strips = 0, n_segs = 0, halo_a = 0;
     std::string err;
 
     void *fptr(int c) const { return ws + L.f[c]; }
@@ -157,13 +157,21 @@ FieldParams field_params(const lbm_solver *h, double t_steps)
 
 template <class PR>
 struct Kernels {
+    template <int B, bool PC>
+    static void step_w(const StepParams &sp, int nblocks, hipStream_t st)
+    {
+        if (sp.bc_lo != BC_PERIODIC)
+            hipLaunchKernelGGL((step_kernel<PR, B, PC, true>), dim3(nblocks), dim3(B), 0, st, sp);
+        else
+            hipLaunchKernelGGL((step_kernel<PR, B, PC, false>), dim3(nblocks), dim3(B), 0, st, sp);
+    }
     template <int B>
     static hipError_t step_b(const StepParams &sp, int nblocks, bool pc, hipStream_t st)
     {
         if (pc)
-            hipLaunchKernelGGL((step_kernel<PR, B, true>), dim3(nblocks), dim3(B), 0, st, sp);
+            step_w<B, true>(sp, nblocks, st);
         else
-            hipLaunchKernelGGL((step_kernel<PR, B, false>), dim3(nblocks), dim3(B), 0, st, sp);
+            step_w<B, false>(sp, nblocks, st);
         return hipGetLastError();
     }
     static hipError_t step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st)
@@ -171,6 +179,7 @@ struct Kernels {
         switch (block) {
         case 64: return step_b<64>(sp, nblocks, pc, st);
         case 128: return step_b<128>(sp, nblocks, pc, st);
+        case 512: return step_b<512>(sp, nblocks, pc, st);
         default: return step_b<256>(sp, nblocks, pc, st);
         }
     }
@@ -203,13 +212,29 @@ struct Kernels {
 
 int halo_of(const lbm_solver *h) { return h->scheme == LBM_SCHEME_PC ? 5 : 3; }
 
+// Column strips: when the plate is wider than one block's reach, each
+// strip's output width is a multiple of 128 bytes of the population type
+// (32 floats / doubles, 64 halves), so no cache line is written by two
+// blocks; the spare threads of the block extend the halo.
 void set_shape(lbm_solver *h, int block, int n_segs)
 {
-    const int wmax = block - 2 * halo_of(h);
-    const int n_strips = (h->nx + wmax - 1) / wmax;
+    const int halo = halo_of(h);
+    const int wmax = block - 2 * halo;
+    const int align = (h->prec == LBM_FP16_STORE || h->prec == LBM_BF16_STORE) ? 64 : 32;
+    int strip_w, n_strips, halo_a;
+    if (h->nx <= wmax) {
+        strip_w = h->nx;
+        n_strips = 1;
+        halo_a = halo;
+    } else {
+        strip_w = wmax >= align ? wmax / align * align : wmax;
+        n_strips = (h->nx + strip_w - 1) / strip_w;
+        halo_a = (block - strip_w) / 2;
+    }
     h->block = block;
     h->n_strips = n_strips;
-    h->strip_w = (h->nx + n_strips - 1) / n_strips;
+    h->strip_w = strip_w;
+    h->halo_a = halo_a;
     h->n_segs = n_segs;
 }
 
@@ -323,10 +348,10 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
 lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs)
 {
     if (!h) return LBM_ERR_ARG;
-    if (block != 64 && block != 128 && block != 256) return fail(h, LBM_ERR_ARG, "block must be 64, 128 or 256");
+    if (block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(h, LBM_ERR_ARG, "block must be 64, 128, 256 or 512");
     if (n_segs < 1 || n_segs > h->ny) return fail(h, LBM_ERR_ARG, "n_segs must be in [1, ny]");
-    const long long nblocks = (long long)((h->nx + block - 2 * halo_of(h) - 1) / (block - 2 * halo_of(h))) * n_segs;
-    if (nblocks > (1LL << 30)) return fail(h, LBM_ERR_ARG, "too many blocks");
+    if ((long long)h->nx * n_segs > (1LL << 30)) return fail(h, LBM_ERR_ARG, "too many blocks");
     set_shape(h, block, n_segs);
     return LBM_OK;
 }
@@ -423,6 +448,7 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
     sp.f_scale = h->f_scale;
     sp.f_inv_scale = 1.0 / h->f_scale;
     sp.strip_w = h->strip_w;
+    sp.halo_a = h->halo_a;
     sp.n_strips = h->n_strips;
     sp.n_segs = h->n_segs;
     sp.flag = h->flag();

@@ -26,6 +26,9 @@
 // its neighbours wrote in the previous iteration, so the halo in x is 5
 // columns (PC) or 3 (explicit) and the segment is extended by the same
 // pipeline depth in y; halo work is recomputed, never exchanged.
+// Within an iteration the global loads for stages A and C are issued first
+// and stages D, E, F (which only need earlier rows) run before A, B, C, so
+// the loads are in flight while D-F compute.
 //
 // Walls (y edges only) lie half a spacing outside the node rows 0 and ny-1.
 // Ghost displacement rows for the finite differences: momentum wall -- the
@@ -55,6 +58,7 @@ struct StepParams {
     double val_lo[2], val_hi[2];  // j* or T* in lattice units
     double f_scale, f_inv_scale;  // 16-bit population scaling (1 otherwise)
     int strip_w, n_strips, n_segs;
+    int halo_a;             // threads left of the first output column (>= the stencil halo)
     unsigned int *flag;     // set to 1 on J <= 0 or a non-finite value
     long long step;         // index n of the input state
 };
@@ -133,7 +137,7 @@ __device__ __forceinline__ void wall_populations(bool top, int kind, const TC fc
     }
 }
 
-template <class PR, int BLOCK, bool PC>
+template <class PR, int BLOCK, bool PC, bool WALLED>
 __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
 {
     using TF = typename PR::TF;
@@ -142,15 +146,15 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     using TC = typename PR::TC;
     using FS = FStore<TF>;
     constexpr int HX = PC ? 5 : 3;
-    constexpr int NU = PC ? 7 : 5;   // rows of u_n kept: R .. R-NU+1
-    constexpr int NJ = PC ? 5 : 3;   // rows of j_n kept: R-2 .. R-NJ-1
+    constexpr int NU = PC ? 6 : 4;   // rows of u_n kept: R .. R-NU+1
+    constexpr int NJ = PC ? 4 : 2;   // rows of j_n kept: R-2 .. R-NJ-1
 
     __shared__ TU s_u[2][2][BLOCK];
     __shared__ TC s_k[2][2][BLOCK];
     __shared__ TC s_f[2][6][BLOCK];
     __shared__ TU s_up[PC ? 2 : 1][2][BLOCK];
     __shared__ TC s_kp[PC ? 2 : 1][2][BLOCK];
-    __shared__ TC s_wall[2][3][BLOCK];
+    __shared__ TC s_wall[WALLED ? 2 : 1][3][BLOCK];
 
     const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
     TF *__restrict__ fout = static_cast<TF *>(p.f_out);
@@ -175,15 +179,18 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int logical = xcd * xq + min(xcd, xr) + loc;
     const int strip = logical / p.n_segs;
     const int seg = logical - strip * p.n_segs;
+    // Output strips start on multiples of strip_w, which the host keeps a
+    // multiple of the 128-byte line, so row writes cover whole lines; the
+    // threads outside [halo_a, halo_a + strip_w) only feed the halo.
     const int x0 = strip * p.strip_w;
-    const int xc = x0 - HX + t;
+    const int xc = x0 - p.halo_a + t;
     int gx = xc % nx;
     if (gx < 0) gx += nx;
-    const bool out_col = (t >= HX) && (t < HX + p.strip_w) && (xc < nx);
+    const bool out_col = (t >= p.halo_a) && (t < p.halo_a + p.strip_w) && (xc < nx);
     const int y0 = (int)((long long)seg * ny / p.n_segs);
     const int y1 = (int)((long long)(seg + 1) * ny / p.n_segs);
 
-    const bool walled = p.bc_lo != BC_PERIODIC;
+    constexpr bool walled = WALLED;
     const int bc_lo = p.bc_lo, bc_hi = p.bc_hi;
     const TC omega = TC(p.omega), lam = TC(p.lam), mu = TC(p.mu);
     const TC bx = TC(p.bx), by = TC(p.by);
@@ -196,6 +203,15 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const TU uw_hi_p[2] = {TU(p.val_hi[0] * (tn + 1)), TU(p.val_hi[1] * (tn + 1))};
 
     auto is_node = [&](int r) { return !walled || (r >= 0 && r < ny); };
+    // row for a load: wrapped (periodic) or clamped into the plate (walls)
+    auto rowc = [&](int r) {
+        if (!walled) {
+            r %= ny;
+            if (r < 0) r += ny;
+            return r;
+        }
+        return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+    };
     auto rowi = [&](int r) {
         if (!walled) {
             r %= ny;
@@ -237,7 +253,7 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     // register rings: index k holds row (current stage row) - k
     TU uR[NU][2];
     TC kA2[3][2];
-    TC sN[3][2];
+    TC sN[2][2];
     TC jN[NJ][2];
     TC hxCur[2] = {0, 0}, hxPrev[2] = {0, 0};
     TC o0[2] = {0, 0}, o2[3] = {0, 0, 0}, o4 = 0;
@@ -250,131 +266,40 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     for (int k = 0; k < NU; ++k) uR[k][0] = uR[k][1] = TU(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        kA2[k][0] = kA2[k][1] = sN[k][0] = sN[k][1] = TC(0);
+        kA2[k][0] = kA2[k][1] = TC(0);
         jfR[k][0] = jfR[k][1] = kpA2[k][0] = kpA2[k][1] = TC(0);
         upR[k][0] = upR[k][1] = TU(0);
     }
 #pragma unroll
     for (int k = 0; k < NJ; ++k) jN[k][0] = jN[k][1] = TC(0);
+    sN[0][0] = sN[0][1] = sN[1][0] = sN[1][1] = TC(0);
 
     bool bad = false;
     const int n_iter = (y1 - y0) + (PC ? 11 : 7);
     const int Rstart = y0 - HX;
 
+#pragma unroll 2
     for (int it = 0; it < n_iter; ++it) {
         const int R = Rstart + it;
         const int b = it & 1, pb = b ^ 1;
 
-        // ---------------- stage A: u_n at row R
+        // Loads of this iteration (u_n at row R for stage A, f_n and j_n at
+        // row R-2 for stage C) are issued first; stages D-F, which only use
+        // earlier rows, run while they are in flight. Rows beyond a wall are
+        // clamped to a valid address and their values discarded.
+        const int rA = R, rC = R - 2;
+        const bool nodeA = is_node(rA), nodeC = is_node(rC);
+        const size_t oA = (size_t)rowc(rA) * nx + gx;
+        const size_t oC = (size_t)rowc(rC) * nx + gx;
+        const TU la0 = uin[oA], la1 = uin[plane + oA];
+        TF lf[9];
 #pragma unroll
-        for (int k = NU - 1; k > 0; --k) {
-            uR[k][0] = uR[k - 1][0];
-            uR[k][1] = uR[k - 1][1];
-        }
-        if (is_node(R)) {
-            const size_t o = (size_t)rowi(R) * nx + gx;
-            uR[0][0] = uin[o];
-            uR[0][1] = uin[plane + o];
-        } else if (R == ny && bc_hi != BC_PERIODIC) {
-            uR[0][0] = ghost_hi(0, uR[1][0], uR[2][0], uw_hi_n[0]);
-            uR[0][1] = ghost_hi(0, uR[1][1], uR[2][1], uw_hi_n[1]);
-        } else if (R == ny + 1 && bc_hi != BC_PERIODIC) {
-            uR[0][0] = ghost_hi(1, uR[2][0], uR[3][0], uw_hi_n[0]);
-            uR[0][1] = ghost_hi(1, uR[2][1], uR[3][1], uw_hi_n[1]);
-        } else {
-            uR[0][0] = uR[0][1] = TU(0);
-        }
-        s_u[b][0][t] = uR[0][0];
-        s_u[b][1][t] = uR[0][1];
-
-        // ---------------- stage B: K at row R-1
-        {
-            TC H[4], K[4];
-            H[0] = TC((s_u[pb][0][tr] - s_u[pb][0][tl]) * TU(0.5));
-            H[2] = TC((s_u[pb][1][tr] - s_u[pb][1][tl]) * TU(0.5));
-            const int rB = R - 1;
-            TU um0 = uR[2][0], um1 = uR[2][1];
-            if (walled && rB == 0) {
-                um0 = ghost_lo(uR[1][0], uR[0][0], uw_lo_n[0]);
-                um1 = ghost_lo(uR[1][1], uR[0][1], uw_lo_n[1]);
-            }
-            H[1] = TC((uR[0][0] - um0) * TU(0.5));
-            H[3] = TC((uR[0][1] - um1) * TU(0.5));
-            const TC J = stress_sum(H, lam, mu, K);
-            if (out_col && rB >= y0 && rB < y1 && !(J > TC(0))) bad = true;
-            s_k[b][0][t] = K[0];
-            s_k[b][1][t] = K[2];
-#pragma unroll
-            for (int k = 2; k > 0; --k) {
-                kA2[k][0] = kA2[k - 1][0];
-                kA2[k][1] = kA2[k - 1][1];
-            }
-            kA2[0][0] = K[1];
-            kA2[0][1] = K[3];
-            hxPrev[0] = hxCur[0];
-            hxPrev[1] = hxCur[1];
-            hxCur[0] = H[0];
-            hxCur[1] = H[2];
-        }
-
-        // ---------------- stage C: S_n at row R-2, collision
-        const int rC = R - 2;
-        TC fc[9];
-        {
-            TC k12d = kA2[2][0], k22d = kA2[2][1];
-            if (walled && rC == 0) ghost_lo_K(uR[2], uR[1], hxPrev, hxCur, uw_lo_n, k12d, k22d);
-            const TC Sx = bx + TC(0.5) * (s_k[pb][0][tr] - s_k[pb][0][tl]) + TC(0.5) * (kA2[0][0] - k12d);
-            const TC Sy = by + TC(0.5) * (s_k[pb][1][tr] - s_k[pb][1][tl]) + TC(0.5) * (kA2[0][1] - k22d);
-#pragma unroll
-            for (int k = 2; k > 0; --k) {
-                sN[k][0] = sN[k - 1][0];
-                sN[k][1] = sN[k - 1][1];
-            }
-            sN[0][0] = Sx;
-            sN[0][1] = Sy;
-#pragma unroll
-            for (int k = NJ - 1; k > 0; --k) {
-                jN[k][0] = jN[k - 1][0];
-                jN[k][1] = jN[k - 1][1];
-            }
-            if (is_node(rC)) {
-                const size_t o = (size_t)rowi(rC) * nx + gx;
-                TC f[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * plane + o, f_inv);
-                const TC jx = TC(jin[o]), jy = TC(jin[plane + o]);
-                jN[0][0] = jx;
-                jN[0][1] = jy;
-                TC r, pxx;
-                collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
-                if (walled && rC == 0) {
-                    TC w[3];
-                    wall_populations(false, bc_lo, fc, p.val_lo, r, pxx, kA2[1][0], kA2[1][1], w);
-                    s_wall[0][0][t] = w[0];
-                    s_wall[0][1][t] = w[1];
-                    s_wall[0][2][t] = w[2];
-                }
-                if (walled && rC == ny - 1) {
-                    TC w[3];
-                    wall_populations(true, bc_hi, fc, p.val_hi, r, pxx, kA2[1][0], kA2[1][1], w);
-                    s_wall[1][0][t] = w[0];
-                    s_wall[1][1][t] = w[1];
-                    s_wall[1][2][t] = w[2];
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) fc[i] = TC(0);
-                jN[0][0] = jN[0][1] = TC(0);
-            }
-            s_f[b][0][t] = fc[1];
-            s_f[b][1][t] = fc[3];
-            s_f[b][2][t] = fc[5];
-            s_f[b][3][t] = fc[6];
-            s_f[b][4][t] = fc[7];
-            s_f[b][5][t] = fc[8];
-        }
+        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
+        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
 
         // ---------------- stage D: pull row R-4, moments
+        // (rings not yet advanced this iteration: uR[k] = row R-1-k,
+        //  sN[k] = row R-3-k, jN[k] = row R-3-k)
         const int rD = R - 4;
         {
             const TC a1 = s_f[pb][0][tl], a3 = s_f[pb][1][tr], a5 = s_f[pb][2][tl];
@@ -399,19 +324,12 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
                 fn[7] = s_wall[1][1][t];
                 fn[8] = s_wall[1][2][t];
             }
-            // advance the pull rings
             n5[1] = n5[0];
             n5[0] = a5;
             n6[1] = n6[0];
             n6[0] = a6;
             n1 = a1;
             n3 = a3;
-            o2[2] = o2[1];
-            o2[1] = o2[0];
-            o2[0] = fc[2];
-            o0[1] = o0[0];
-            o0[0] = fc[0];
-            o4 = fc[4];
 
             const bool nodeD = is_node(rD);
             const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
@@ -422,12 +340,12 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
                 for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn[i], f_scale);
             }
             if constexpr (PC) {
-                const TC jpx = jfx + TC(0.5) * sN[2][0];
-                const TC jpy = jfy + TC(0.5) * sN[2][1];
+                const TC jpx = jfx + TC(0.5) * sN[1][0];
+                const TC jpy = jfy + TC(0.5) * sN[1][1];
                 TU upx, upy;
                 if (nodeD) {
-                    upx = uR[4][0] + TU(TC(0.5) * (jpx + jN[2][0]));
-                    upy = uR[4][1] + TU(TC(0.5) * (jpy + jN[2][1]));
+                    upx = uR[3][0] + TU(TC(0.5) * (jpx + jN[1][0]));
+                    upy = uR[3][1] + TU(TC(0.5) * (jpy + jN[1][1]));
                 } else if (rD == ny && bc_hi != BC_PERIODIC) {
                     upx = ghost_hi(0, upR[0][0], upR[1][0], uw_hi_p[0]);
                     upy = ghost_hi(0, upR[0][1], upR[1][1], uw_hi_p[1]);
@@ -453,10 +371,10 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
             } else {
                 // explicit: the source at t also serves the moment step
                 if (nodeD && out_col && rD >= y0 && rD < y1) {
-                    const TC jx = jfx + TC(0.5) * sN[2][0];
-                    const TC jy = jfy + TC(0.5) * sN[2][1];
-                    const TU ux = uR[4][0] + TU(TC(0.5) * (jx + jN[2][0]));
-                    const TU uy = uR[4][1] + TU(TC(0.5) * (jy + jN[2][1]));
+                    const TC jx = jfx + TC(0.5) * sN[1][0];
+                    const TC jy = jfy + TC(0.5) * sN[1][1];
+                    const TU ux = uR[3][0] + TU(TC(0.5) * (jx + jN[1][0]));
+                    const TU uy = uR[3][1] + TU(TC(0.5) * (jy + jN[1][1]));
                     const size_t o = (size_t)rowi(rD) * nx + gx;
                     uout[o] = ux;
                     uout[plane + o] = uy;
@@ -506,8 +424,8 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
                 const TC Sy = by + TC(0.5) * (s_kp[pb][1][tr] - s_kp[pb][1][tl]) + TC(0.5) * (kpA2[0][1] - k22d);
                 const TC jx = jfR[2][0] + TC(0.5) * Sx;
                 const TC jy = jfR[2][1] + TC(0.5) * Sy;
-                const TU ux = uR[6][0] + TU(TC(0.5) * (jx + jN[4][0]));
-                const TU uy = uR[6][1] + TU(TC(0.5) * (jy + jN[4][1]));
+                const TU ux = uR[5][0] + TU(TC(0.5) * (jx + jN[3][0]));
+                const TU uy = uR[5][1] + TU(TC(0.5) * (jy + jN[3][1]));
                 const size_t o = (size_t)rowi(rF) * nx + gx;
                 uout[o] = ux;
                 uout[plane + o] = uy;
@@ -516,6 +434,116 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
                 if (!isfinite((double)ux) || !isfinite((double)uy) || !isfinite((double)jx) || !isfinite((double)jy))
                     bad = true;
             }
+        }
+
+        // ---------------- stage A: u_n at row R
+#pragma unroll
+        for (int k = NU - 1; k > 0; --k) {
+            uR[k][0] = uR[k - 1][0];
+            uR[k][1] = uR[k - 1][1];
+        }
+        if (nodeA) {
+            uR[0][0] = la0;
+            uR[0][1] = la1;
+        } else if (R == ny && bc_hi != BC_PERIODIC) {
+            uR[0][0] = ghost_hi(0, uR[1][0], uR[2][0], uw_hi_n[0]);
+            uR[0][1] = ghost_hi(0, uR[1][1], uR[2][1], uw_hi_n[1]);
+        } else if (R == ny + 1 && bc_hi != BC_PERIODIC) {
+            uR[0][0] = ghost_hi(1, uR[2][0], uR[3][0], uw_hi_n[0]);
+            uR[0][1] = ghost_hi(1, uR[2][1], uR[3][1], uw_hi_n[1]);
+        } else {
+            uR[0][0] = uR[0][1] = TU(0);
+        }
+        s_u[b][0][t] = uR[0][0];
+        s_u[b][1][t] = uR[0][1];
+
+        // ---------------- stage B: K at row R-1
+        {
+            TC H[4], K[4];
+            H[0] = TC((s_u[pb][0][tr] - s_u[pb][0][tl]) * TU(0.5));
+            H[2] = TC((s_u[pb][1][tr] - s_u[pb][1][tl]) * TU(0.5));
+            const int rB = R - 1;
+            TU um0 = uR[2][0], um1 = uR[2][1];
+            if (walled && rB == 0) {
+                um0 = ghost_lo(uR[1][0], uR[0][0], uw_lo_n[0]);
+                um1 = ghost_lo(uR[1][1], uR[0][1], uw_lo_n[1]);
+            }
+            H[1] = TC((uR[0][0] - um0) * TU(0.5));
+            H[3] = TC((uR[0][1] - um1) * TU(0.5));
+            const TC J = stress_sum(H, lam, mu, K);
+            if (out_col && rB >= y0 && rB < y1 && !(J > TC(0))) bad = true;
+            s_k[b][0][t] = K[0];
+            s_k[b][1][t] = K[2];
+#pragma unroll
+            for (int k = 2; k > 0; --k) {
+                kA2[k][0] = kA2[k - 1][0];
+                kA2[k][1] = kA2[k - 1][1];
+            }
+            kA2[0][0] = K[1];
+            kA2[0][1] = K[3];
+            hxPrev[0] = hxCur[0];
+            hxPrev[1] = hxCur[1];
+            hxCur[0] = H[0];
+            hxCur[1] = H[2];
+        }
+
+        // ---------------- stage C: S_n at row R-2, collision
+        {
+            TC fc[9];
+            TC k12d = kA2[2][0], k22d = kA2[2][1];
+            if (walled && rC == 0) ghost_lo_K(uR[2], uR[1], hxPrev, hxCur, uw_lo_n, k12d, k22d);
+            const TC Sx = bx + TC(0.5) * (s_k[pb][0][tr] - s_k[pb][0][tl]) + TC(0.5) * (kA2[0][0] - k12d);
+            const TC Sy = by + TC(0.5) * (s_k[pb][1][tr] - s_k[pb][1][tl]) + TC(0.5) * (kA2[0][1] - k22d);
+            sN[1][0] = sN[0][0];
+            sN[1][1] = sN[0][1];
+            sN[0][0] = Sx;
+            sN[0][1] = Sy;
+#pragma unroll
+            for (int k = NJ - 1; k > 0; --k) {
+                jN[k][0] = jN[k - 1][0];
+                jN[k][1] = jN[k - 1][1];
+            }
+            if (nodeC) {
+                TC f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
+                const TC jx = TC(lj0), jy = TC(lj1);
+                jN[0][0] = jx;
+                jN[0][1] = jy;
+                TC r, pxx;
+                collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
+                if (walled && rC == 0) {
+                    TC w[3];
+                    wall_populations(false, bc_lo, fc, p.val_lo, r, pxx, kA2[1][0], kA2[1][1], w);
+                    s_wall[0][0][t] = w[0];
+                    s_wall[0][1][t] = w[1];
+                    s_wall[0][2][t] = w[2];
+                }
+                if (walled && rC == ny - 1) {
+                    TC w[3];
+                    wall_populations(true, bc_hi, fc, p.val_hi, r, pxx, kA2[1][0], kA2[1][1], w);
+                    s_wall[1][0][t] = w[0];
+                    s_wall[1][1][t] = w[1];
+                    s_wall[1][2][t] = w[2];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fc[i] = TC(0);
+                jN[0][0] = jN[0][1] = TC(0);
+            }
+            s_f[b][0][t] = fc[1];
+            s_f[b][1][t] = fc[3];
+            s_f[b][2][t] = fc[5];
+            s_f[b][3][t] = fc[6];
+            s_f[b][4][t] = fc[7];
+            s_f[b][5][t] = fc[8];
+            // own-column collision rings of the pull
+            o2[2] = o2[1];
+            o2[1] = o2[0];
+            o2[0] = fc[2];
+            o0[1] = o0[0];
+            o0[0] = fc[0];
+            o4 = fc[4];
         }
         __syncthreads();
     }

@@ -112,7 +112,7 @@ def test_tiling_does_not_change_results(gpu, precision):
     nx, ny = 260, 90
     u0, v0, _, _ = random_case(nx, ny, 15, 0.05)
     outs = []
-    for block, segs in [(256, 1), (256, 5), (128, 3), (64, 9), (64, 90)]:
+    for block, segs in [(256, 1), (256, 5), (512, 2), (128, 3), (64, 9), (64, 90)]:
         s = lbm.Solver(nx, ny, 1.0, precision, "pc")
         s.set_material(1.0, 0.1, 0.05, 0.8)
         s.set_tiling(block, segs)
