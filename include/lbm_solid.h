@@ -142,6 +142,75 @@ void lbm_destroy(lbm_solver *h);
  * lbm_create if h is NULL). Valid until the next call on h. */
 const char *lbm_last_error(const lbm_solver *h);
 
+/* ------------------------------------------------------------------------
+ * Batches: many plates of uneven sizes advanced together.
+ *
+ * A batch owns an arena inside the caller's device workspace. Plates are
+ * admitted (lbm_batch_add) while the arena and the tile table have room --
+ * admission by device-memory footprint -- and keep their state resident
+ * until retired. lbm_batch_step advances every admitted plate that has steps
+ * left by up to nsteps, in one persistent launch per time step for all
+ * plates, enqueued as a HIP graph of nsteps launches. All plates of a batch
+ * share the precision, the scheme and the kind of y edges (all periodic, or
+ * all walls with per-plate rules and values); x edges are periodic.
+ * The batch uses 256-thread blocks; plates are cut into column strips and
+ * segments of about 64 rows.
+ * ------------------------------------------------------------------------ */
+
+typedef struct lbm_batch lbm_batch;
+
+/* One plate's geometry, material (Sec. 7) and y-edge rules (Sec. 6), in
+ * physical units as for the single-plate calls. */
+typedef struct {
+    int nx, ny;
+    double dx;
+    double rho0, lambda, mu, tau_over_dt;
+    double body[2];
+    lbm_bc bc_ymin, bc_ymax;
+    double val_ymin[2], val_ymax[2];
+} lbm_plate_desc;
+
+/* Arena bytes one plate of nx * ny sites uses at precision p. */
+size_t lbm_batch_plate_bytes(int nx, int ny, lbm_precision p);
+/* Tile-table entries one plate uses (column strips times row segments). */
+int lbm_batch_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s);
+/* Workspace bytes of a batch with room for max_plates plates, max_tiles
+ * tiles and arena_bytes of plate state. */
+size_t lbm_batch_workspace_bytes(int max_plates, int max_tiles, size_t arena_bytes);
+
+/* Create a batch on a caller-owned, 256-byte aligned device workspace and a
+ * HIP stream (both must outlive it). walled: 0 = plates periodic in y,
+ * 1 = plates with y walls. Everything beyond the tables is arena. Allocates
+ * small pinned host buffers for the tables. */
+lbm_status lbm_batch_create(int max_plates, int max_tiles, lbm_precision p, lbm_scheme s, int walled,
+                            void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_batch **out);
+
+/* Admit a plate with start fields u0, v0 (host, [2][ny][nx], physical) that
+ * is to run nsteps steps in total; returns its slot. LBM_ERR_NOMEM (and no
+ * change) if the arena, the tile table or the slots are full. Synchronises
+ * the stream. */
+lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0, const double *v0,
+                         int64_t nsteps, int *slot);
+
+/* Enqueue up to nsteps steps (at most 2^20) for every plate with steps
+ * left; a plate stops when it has done its nsteps. Returns at once. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Steps done and left and the unstable flag of a plate. Synchronises. */
+lbm_status lbm_batch_query(lbm_batch *b, int slot, int64_t *steps_done, int64_t *steps_left, int *unstable);
+
+/* Fields and diagnostics of a plate, as lbm_read_fields. Synchronises. */
+lbm_status lbm_batch_read(lbm_batch *b, int slot, double *u, double *v, double *P, lbm_diagnostics *d);
+
+/* Free a plate's slot, arena space and tiles. Synchronises the stream. */
+lbm_status lbm_batch_retire(lbm_batch *b, int slot);
+
+/* Live plates, free arena bytes and the largest free arena block. */
+lbm_status lbm_batch_info(const lbm_batch *b, int *live_plates, size_t *arena_free, size_t *arena_largest_free);
+
+void lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "lbm_solid.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lbm_solid.hip", "lbm_batch.hip")]
 LIB = os.path.join(HERE, "liblbm_solid.so")
 ARCH = "gfx950"
 
@@ -25,7 +25,7 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, SRC, "-o", tmp]
+    cmd = ["hipcc", *HIPCC_FLAGS, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -245,7 +245,7 @@ __global__ void __launch_bounds__(256) diag_kernel(const DiagParams p)
 }
 
 // Second stage: one block folds the per-block partials in index order.
-__global__ void __launch_bounds__(64) diag_final_kernel(const double *partials, int nblocks, double *out)
+static __global__ void __launch_bounds__(64) diag_final_kernel(const double *partials, int nblocks, double *out)
 {
     if (threadIdx.x != 0) return;
     double acc[7] = {0, 0, 0, 0, 1e300, 0, 0};

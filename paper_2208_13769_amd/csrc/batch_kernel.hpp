@@ -1,0 +1,79 @@
+// batch_kernel.hpp -- one time step of many plates in one launch.
+//
+// The plates of a batch live in one device arena; a plate table and a tile
+// table (plate, strip, segment) sit in device memory. A persistent grid of
+// a fixed size walks the tile table with a stride of gridDim.x, so one launch
+// (and one captured graph of K launches) serves any mix of plate sizes; the
+// host only rewrites the tables between chunks. Launch k of a chunk advances
+// plate p iff k < p.nsteps; its input copy is (parity0 + k) & 1 and its step
+// index step0 + k.
+#pragma once
+
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+struct PlateDesc {
+    void *f[2], *u[2], *j[2];  // the two state copies
+    int nx, ny;
+    long long plane;
+    double omega, lam, mu, bx, by;  // lattice units
+    int bc_lo, bc_hi;
+    double val_lo[2], val_hi[2];
+    double f_scale, f_inv_scale;
+    int strip_w, n_strips, n_segs, halo_a;
+    long long step0;  // step index of the state at the start of the chunk
+    int parity0;      // copy holding that state
+    int nsteps;       // steps of this plate in the chunk (0: idle)
+    unsigned *flag;   // this plate's unstable flag
+};
+
+struct TileDesc {
+    int plate, strip, seg, pad;
+};
+
+template <class PR, int BLOCK, bool PC, bool WALLED>
+__global__ void __launch_bounds__(BLOCK)
+    batch_step_kernel(const PlateDesc *__restrict__ plates, const TileDesc *__restrict__ tiles,
+                      const int *__restrict__ n_tiles, const int k)
+{
+    const int nt = *n_tiles;
+    for (int tile = blockIdx.x; tile < nt; tile += gridDim.x) {
+        const TileDesc td = tiles[tile];
+        const PlateDesc &pd = plates[td.plate];
+        if (k >= pd.nsteps) continue;  // uniform over the block
+        const int in = (pd.parity0 + k) & 1;
+        StepParams sp;
+        sp.f_in = pd.f[in];
+        sp.u_in = pd.u[in];
+        sp.j_in = pd.j[in];
+        sp.f_out = pd.f[in ^ 1];
+        sp.u_out = pd.u[in ^ 1];
+        sp.j_out = pd.j[in ^ 1];
+        sp.nx = pd.nx;
+        sp.ny = pd.ny;
+        sp.plane = pd.plane;
+        sp.omega = pd.omega;
+        sp.lam = pd.lam;
+        sp.mu = pd.mu;
+        sp.bx = pd.bx;
+        sp.by = pd.by;
+        sp.bc_lo = pd.bc_lo;
+        sp.bc_hi = pd.bc_hi;
+        sp.val_lo[0] = pd.val_lo[0];
+        sp.val_lo[1] = pd.val_lo[1];
+        sp.val_hi[0] = pd.val_hi[0];
+        sp.val_hi[1] = pd.val_hi[1];
+        sp.f_scale = pd.f_scale;
+        sp.f_inv_scale = pd.f_inv_scale;
+        sp.strip_w = pd.strip_w;
+        sp.n_strips = pd.n_strips;
+        sp.n_segs = pd.n_segs;
+        sp.halo_a = pd.halo_a;
+        sp.flag = pd.flag;
+        sp.step = pd.step0 + k;
+        step_tile<PR, BLOCK, PC, WALLED>(sp, td.strip, td.seg);
+    }
+}
+
+}  // namespace lbm

@@ -1,0 +1,327 @@
+// host_common.hpp -- host-side helpers shared by the single-plate and the
+// batched runtimes: state layout, launch shape and unit conversion.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_solid.h"
+#include "aux_kernels.hpp"
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct ElemSizes {
+    size_t f, u, j;  // bytes per element
+};
+
+inline ElemSizes elem_sizes(lbm_precision p)
+{
+    switch (p) {
+    case LBM_FP64: return {8, 8, 8};
+    case LBM_FP32: return {4, 4, 4};
+    case LBM_FP16_STORE:
+    case LBM_BF16_STORE: return {2, 8, 4};
+    }
+    return {0, 0, 0};
+}
+
+inline bool valid_precision(int p) { return p >= LBM_FP64 && p <= LBM_BF16_STORE; }
+
+// Offsets of the two state copies (f, u, j) of one plate from its base.
+struct StateLayout {
+    size_t f[2], u[2], j[2];
+    size_t bytes;  // total, 256-byte aligned
+};
+
+inline StateLayout state_layout(int nx, int ny, lbm_precision p)
+{
+    StateLayout L{};
+    const ElemSizes s = elem_sizes(p);
+    const size_t n = (size_t)nx * ny;
+    size_t off = 0;
+    for (int c = 0; c < 2; ++c) {
+        L.f[c] = off;
+        off = align_up(off + 9 * n * s.f);
+        L.u[c] = off;
+        off = align_up(off + 2 * n * s.u);
+        L.j[c] = off;
+        off = align_up(off + 2 * n * s.j);
+    }
+    L.bytes = off;
+    return L;
+}
+
+// Launch shape of one plate: column strips and row segments.
+struct Shape {
+    int block, strip_w, n_strips, n_segs, halo_a;
+};
+
+// When the plate is wider than one block's reach, each strip's output width
+// is a multiple of 128 bytes of the population type (32 floats / doubles,
+// 64 halves), so no cache line is written by two blocks; the spare threads
+// of the block extend the halo.
+inline Shape make_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int block, int n_segs)
+{
+    const int halo = s == LBM_SCHEME_PC ? 5 : 3;
+    const int wmax = block - 2 * halo;
+    const int align = (p == LBM_FP16_STORE || p == LBM_BF16_STORE) ? 64 : 32;
+    Shape sh{};
+    sh.block = block;
+    if (nx <= wmax) {
+        sh.strip_w = nx;
+        sh.n_strips = 1;
+        sh.halo_a = halo;
+    } else {
+        sh.strip_w = wmax >= align ? wmax / align * align : wmax;
+        sh.n_strips = (nx + sh.strip_w - 1) / sh.strip_w;
+        sh.halo_a = (block - sh.strip_w) / 2;
+    }
+    sh.n_segs = std::max(1, std::min(n_segs, ny));
+    return sh;
+}
+
+// Physical -> lattice units (dX = dt = rho0 = 1, c = dX/dt = sqrt(3 mu / rho0)).
+struct Units {
+    double dx, rho0, lam, mu;
+    double dt() const { return dx / (std::sqrt(3.0) * std::sqrt(mu / rho0)); }
+    double c() const { return dx / dt(); }
+    double stress() const { return rho0 * c() * c(); }  // P = stress * P_L
+    double momentum() const { return rho0 * c(); }     // j = momentum * j_L
+};
+
+// Material, body force and wall parameters of a step in lattice units.
+inline void fill_physics(StepParams &sp, const Units &U, double tau_over_dt, const double body[2], int bc_lo,
+                         const double val_lo[2], int bc_hi, const double val_hi[2])
+{
+    const double c = U.c(), sl = 1.0 / U.stress();
+    sp.omega = 1.0 / tau_over_dt;
+    sp.lam = U.lam * sl;
+    sp.mu = U.mu * sl;
+    sp.bx = body[0] * U.dt() / c;
+    sp.by = body[1] * U.dt() / c;
+    sp.bc_lo = bc_lo;
+    sp.bc_hi = bc_hi;
+    for (int a = 0; a < 2; ++a) {
+        // j* -> lattice momentum, T* -> lattice stress
+        sp.val_lo[a] = bc_lo == LBM_BC_DIRICHLET_J ? val_lo[a] / U.momentum() : val_lo[a] * sl;
+        sp.val_hi[a] = bc_hi == LBM_BC_DIRICHLET_J ? val_hi[a] / U.momentum() : val_hi[a] * sl;
+    }
+}
+
+// Geometry/material view used by the start-up, read-out and diagnostics kernels.
+inline FieldParams field_params(int nx, int ny, const Units &U, int bc_lo, const double val_lo[2], int bc_hi,
+                                const double val_hi[2], double t_steps)
+{
+    FieldParams fp{};
+    fp.nx = nx;
+    fp.ny = ny;
+    fp.plane = (long long)nx * ny;
+    fp.bc_lo = bc_lo;
+    fp.bc_hi = bc_hi;
+    for (int a = 0; a < 2; ++a) {
+        fp.uw_lo[a] = bc_lo == LBM_BC_DIRICHLET_J ? val_lo[a] / U.momentum() * t_steps : 0.0;
+        fp.uw_hi[a] = bc_hi == LBM_BC_DIRICHLET_J ? val_hi[a] / U.momentum() * t_steps : 0.0;
+    }
+    fp.lam = U.lam / U.stress();
+    fp.mu = U.mu / U.stress();
+    return fp;
+}
+
+// ---------------------------------------------------------------- launches
+
+template <class PR>
+struct Kernels {
+    template <int B, bool PC>
+    static void step_w(const StepParams &sp, int nblocks, hipStream_t st)
+    {
+        if (sp.bc_lo != BC_PERIODIC)
+            hipLaunchKernelGGL((step_kernel<PR, B, PC, true>), dim3(nblocks), dim3(B), 0, st, sp);
+        else
+            hipLaunchKernelGGL((step_kernel<PR, B, PC, false>), dim3(nblocks), dim3(B), 0, st, sp);
+    }
+    template <int B>
+    static hipError_t step_b(const StepParams &sp, int nblocks, bool pc, hipStream_t st)
+    {
+        if (pc)
+            step_w<B, true>(sp, nblocks, st);
+        else
+            step_w<B, false>(sp, nblocks, st);
+        return hipGetLastError();
+    }
+    static hipError_t step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st)
+    {
+        switch (block) {
+        case 64: return step_b<64>(sp, nblocks, pc, st);
+        case 128: return step_b<128>(sp, nblocks, pc, st);
+        case 512: return step_b<512>(sp, nblocks, pc, st);
+        default: return step_b<256>(sp, nblocks, pc, st);
+        }
+    }
+    static hipError_t init(const InitParams &ip, int nblocks, hipStream_t st)
+    {
+        hipLaunchKernelGGL((init_kernel<PR>), dim3(nblocks), dim3(256), 0, st, ip);
+        return hipGetLastError();
+    }
+    static hipError_t readout(const ReadParams &rp, int nblocks, hipStream_t st)
+    {
+        hipLaunchKernelGGL((readout_kernel<PR>), dim3(nblocks), dim3(256), 0, st, rp);
+        return hipGetLastError();
+    }
+    static hipError_t diag(const DiagParams &dp, int nblocks, hipStream_t st)
+    {
+        hipLaunchKernelGGL((diag_kernel<PR>), dim3(nblocks), dim3(256), 0, st, dp);
+        return hipGetLastError();
+    }
+};
+
+#define LBM_DISPATCH(prec, expr_with_PR)                                  \
+    [&]() -> hipError_t {                                                 \
+        switch (prec) {                                                   \
+        case LBM_FP64: { using PR = PrecF64; return expr_with_PR; }        \
+        case LBM_FP32: { using PR = PrecF32; return expr_with_PR; }        \
+        case LBM_FP16_STORE: { using PR = PrecF16; return expr_with_PR; }  \
+        default: { using PR = PrecBF16; return expr_with_PR; }            \
+        }                                                                 \
+    }()
+
+constexpr int kMaxDiagBlocks = 1024;
+constexpr size_t kStagingCap = size_t(16) << 20;  // bytes of read-out staging at most
+
+inline size_t staging_bytes_for(int nx, int ny)
+{
+    return std::min(8 * (size_t)nx * ny * sizeof(double), std::max(kStagingCap, 8 * (size_t)nx * sizeof(double)));
+}
+
+// Everything needed to start, read and diagnose one plate's state.
+struct PlateIO {
+    int nx, ny;
+    lbm_precision prec;
+    Units U;
+    int bc_lo, bc_hi;
+    double val_lo[2], val_hi[2];
+    void *f, *u, *j;            // current state copy
+    void *f_other;              // the other copy (staging for start-up)
+    double f_scale;
+    double *staging;            // read-out staging
+    size_t staging_bytes;
+    double *partials;           // kMaxDiagBlocks * 8 doubles
+    double *diag_out;           // 8 doubles
+    hipStream_t stream;
+};
+
+// f = f^eq of the start fields (u0, v0 host arrays). For 16-bit storage the
+// population scale is chosen here (returned in *scale); *nonfinite is set if
+// the start populations are not finite. Synchronises.
+inline hipError_t plate_start(const PlateIO &io, const double *u0, const double *v0, double *scale, bool *nonfinite)
+{
+    *nonfinite = false;
+    const size_t n = (size_t)io.nx * io.ny;
+    double *su = static_cast<double *>(io.f_other);  // the other copy holds >= 32 bytes per site
+    double *sv = su + 2 * n;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(su, u0, 2 * n * sizeof(double), hipMemcpyHostToDevice, io.stream))) return e;
+    if ((e = hipMemcpyAsync(sv, v0, 2 * n * sizeof(double), hipMemcpyHostToDevice, io.stream))) return e;
+    InitParams ip{};
+    const double zero[2] = {0.0, 0.0};
+    ip.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, zero, io.bc_hi, zero, 0.0);
+    ip.u0 = su;
+    ip.v0 = sv;
+    ip.f = io.f;
+    ip.u = io.u;
+    ip.j = io.j;
+    ip.inv_dx = 1.0 / io.U.dx;
+    ip.v_to_j = io.U.dt() / io.U.dx;
+    const int nblocks = (int)((n + 255) / 256);
+    *scale = 1.0;
+    if (io.prec == LBM_FP16_STORE || io.prec == LBM_BF16_STORE) {
+        // power-of-two scale that puts max |f| near 2^12 (FP16 tops out at 65504)
+        if ((size_t)nblocks * sizeof(double) > io.staging_bytes) return hipErrorOutOfMemory;
+        ip.mode = 0;
+        ip.maxf = io.staging;
+        if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::init(ip, nblocks, io.stream)))) return e;
+        std::vector<double> m(nblocks);
+        if ((e = hipMemcpyAsync(m.data(), ip.maxf, nblocks * sizeof(double), hipMemcpyDeviceToHost, io.stream)))
+            return e;
+        if ((e = hipStreamSynchronize(io.stream))) return e;
+        double mx = 0.0;
+        for (double v : m) mx = std::max(mx, v);
+        if (!std::isfinite(mx)) {
+            *nonfinite = true;
+            return hipSuccess;
+        }
+        if (mx > 0.0) *scale = std::ldexp(1.0, (int)std::floor(std::log2(4096.0 / mx)));
+    }
+    ip.mode = 1;
+    ip.f_scale = *scale;
+    if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::init(ip, nblocks, io.stream)))) return e;
+    return hipStreamSynchronize(io.stream);
+}
+
+// u, v, P (any may be NULL) and diagnostics (out7 may be NULL) of a plate
+// after t_steps steps. Synchronises.
+inline hipError_t plate_read(const PlateIO &io, double t_steps, double *u, double *v, double *P, double *out7)
+{
+    const int nx = io.nx, ny = io.ny;
+    const size_t n = (size_t)nx * ny;
+    hipError_t e;
+    if (u || v || P) {
+        ReadParams rp{};
+        rp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+        rp.u = io.u;
+        rp.j = io.j;
+        rp.out = io.staging;
+        rp.dx = io.U.dx;
+        rp.c = io.U.c();
+        rp.stress = io.U.stress();
+        const int rows_per =
+            (int)std::max<size_t>(1, std::min<size_t>(ny, io.staging_bytes / (8 * sizeof(double) * nx)));
+        for (int y = 0; y < ny; y += rows_per) {
+            const int rows = std::min(rows_per, ny - y);
+            rp.y_begin = y;
+            rp.rows = rows;
+            const size_t cnt = (size_t)rows * nx;
+            if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::readout(rp, (int)((cnt + 255) / 256), io.stream)))) return e;
+            double *dst[8] = {u, u ? u + n : nullptr, v, v ? v + n : nullptr,
+                              P, P ? P + n : nullptr, P ? P + 2 * n : nullptr, P ? P + 3 * n : nullptr};
+            for (int k = 0; k < 8; ++k) {
+                if (!dst[k]) continue;
+                if ((e = hipMemcpyAsync(dst[k] + (size_t)y * nx, rp.out + k * cnt, cnt * sizeof(double),
+                                        hipMemcpyDeviceToHost, io.stream)))
+                    return e;
+            }
+            if ((e = hipStreamSynchronize(io.stream))) return e;
+        }
+    }
+    if (out7) {
+        DiagParams dp{};
+        dp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+        dp.f = io.f;
+        dp.u = io.u;
+        dp.j = io.j;
+        dp.f_inv_scale = 1.0 / io.f_scale;
+        dp.rho0 = io.U.rho0;
+        dp.dx = io.U.dx;
+        dp.c = io.U.c();
+        dp.lam_phys = io.U.lam;
+        dp.mu_phys = io.U.mu;
+        dp.partials = io.partials;
+        const int nblocks = (int)std::min<size_t>(kMaxDiagBlocks, (n + 255) / 256);
+        if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::diag(dp, nblocks, io.stream)))) return e;
+        hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, io.stream, io.partials, nblocks, io.diag_out);
+        if ((e = hipGetLastError())) return e;
+        if ((e = hipMemcpyAsync(out7, io.diag_out, 7 * sizeof(double), hipMemcpyDeviceToHost, io.stream))) return e;
+        if ((e = hipStreamSynchronize(io.stream))) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace lbm

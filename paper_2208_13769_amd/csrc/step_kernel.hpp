@@ -137,8 +137,10 @@ __device__ __forceinline__ void wall_populations(bool top, int kind, const TC fc
     }
 }
 
+// One tile (column strip `strip`, row segment `seg`) of one plate for one
+// time step. Called by every thread of a block; ends with a barrier.
 template <class PR, int BLOCK, bool PC, bool WALLED>
-__global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
+__device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
@@ -169,16 +171,6 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)p.plane;
 
-    // Tile of this block. Blocks are dealt round-robin to the 8 XCDs; the
-    // remap gives each XCD a run of consecutive tiles, which are vertical
-    // neighbours sharing their halo rows in that XCD's L2.
-    const int nb = p.n_strips * p.n_segs;
-    const int bid = blockIdx.x;
-    const int xq = nb >> 3, xr = nb & 7;
-    const int xcd = bid & 7, loc = bid >> 3;
-    const int logical = xcd * xq + min(xcd, xr) + loc;
-    const int strip = logical / p.n_segs;
-    const int seg = logical - strip * p.n_segs;
     // Output strips start on multiples of strip_w, which the host keeps a
     // multiple of the 128-byte line, so row writes cover whole lines; the
     // threads outside [halo_a, halo_a + strip_w) only feed the halo.
@@ -278,7 +270,7 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int n_iter = (y1 - y0) + (PC ? 11 : 7);
     const int Rstart = y0 - HX;
 
-#pragma unroll 2
+
     for (int it = 0; it < n_iter; ++it) {
         const int R = Rstart + it;
         const int b = it & 1, pb = b ^ 1;
@@ -548,6 +540,22 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
         __syncthreads();
     }
     if (bad) p.flag[0] = 1u;
+}
+
+// Single-plate step: one block per tile. Blocks are dealt round-robin to the
+// 8 XCDs; the remap gives each XCD a run of consecutive tiles, which are
+// vertical neighbours sharing their halo rows in that XCD's L2.
+template <class PR, int BLOCK, bool PC, bool WALLED>
+__global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
+{
+    const int nb = p.n_strips * p.n_segs;
+    const int bid = blockIdx.x;
+    const int xq = nb >> 3, xr = nb & 7;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int logical = xcd * xq + min(xcd, xr) + loc;
+    const int strip = logical / p.n_segs;
+    const int seg = logical - strip * p.n_segs;
+    step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg);
 }
 
 }  // namespace lbm

@@ -1,0 +1,146 @@
+"""Batched plates (one persistent launch per step, graph-captured chunks)
+against the same plates run alone, and against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2208_13769_amd import inputs
+from tests.helpers import oracle_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _plate_inputs(n, ny, seed, walled):
+    if walled:
+        u0, v0 = inputs.top_pulse(max(n, ny), 0.01)
+        u0, v0 = u0[:, :ny, :n].copy(), v0[:, :ny, :n].copy()
+        v0 = v0 + inputs.filtered_random_velocity(n, ny, 2.0, seed, 0.002)[1]
+    else:
+        u0, v0 = inputs.filtered_random_velocity(n, ny, 3.0, seed, 0.03)
+    return np.ascontiguousarray(u0), np.ascontiguousarray(v0)
+
+
+def _single(spec, u0, v0, nsteps, precision, scheme="pc"):
+    from paper_2208_13769_amd import lbm
+
+    s = lbm.Solver(spec.nx, spec.ny, spec.dx, precision, scheme)
+    s.set_material(spec.rho0, spec.lam, spec.mu, spec.tau_over_dt)
+    if spec.bc_ymin != lbm.LBM_BC_PERIODIC:
+        s.set_boundary(lbm.LBM_EDGE_YMIN, spec.bc_ymin, spec.val_ymin)
+        s.set_boundary(lbm.LBM_EDGE_YMAX, spec.bc_ymax, spec.val_ymax)
+    s.set_fields(u0, v0)
+    s.step(nsteps)
+    out = s.read()
+    s.close()
+    return out
+
+
+def _specs(walled):
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.batch import PlateSpec
+
+    sizes = [(40, 33), (64, 64), (100, 71), (260, 90), (300, 150), (517, 40)]
+    specs = []
+    for k, (nx, ny) in enumerate(sizes):
+        sp = PlateSpec(nx=nx, ny=ny, lam=0.05 + 0.02 * k, mu=0.03 + 0.01 * k, tau_over_dt=0.7 + 0.05 * k)
+        if walled:
+            sp.bc_ymin, sp.bc_ymax = lbm.LBM_BC_DIRICHLET_J, lbm.LBM_BC_NEUMANN_T
+            sp.val_ymin = (0.0, 0.0)
+            sp.val_ymax = (0.0, 0.001 * (k % 2))
+        specs.append(sp)
+    return specs
+
+
+@pytest.mark.parametrize("precision,walled", [("fp16", True), ("fp32", False), ("fp64", True)])
+def test_batch_equals_plates_alone(gpu, precision, walled):
+    """Every plate of a mixed batch equals the same plate run alone, bitwise,
+    after each of several graph-replayed chunks (eager reads in between);
+    plates with fewer steps stop at their own count."""
+    from paper_2208_13769_amd.batch import Batch
+
+    specs = _specs(walled)
+    targets = [60, 60, 35, 60, 50, 60]
+    b = Batch(max_plates=8, arena_bytes=256 << 20, precision=precision, walled=walled)
+    slots, ins = [], []
+    for k, sp in enumerate(specs):
+        u0, v0 = _plate_inputs(sp.nx, sp.ny, 30 + k, walled)
+        ins.append((u0, v0))
+        slots.append(b.add(sp, u0, v0, targets[k]))
+    assert None not in slots
+    done = 0
+    for chunk in (20, 20, 20):
+        b.step(chunk)
+        done += chunk
+        for k, sp in enumerate(specs):
+            n = min(done, targets[k])
+            ub, vb, Pb, db, st = b.read(slots[k])
+            us, vs, Ps, ds, st2 = _single(sp, *ins[k], n, precision)
+            assert st == 0 and st2 == 0 and db.steps == n
+            assert np.array_equal(ub, us) and np.array_equal(vb, vs), (k, n)
+    b.close()
+
+
+def test_batch_fp64_matches_oracle(gpu):
+    from paper_2208_13769_amd.batch import Batch
+
+    specs = _specs(True)[:3]
+    b = Batch(max_plates=4, arena_bytes=64 << 20, precision="fp64", walled=True)
+    for k, sp in enumerate(specs):
+        u0, v0 = _plate_inputs(sp.nx, sp.ny, 40 + k, True)
+        slot = b.add(sp, u0, v0, 40)
+        b.step(40)
+        ub, vb, Pb, db, st = b.read(slot)
+        uo, vo, Po, do = oracle_run(sp.nx, sp.ny, u0, v0, 40, lam=sp.lam, mu=sp.mu, tau=sp.tau_over_dt,
+                                    bc_lo=("dirichlet", sp.val_ymin), bc_hi=("neumann", sp.val_ymax))
+        assert rel_l2(ub, uo) < 1e-12 and rel_l2(Pb, Po) < 1e-12
+        b.retire(slot)
+    b.close()
+
+
+def test_batch_admission_and_reuse(gpu):
+    """Admission by arena footprint: a plate that does not fit is refused;
+    retiring frees the space for the next one, which then runs correctly."""
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+
+    sp_big = PlateSpec(nx=256, ny=256)
+    b0 = Batch(max_plates=4, arena_bytes=1, precision="fp32")
+    need = b0.plate_bytes(256, 256)
+    b0.close()
+    b = Batch(max_plates=4, arena_bytes=need + need // 2, precision="fp32")
+    u0, v0 = _plate_inputs(256, 256, 50, False)
+    s1 = b.add(sp_big, u0, v0, 10)
+    assert s1 is not None
+    assert b.add(sp_big, u0, v0, 10) is None  # no room for a second one
+    b.step(10)
+    b.retire(s1)
+    sp2 = PlateSpec(nx=200, ny=180, lam=0.08, mu=0.04)
+    u2, v2 = _plate_inputs(200, 180, 51, False)
+    s2 = b.add(sp2, u2, v2, 25)
+    assert s2 is not None
+    b.step(25)
+    ub, vb, *_ = b.read(s2)
+    us, vs, *_ = _single(sp2, u2, v2, 25, "fp32")
+    assert np.array_equal(ub, us) and np.array_equal(vb, vs)
+    n, free, big = b.info()
+    assert n == 1 and free > 0
+    b.close()
+
+
+def test_batch_unstable_plate_is_isolated(gpu):
+    """A plate that blows up (lam/mu = 10) raises its own flag; the other
+    plate's result is unchanged."""
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+
+    good = PlateSpec(nx=96, ny=64)
+    bad = PlateSpec(nx=64, ny=64, lam=0.5, mu=0.05)
+    ug, vg = _plate_inputs(96, 64, 60, False)
+    ub_, vb_ = inputs.random_field(64, 64, 61, 0.0), inputs.random_field(64, 64, 62, 1e-6)
+    b = Batch(max_plates=2, arena_bytes=64 << 20, precision="fp32")
+    sg = b.add(good, ug, vg, 300)
+    sb = b.add(bad, ub_, vb_, 300)
+    b.step(300)
+    assert b.query(sb)[2] is True
+    assert b.query(sg)[2] is False
+    u1, v1, *_ = b.read(sg)
+    u2, v2, *_ = _single(good, ug, vg, 300, "fp32")
+    assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
+    b.close()
