@@ -97,6 +97,97 @@ def cpu_baseline(wl, steps: int):
                        f"FP64, {el:.1f} s"), (u, v, P)
 
 
+def bench_config4(args):
+    """256 plates of uneven sizes in one batch (one persistent launch per
+    step, graph-captured chunks), FP16 populations, 2000 steps each."""
+    import torch
+
+    from paper_2208_13769_amd import inputs, lbm
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+
+    plates = inputs.plate_batch(256, seed=4)
+    steps = args.plate_steps
+    specs, fields = [], []
+    for pl in plates:
+        specs.append(PlateSpec(nx=pl.n, ny=pl.n, lam=pl.lam, mu=pl.mu, tau_over_dt=0.8,
+                               bc_ymin=lbm.LBM_BC_DIRICHLET_J, bc_ymax=lbm.LBM_BC_NEUMANN_T))
+        fields.append(inputs.top_pulse(pl.n, 0.01))
+    sites = sum(sp.nx * sp.ny for sp in specs)
+
+    def run_batch(precision):
+        arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, precision) for sp in specs) + (64 << 20)
+        b = Batch(max_plates=len(specs), arena_bytes=arena, precision=precision, walled=True)
+        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
+        b.step(args.chunk)  # warm-up chunk: graph capture, first touch
+        torch.cuda.synchronize()
+        # restart from the start fields for the timed run
+        for s_ in slots:
+            b.retire(s_)
+        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        left = steps
+        while left > 0:
+            b.step(min(args.chunk, left))
+            left -= args.chunk
+        e1.record(b.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        return b, slots, ms
+
+    b16, s16, ms16 = run_batch("fp16")
+    bad = [i for i, s_ in enumerate(s16) if b16.query(s_)[2]]
+    done_sites = sum(specs[i].nx * specs[i].ny for i in range(len(specs)) if i not in bad)
+    mlups16 = done_sites * steps / (ms16 / 1e3) / 1e6
+    b64, s64, ms64 = run_batch("fp64")
+    errs_u, errs_p = [], []
+    for i in range(len(specs)):
+        if i in bad:
+            continue
+        u1, _, p1, _, _ = b16.read(s16[i])
+        u2, _, p2, _, _ = b64.read(s64[i])
+        errs_u.append(np.linalg.norm(u1 - u2) / np.linalg.norm(u2))
+        errs_p.append(np.linalg.norm(p1 - p2) / np.linalg.norm(p2))
+    b16.close()
+    b64.close()
+    # plain FP32, one plate at a time, on every 16th plate
+    sample = list(range(0, len(specs), 16))
+    t_fp32, ups_fp32 = 0.0, 0
+    for i in sample:
+        sp, (u0, v0) = specs[i], fields[i]
+        s = lbm.Solver(sp.nx, sp.ny, 1.0, "fp32", "pc")
+        s.set_material(1.0, sp.lam, sp.mu, sp.tau_over_dt)
+        s.set_boundary(lbm.LBM_EDGE_YMIN, sp.bc_ymin, (0.0, 0.0))
+        s.set_boundary(lbm.LBM_EDGE_YMAX, sp.bc_ymax, (0.0, 0.0))
+        s.set_fields(u0, v0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        t_fp32 += time.perf_counter() - t0
+        ups_fp32 += sp.nx * sp.ny * steps
+        s.close()
+    out = {
+        "metric": METRIC, "value": round(mlups16, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": args.chunk, "ms_per_step": round(ms16 / steps, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE["fp16"], "data": "synthetic",
+        "config": {"workload": "256 plates, side log-uniform 64..1024 (seed 4), lam U[0.05,0.2], mu U[0.02,0.1], "
+                               "tau/dt=0.8, periodic in x, clamped bottom, traction-free top, initial top "
+                               "velocity pulse 0.01; FP16 populations; one batch, one launch per step",
+                   "plates": len(specs), "sites": sites, "chunk": args.chunk},
+        "diverged_plates": len(bad),
+        "diverged_lam_over_mu": sorted(round(specs[i].lam / specs[i].mu, 2) for i in bad),
+        "error_vs_fp64": {"median_rel_l2_u": float(np.median(errs_u)), "max_rel_l2_u": float(np.max(errs_u)),
+                          "median_rel_l2_P": float(np.median(errs_p)), "max_rel_l2_P": float(np.max(errs_p)),
+                          "reference": "the same batch in FP64 (bitwise equal to single-plate FP64)"},
+        "fp64_batch_MLUPS": round(sites * steps / (ms64 / 1e3) / 1e6, 1),
+        "plain_fp32_one_at_a_time_MLUPS": round(ups_fp32 / t_fp32 / 1e6, 1),
+        "plain_fp32_sample": f"every 16th plate ({len(sample)} plates), {steps} steps each",
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +200,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB (float32 read + "
                          "write) three times: its HBM counter readings calibrate the step kernel's")
+    ap.add_argument("--plate-steps", type=int, default=2000, help="config4: steps per plate")
+    ap.add_argument("--chunk", type=int, default=200, help="config4: steps per graph-captured chunk")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -120,6 +213,9 @@ def main():
     from paper_2208_13769_amd import lbm
     from paper_2208_13769_amd.autotune import best_tiling
 
+    if args.workload == "config4":
+        bench_config4(args)
+        return
     wl = workload(args.workload)
     nx, ny, prec = wl["nx"], wl["ny"], wl["precision"]
     s = lbm.Solver(nx, ny, 1.0, prec, "pc")

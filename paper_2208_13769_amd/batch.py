@@ -203,6 +203,10 @@ class Batch:
     def plate_bytes(self, nx, ny):
         return lbm_batch_plate_bytes(nx, ny, self.precision)
 
+    @staticmethod
+    def plate_bytes_for(nx, ny, precision: str):
+        return lbm_batch_plate_bytes(nx, ny, lbm.PRECISIONS[precision])
+
     def add(self, spec: PlateSpec, u0, v0, nsteps: int):
         slot = lbm_batch_add(self.h, spec.c(), u0, v0, nsteps)
         if slot is not None:

@@ -25,7 +25,8 @@ using namespace lbm;
 namespace {
 
 constexpr int kBatchBlock = 256;
-constexpr int kSegRows = 64;  // target rows per segment of a plate
+constexpr int kSegRowsMax = 64;  // rows per segment when the batch is full
+constexpr int kSegRowsMin = 16;  // shortest segment when few plates run
 
 struct Slot {
     bool live = false;
@@ -72,9 +73,16 @@ BatchLayout batch_layout(int max_plates, int max_tiles, size_t arena_bytes)
     return B;
 }
 
-Shape batch_shape(int nx, int ny, lbm_precision p, lbm_scheme s)
+Shape batch_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int seg_rows)
 {
-    return make_shape(nx, ny, p, s, kBatchBlock, std::max(1, (ny + kSegRows / 2) / kSegRows));
+    return make_shape(nx, ny, p, s, kBatchBlock, std::max(1, (ny + seg_rows / 2) / seg_rows));
+}
+
+// Tile-table entries a plate may need (at the shortest segments).
+int max_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s)
+{
+    const Shape sh = batch_shape(nx, ny, p, s, kSegRowsMin);
+    return sh.n_strips * sh.n_segs;
 }
 
 }  // namespace
@@ -307,8 +315,7 @@ size_t lbm_batch_plate_bytes(int nx, int ny, lbm_precision p)
 int lbm_batch_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s)
 {
     if (nx < 5 || ny < 5 || !valid_precision(p)) return 0;
-    const Shape sh = batch_shape(nx, ny, p, s);
-    return sh.n_strips * sh.n_segs;
+    return max_plate_tiles(nx, ny, p, s);
 }
 
 size_t lbm_batch_workspace_bytes(int max_plates, int max_tiles, size_t arena_bytes)
@@ -398,8 +405,9 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
             break;
         }
     if (s < 0) return bfail(b, LBM_ERR_NOMEM, "no free plate slot");
-    const Shape sh = batch_shape(d->nx, d->ny, b->prec, b->scheme);
-    if (b->tiles_used + sh.n_strips * sh.n_segs > b->max_tiles) return bfail(b, LBM_ERR_NOMEM, "tile table full");
+    const Shape sh = batch_shape(d->nx, d->ny, b->prec, b->scheme, kSegRowsMax);
+    const int tmax = max_plate_tiles(d->nx, d->ny, b->prec, b->scheme);
+    if (b->tiles_used + tmax > b->max_tiles) return bfail(b, LBM_ERR_NOMEM, "tile table full");
     const StateLayout L = state_layout(d->nx, d->ny, b->prec);
     size_t off = 0;
     if (!arena_alloc(b, L.bytes, &off)) return bfail(b, LBM_ERR_NOMEM, "arena full");
@@ -434,7 +442,7 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
     }
     sl.f_scale = scale;
     sl.live = true;
-    b->tiles_used += sh.n_strips * sh.n_segs;
+    b->tiles_used += tmax;
     b->tables_valid = false;
     *slot = s;
     return LBM_OK;
@@ -460,11 +468,25 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     // rewrite the tables in the pinned buffer not read by an earlier copy still in flight
     const int w = b->buf;
     if (b->ev_used[w]) BHIP_TRY(b, hipEventSynchronize(b->ev[w]));
+    const bool tiles_changed = !b->tables_valid || run != b->running;
+    if (tiles_changed) {
+        // Segment height for the running set: about two tiles per block of
+        // the persistent grid, segments between kSegRowsMin and kSegRowsMax
+        // rows (short segments keep a step short when few plates run; long
+        // ones keep the halo rows few when many do).
+        long long strip_rows = 0;
+        for (int i : run) {
+            const Shape one = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, 1 << 30);
+            strip_rows += (long long)one.n_strips * b->slots[i].ny;
+        }
+        const long long want = 2LL * b->grid;
+        const int seg_rows = (int)std::max<long long>(kSegRowsMin, std::min<long long>(kSegRowsMax, strip_rows / want));
+        for (int i : run) b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, seg_rows);
+    }
     int max_slot = 0;
     for (int i : run) max_slot = std::max(max_slot, i + 1);
     std::memset(b->h_plates[w], 0, sizeof(PlateDesc) * max_slot);
     for (int i : run) b->h_plates[w][i] = describe(b, i, (int)std::min<int64_t>(K, b->slots[i].target - b->slots[i].done));
-    const bool tiles_changed = !b->tables_valid || run != b->running;
     int nt = 0;
     if (tiles_changed) {
         // plate by plate, strip by strip; consecutive tiles are vertical
@@ -548,7 +570,7 @@ lbm_status lbm_batch_retire(lbm_batch *b, int slot)
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
     Slot &sl = b->slots[slot];
     arena_free(b, sl.arena_off, sl.L.bytes);
-    b->tiles_used -= sl.shape.n_strips * sl.shape.n_segs;
+    b->tiles_used -= max_plate_tiles(sl.nx, sl.ny, b->prec, b->scheme);
     sl.live = false;
     b->tables_valid = false;
     return LBM_OK;
