@@ -67,15 +67,16 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_for(precision: str, sites: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"step_{precision}_4096_counters.json")
+def traffic_for(precision: str, sites: int, block: int, segs: int):
+    """HBM bytes per launch from the committed rocprofv3 counter record, if it
+    was taken on the current kernel source with the same launch shape."""
+    path = os.path.join(ROOT, "profiles", f"step_{precision}_4096_counters.txt")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("kernel_hash") != kernel_source_hash() or rec.get("sites") != sites:
+    if (rec.get("kernel_hash") != kernel_source_hash() or rec.get("sites") != sites
+            or rec.get("tiling") != {"block": block, "n_segs": segs}):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -262,7 +263,7 @@ def main():
     bytes_launch = BYTES_PER_UPDATE[prec] * sites
     achieved = bytes_launch / (ms_step / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites, block, segs),
                 "bytes_per_update": BYTES_PER_UPDATE[prec]}
 
     out = {
