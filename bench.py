@@ -6,12 +6,19 @@ dX = rho0 = 1, neo-Hooke lam = 0.1, mu = 0.05, tau/dt = 0.8, predictor-
 corrector source, FP32 storage and arithmetic; u0 = 0 and a seeded
 Gaussian-filtered velocity field (sigma = 32 cells, seed 2) scaled to the
 calibrated peak velocity (tests/golden/config2_amplitude.json). A "step" is
-one time step of the whole grid (one launch of the fused step kernel).
+one time step of the whole grid; the fused step kernel advances one or two
+steps per launch (the autotuner picks).
 
-Prints one JSON line with MLUPS, the HBM roofline fraction of the step kernel
-(algorithmic bytes per lattice update: the 13-value state read once and
-written once), the FP64 oracle timed on the host cores on a bounded sample,
-and the rel-L2 error of the GPU against that oracle sample.
+Prints one JSON line with MLUPS, the HBM roofline fraction of the step kernel,
+the FP64 oracle timed on the host cores on a bounded sample, and the rel-L2
+error of the GPU against that oracle sample.
+
+Roofline accounting: a launch must read the 13-value state (f, u, j) of every
+site once and write it once, however many time steps it fuses, so its
+algorithmic bytes are BYTES_PER_SITE_PASS x sites per launch (104 B per site
+in FP32). With two steps per launch that is 52 B per lattice update; the
+per-step figure of a one-step-per-launch pass (104 B per update in FP32) is
+reported beside it as ``per_step_equivalent_GBps`` for comparison only.
 """
 from __future__ import annotations
 
@@ -29,9 +36,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (fp64/fp32/fp16-storage) at stated error vs FP64 oracle; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per lattice update: f (9), u (2), j (2) read and written
-BYTES_PER_UPDATE = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
-                    "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
+# algorithmic bytes per site per pass over the state: f (9), u (2), j (2)
+# read once and written once
+BYTES_PER_SITE_PASS = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
+                       "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
 
 
@@ -67,7 +75,7 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_for(precision: str, sites: int, block: int, segs: int):
+def traffic_for(precision: str, sites: int, block: int, segs: int, spl: int):
     """HBM bytes per launch from the committed rocprofv3 counter record, if it
     was taken on the current kernel source with the same launch shape."""
     path = os.path.join(ROOT, "profiles", f"step_{precision}_4096_counters.txt")
@@ -76,7 +84,7 @@ def traffic_for(precision: str, sites: int, block: int, segs: int):
     with open(path) as fh:
         rec = json.load(fh)
     if (rec.get("kernel_hash") != kernel_source_hash() or rec.get("sites") != sites
-            or rec.get("tiling") != {"block": block, "n_segs": segs}):
+            or rec.get("tiling") != {"block": block, "n_segs": segs, "steps_per_launch": spl}):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -195,9 +203,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config2")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiling", default="auto", help="auto | default | BLOCK,NSEGS")
+    ap.add_argument("--tiling", default="auto", help="auto | default | BLOCK,NSEGS,STEPS_PER_LAUNCH")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB (float32 read + "
                          "write) three times: its HBM counter readings calibrate the step kernel's")
@@ -224,15 +232,18 @@ def main():
     s.set_fields(wl["u0"], wl["v0"])
     tiling_source = "default"
     if args.tiling == "auto":
-        block, segs = best_tiling(s, nx, ny, prec, "pc")
+        block, segs, spl = best_tiling(s, nx, ny, prec, "pc")
+        s.set_steps_per_launch(spl)
         s.set_tiling(block, segs)
         s.set_fields(wl["u0"], wl["v0"])
         tiling_source = "autotuned"
     elif args.tiling != "default":
-        block, segs = map(int, args.tiling.split(","))
+        block, segs, spl = map(int, args.tiling.split(","))
+        s.set_steps_per_launch(spl)
         s.set_tiling(block, segs)
         tiling_source = "given"
     block, segs = s.tiling()
+    spl = s.steps_per_launch()
 
     stream = s.stream
     if args.copy_probe_mib > 0:
@@ -260,18 +271,22 @@ def main():
     sites = nx * ny
     ms_step = ms / args.steps
     mlups = sites * args.steps / (ms / 1e3) / 1e6
-    bytes_launch = BYTES_PER_UPDATE[prec] * sites
-    achieved = bytes_launch / (ms_step / 1e3) / 1e9
+    # a launch advances every site by `spl` time steps in one pass over the state
+    ms_launch = spl * ms_step
+    bytes_launch = BYTES_PER_SITE_PASS[prec] * sites
+    achieved = bytes_launch / (ms_launch / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites, block, segs),
-                "bytes_per_update": BYTES_PER_UPDATE[prec]}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites, block, segs, spl),
+                "kernel": "step2_kernel" if spl == 2 else "step_kernel", "steps_per_launch": spl,
+                "launch_us": round(ms_launch * 1e3, 2), "bytes_per_site_per_launch": BYTES_PER_SITE_PASS[prec],
+                "per_step_equivalent_GBps": round(BYTES_PER_SITE_PASS[prec] * sites / (ms_step / 1e3) / 1e9, 1)}
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [nx, ny], "sites": sites, "precision": prec, "scheme": "pc",
-                   "tiling": {"block": block, "n_segs": segs, "source": tiling_source},
+                   "tiling": {"block": block, "n_segs": segs, "steps_per_launch": spl, "source": tiling_source},
                    "wall_s": round(wall, 4)},
         "roofline": roofline,
         "run": {"status": int(status), "max_strain": diag.max_strain, "min_J": diag.min_J},

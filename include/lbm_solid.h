@@ -132,6 +132,22 @@ lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_d
 lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs);
 lbm_status lbm_get_tiling(const lbm_solver *h, int *block, int *n_segs);
 
+/* Time steps per launch of the step kernel: 1, or 2 with the
+ * predictor-corrector scheme (two steps fused in one pass over the state,
+ * which halves the memory traffic per step; results are bitwise the same).
+ * An odd remainder of lbm_step runs as a single step. With 2, blocks are at
+ * most 256 threads (a 512-thread tiling is lowered to 256). */
+lbm_status lbm_set_steps_per_launch(lbm_solver *h, int k);
+lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k);
+
+/* Number of blocks of the step kernel with this launch shape (threads per
+ * block, time steps per launch) that the handle's device runs at once, for
+ * the handle's precision, scheme and boundaries: blocks per compute unit from
+ * the occupancy calculator times the number of compute units. A grid of at
+ * most this many blocks runs in a single wave of blocks; n_segs can be
+ * chosen with it. Writes 0 for a shape the handle cannot launch. */
+lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_launch, int *blocks);
+
 /* Time step dt of the handle's material. */
 lbm_status lbm_get_dt(const lbm_solver *h, double *dt);
 

@@ -8,6 +8,7 @@ fastest. Results are cached in a JSON file (``$LBM_AUTOTUNE_CACHE``, default
 ``~/.cache/lbm_solid/autotune.json``) keyed by device name and problem.
 
 Tuning advances the solver's state: call ``set_fields`` again afterwards.
+``best_tiling`` returns (block, segments, steps per launch).
 """
 from __future__ import annotations
 
@@ -42,30 +43,51 @@ def _store_cache(cache: dict) -> None:
         pass
 
 
-def candidates(nx: int, ny: int, scheme: str):
-    """Block widths that fit the plate and segment counts spanning 1/4 to 16
-    blocks per CU of a 256-CU device, each segment at least 8 rows."""
+def strips(nx: int, block: int, precision: str, scheme: str, spl: int) -> int:
+    """Column strips of a launch shape (the library's own rule: strips as wide
+    as the block minus both halos, rounded down to whole 128-byte lines)."""
+    halo = HALO[scheme] * spl
+    wmax = block - 2 * halo
+    if nx <= wmax:
+        return 1
+    align = 64 if precision in ("fp16", "bf16") else 32
+    w = wmax // align * align if wmax >= align else wmax
+    return -(-nx // w)
+
+
+def candidates(solver, nx: int, ny: int, precision: str, scheme: str):
+    """(block, segments, steps per launch): block widths that fit the plate,
+    one or two time steps per launch (two only with the predictor-corrector
+    and blocks of at most 256 threads), and segment counts that fill 1/2, 1,
+    2, 3 or 4 waves of the blocks the device holds at once (each segment at
+    least 8 rows)."""
     out = []
-    for block in (64, 128, 256, 512):
-        w = block - 2 * HALO[scheme]
-        strips = -(-nx // w)
-        if block > 64 and strips == 1 and nx <= (block // 2) - 2 * HALO[scheme]:
-            continue  # a narrower block already covers the width
-        seen = set()
-        for target in (64, 128, 256, 512, 1024, 2048, 4096):
-            segs = max(1, min(ny // 8 if ny >= 8 else 1, -(-target // strips)))
-            if segs not in seen:
-                seen.add(segs)
-                out.append((block, segs))
+    for spl in ((1, 2) if scheme == "pc" else (1,)):
+        for block in (64, 128, 256, 512):
+            resident = solver.resident_blocks(block, spl)
+            if resident <= 0:
+                continue
+            halo = HALO[scheme] * spl
+            n_str = strips(nx, block, precision, scheme, spl)
+            if block > 64 and n_str == 1 and nx <= (block // 2) - 2 * halo:
+                continue  # a narrower block already covers the width
+            seen = set()
+            for waves in (0.5, 1, 2, 3, 4):
+                segs = max(1, min(max(1, ny // 8), int(waves * resident) // n_str))
+                if segs not in seen:
+                    seen.add(segs)
+                    out.append((block, segs, spl))
     return out
 
 
 def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
+    """Time every candidate; returns ((block, segs, steps per launch), ms per step, table)."""
     import torch
 
     stream = solver.stream
     best, best_ms, table = None, float("inf"), []
-    for block, segs in candidates(nx, ny, scheme):
+    for block, segs, spl in candidates(solver, nx, ny, precision, scheme):
+        solver.set_steps_per_launch(spl)
         solver.set_tiling(block, segs)
         solver.step(2)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -75,16 +97,16 @@ def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        table.append([block, segs, ms])
+        table.append([block, segs, spl, ms])
         if ms < best_ms:
-            best, best_ms = (block, segs), ms
+            best, best_ms = (block, segs, spl), ms
     return best, best_ms, table
 
 
 def best_tiling(solver, nx: int, ny: int, precision: str, scheme: str):
     import torch
 
-    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}"
+    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v3"
     cache = _load_cache()
     if key in cache:
         return tuple(cache[key]["tiling"])

@@ -69,9 +69,10 @@ struct Shape {
 // is a multiple of 128 bytes of the population type (32 floats / doubles,
 // 64 halves), so no cache line is written by two blocks; the spare threads
 // of the block extend the halo.
-inline Shape make_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int block, int n_segs)
+inline Shape make_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int block, int n_segs,
+                        int steps_per_launch = 1)
 {
-    const int halo = s == LBM_SCHEME_PC ? 5 : 3;
+    const int halo = (s == LBM_SCHEME_PC ? 5 : 3) * steps_per_launch;
     const int wmax = block - 2 * halo;
     const int align = (p == LBM_FP16_STORE || p == LBM_BF16_STORE) ? 64 : 32;
     Shape sh{};
@@ -166,6 +167,53 @@ struct Kernels {
         default: return step_b<256>(sp, nblocks, pc, st);
         }
     }
+    template <int B>
+    static void step2_b(const StepParams &sp, int nblocks, hipStream_t st)
+    {
+        if (sp.bc_lo != BC_PERIODIC)
+            hipLaunchKernelGGL((step2_kernel<PR, B, true>), dim3(nblocks), dim3(B), 0, st, sp);
+        else
+            hipLaunchKernelGGL((step2_kernel<PR, B, false>), dim3(nblocks), dim3(B), 0, st, sp);
+    }
+    // two predictor-corrector steps per launch
+    static hipError_t step2(const StepParams &sp, int block, int nblocks, hipStream_t st)
+    {
+        // (two pipelines of LDS do not fit a 512-thread block)
+        switch (block) {
+        case 64: step2_b<64>(sp, nblocks, st); break;
+        case 128: step2_b<128>(sp, nblocks, st); break;
+        case 256: step2_b<256>(sp, nblocks, st); break;
+        default: return hipErrorInvalidConfiguration;
+        }
+        return hipGetLastError();
+    }
+    // blocks of one step-kernel instantiation that a compute unit holds at once
+    template <typename K>
+    static int per_cu(K kernel, int block)
+    {
+        int n = 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) == hipSuccess ? n : 0;
+    }
+    template <int B>
+    static int resident_b(int spl, bool pc, bool walled)
+    {
+        if constexpr (B <= 256) {
+            if (spl == 2)
+                return walled ? per_cu(step2_kernel<PR, B, true>, B) : per_cu(step2_kernel<PR, B, false>, B);
+        }
+        if (pc)
+            return walled ? per_cu(step_kernel<PR, B, true, true>, B) : per_cu(step_kernel<PR, B, true, false>, B);
+        return walled ? per_cu(step_kernel<PR, B, false, true>, B) : per_cu(step_kernel<PR, B, false, false>, B);
+    }
+    static int resident_per_cu(int block, int spl, bool pc, bool walled)
+    {
+        switch (block) {
+        case 64: return resident_b<64>(spl, pc, walled);
+        case 128: return resident_b<128>(spl, pc, walled);
+        case 256: return resident_b<256>(spl, pc, walled);
+        default: return spl == 2 ? 0 : resident_b<512>(1, pc, walled);
+        }
+    }
     static hipError_t init(const InitParams &ip, int nblocks, hipStream_t st)
     {
         hipLaunchKernelGGL((init_kernel<PR>), dim3(nblocks), dim3(256), 0, st, ip);
@@ -258,7 +306,8 @@ inline hipError_t plate_start(const PlateIO &io, const double *u0, const double 
             *nonfinite = true;
             return hipSuccess;
         }
-        if (mx > 0.0) *scale = std::ldexp(1.0, (int)std::floor(std::log2(4096.0 / mx)));
+        // (exponent kept within +-60 so the scale and its inverse stay normal floats)
+        if (mx > 0.0) *scale = std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(std::log2(4096.0 / mx)))));
     }
     ip.mode = 1;
     ip.f_scale = *scale;

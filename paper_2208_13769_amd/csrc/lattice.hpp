@@ -42,12 +42,14 @@ template <>
 struct FStore<double> {
     __device__ static double load(const double *p, size_t i, double) { return p[i]; }
     __device__ static double cvt(double v, double) { return v; }
+    __device__ static double roundtrip(double v, double, double) { return v; }
     __device__ static void store(double *p, size_t i, double v, double) { p[i] = v; }
 };
 template <>
 struct FStore<float> {
     __device__ static float load(const float *p, size_t i, float) { return p[i]; }
     __device__ static float cvt(float v, float) { return v; }
+    __device__ static float roundtrip(float v, float, float) { return v; }
     __device__ static void store(float *p, size_t i, float v, float) { p[i] = v; }
 };
 template <>
@@ -57,6 +59,11 @@ struct FStore<__half> {
         return __half2float(p[i]) * inv_scale;
     }
     __device__ static float cvt(__half v, float inv_scale) { return __half2float(v) * inv_scale; }
+    // the value a store followed by a load gives back
+    __device__ static float roundtrip(float v, float scale, float inv_scale)
+    {
+        return __half2float(__float2half_rn(v * scale)) * inv_scale;
+    }
     __device__ static void store(__half *p, size_t i, float v, float scale)
     {
         p[i] = __float2half_rn(v * scale);
@@ -69,6 +76,10 @@ struct FStore<__hip_bfloat16> {
         return __bfloat162float(p[i]) * inv_scale;
     }
     __device__ static float cvt(__hip_bfloat16 v, float inv_scale) { return __bfloat162float(v) * inv_scale; }
+    __device__ static float roundtrip(float v, float scale, float inv_scale)
+    {
+        return __bfloat162float(__float2bfloat16(v * scale)) * inv_scale;
+    }
     __device__ static void store(__hip_bfloat16 *p, size_t i, float v, float scale)
     {
         p[i] = __float2bfloat16(v * scale);

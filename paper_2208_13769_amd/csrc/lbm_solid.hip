@@ -59,6 +59,7 @@ struct lbm_solver {
     double f_scale = 1.0;
     int64_t steps = 0;
     Shape shape{};
+    int spl = 1;  // time steps per launch (1, or 2 with the predictor-corrector)
     std::string err;
 
     void *fptr(int c) const { return ws + L.state.f[c]; }
@@ -118,21 +119,39 @@ lbm_status hip_fail(lbm_solver *h, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
     } while (0)
 
+int resident_blocks(const lbm_solver *h, int block, int spl)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const bool pc = h->scheme == LBM_SCHEME_PC;
+    const bool walled = h->bc[LBM_EDGE_YMIN] != LBM_BC_PERIODIC;
+    int per_cu = 0;
+    switch (h->prec) {
+    case LBM_FP64: per_cu = Kernels<PrecF64>::resident_per_cu(block, spl, pc, walled); break;
+    case LBM_FP32: per_cu = Kernels<PrecF32>::resident_per_cu(block, spl, pc, walled); break;
+    case LBM_FP16_STORE: per_cu = Kernels<PrecF16>::resident_per_cu(block, spl, pc, walled); break;
+    default: per_cu = Kernels<PrecBF16>::resident_per_cu(block, spl, pc, walled); break;
+    }
+    return per_cu * cus;
+}
+
 void plan_launch(lbm_solver *h)
 {
-    const int halo = h->scheme == LBM_SCHEME_PC ? 5 : 3;
+    const int halo = (h->scheme == LBM_SCHEME_PC ? 5 : 3) * h->spl;
     // narrowest block whose strip covers the width, else 256 threads
     int block = 256;
     if (h->nx <= 64 - 2 * halo)
         block = 64;
     else if (h->nx <= 128 - 2 * halo)
         block = 128;
-    const Shape probe = make_shape(h->nx, h->ny, h->prec, h->scheme, block, 1);
-    // enough blocks to fill 256 CUs a couple of times, segments of >= 16 rows
-    const int target = 1024;
-    int n_segs = (target + probe.n_strips - 1) / probe.n_strips;
+    const Shape probe = make_shape(h->nx, h->ny, h->prec, h->scheme, block, 1, h->spl);
+    // as many segments as fit one wave of resident blocks (the last wave of a
+    // longer grid would run part-empty), each of at least 16 rows
+    const int resident = std::max(resident_blocks(h, block, h->spl), probe.n_strips);
+    int n_segs = resident / probe.n_strips;
     n_segs = std::max(1, std::min(n_segs, h->ny / 16));
-    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs);
+    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs, h->spl);
 }
 
 }  // namespace
@@ -236,7 +255,38 @@ lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs)
         return fail(h, LBM_ERR_ARG, "block must be 64, 128, 256 or 512");
     if (n_segs < 1 || n_segs > h->ny) return fail(h, LBM_ERR_ARG, "n_segs must be in [1, ny]");
     if ((long long)h->nx * n_segs > (1LL << 30)) return fail(h, LBM_ERR_ARG, "too many blocks");
-    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs);
+    if (h->spl == 2 && block > 256) return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch need block <= 256");
+    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs, h->spl);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_steps_per_launch(lbm_solver *h, int k)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (k != 1 && k != 2) return fail(h, LBM_ERR_ARG, "steps per launch must be 1 or 2");
+    if (k == 2 && h->scheme != LBM_SCHEME_PC)
+        return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch need the predictor-corrector scheme");
+    h->spl = k;
+    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, k == 2 ? std::min(h->shape.block, 256) : h->shape.block,
+                          h->shape.n_segs, k);
+    return LBM_OK;
+}
+
+lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_launch, int *blocks)
+{
+    if (!h || !blocks) return LBM_ERR_ARG;
+    *blocks = 0;
+    if (block != 64 && block != 128 && block != 256 && block != 512) return LBM_OK;
+    if (steps_per_launch != 1 && steps_per_launch != 2) return LBM_OK;
+    if (steps_per_launch == 2 && (h->scheme != LBM_SCHEME_PC || block > 256)) return LBM_OK;
+    *blocks = resident_blocks(h, block, steps_per_launch);
+    return LBM_OK;
+}
+
+lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k)
+{
+    if (!h || !k) return LBM_ERR_ARG;
+    *k = h->spl;
     return LBM_OK;
 }
 
@@ -295,7 +345,22 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
     sp.flag = h->flag();
     const int nblocks = h->shape.n_strips * h->shape.n_segs;
     const bool pc = h->scheme == LBM_SCHEME_PC;
-    for (int64_t k = 0; k < nsteps; ++k) {
+    int64_t k = 0;
+    if (h->spl == 2) {
+        for (; k + 2 <= nsteps; k += 2) {
+            sp.f_in = h->fptr(h->cur);
+            sp.u_in = h->uptr(h->cur);
+            sp.j_in = h->jptr(h->cur);
+            sp.f_out = h->fptr(h->cur ^ 1);
+            sp.u_out = h->uptr(h->cur ^ 1);
+            sp.j_out = h->jptr(h->cur ^ 1);
+            sp.step = h->steps;
+            HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step2(sp, h->shape.block, nblocks, h->stream)));
+            h->cur ^= 1;
+            h->steps += 2;
+        }
+    }
+    for (; k < nsteps; ++k) {
         sp.f_in = h->fptr(h->cur);
         sp.u_in = h->uptr(h->cur);
         sp.j_in = h->jptr(h->cur);

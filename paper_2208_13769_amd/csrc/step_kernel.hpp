@@ -137,94 +137,103 @@ __device__ __forceinline__ void wall_populations(bool top, int kind, const TC fc
     }
 }
 
-// One tile (column strip `strip`, row segment `seg`) of one plate for one
-// time step. Called by every thread of a block; ends with a barrier.
+// LDS of one pipeline (one time step in flight): double-buffered rows of the
+// values whose x-neighbours are needed, and the wall populations.
+template <class TU, class TC, int BLOCK, bool PC, bool WALLED>
+struct PipeLds {
+    TU u[2][2][BLOCK];
+    TC k[2][2][BLOCK];
+    TC f[2][6][BLOCK];
+    TU up[PC ? 2 : 1][2][BLOCK];
+    TC kp[PC ? 2 : 1][2][BLOCK];
+    TC wall[WALLED ? 2 : 1][3][BLOCK];
+};
+
+// The y-march pipeline of one time step (state n -> n+1) for one column per
+// thread. `def` runs stages D, E, F (they use only rows of earlier
+// iterations) and hands out f_{n+1} at row R-4 and (PC) u_{n+1}, j_{n+1} at
+// row R-6; `abc` takes u_n at row R and f_n, j_n at row R-2 and runs stages
+// A, B, C. Register rings: index k holds row (current stage row) - k.
 template <class PR, int BLOCK, bool PC, bool WALLED>
-__device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg)
-{
+struct Pipe {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
     using TJ = typename PR::TJ;
     using TC = typename PR::TC;
-    using FS = FStore<TF>;
-    constexpr int HX = PC ? 5 : 3;
-    constexpr int NU = PC ? 6 : 4;   // rows of u_n kept: R .. R-NU+1
-    constexpr int NJ = PC ? 4 : 2;   // rows of j_n kept: R-2 .. R-NJ-1
+    using Lds = PipeLds<TU, TC, BLOCK, PC, WALLED>;
+    static constexpr int NU = PC ? 6 : 4;  // rows of u_n kept
+    static constexpr int NJ = PC ? 4 : 2;  // rows of j_n kept
 
-    __shared__ TU s_u[2][2][BLOCK];
-    __shared__ TC s_k[2][2][BLOCK];
-    __shared__ TC s_f[2][6][BLOCK];
-    __shared__ TU s_up[PC ? 2 : 1][2][BLOCK];
-    __shared__ TC s_kp[PC ? 2 : 1][2][BLOCK];
-    __shared__ TC s_wall[WALLED ? 2 : 1][3][BLOCK];
+    Lds &L;
+    const int t, tl, tr, ny, y0, y1;
+    const bool out_col;
+    const int bc_lo, bc_hi;
+    const TC omega, lam, mu, bx, by;
+    const double *val_lo, *val_hi;
+    TU uw_lo_n[2], uw_hi_n[2], uw_lo_p[2], uw_hi_p[2];
 
-    const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
-    TF *__restrict__ fout = static_cast<TF *>(p.f_out);
-    const TU *__restrict__ uin = static_cast<const TU *>(p.u_in);
-    TU *__restrict__ uout = static_cast<TU *>(p.u_out);
-    const TJ *__restrict__ jin = static_cast<const TJ *>(p.j_in);
-    TJ *__restrict__ jout = static_cast<TJ *>(p.j_out);
+    TU uR[NU][2];
+    TC kA2[3][2];
+    TC sN[2][2];
+    TC jN[NJ][2];
+    TC hxCur[2], hxPrev[2];
+    TC o0[2], o2[3], o4;
+    TC n1, n3, n5[2], n6[2];
+    TC jfR[3][2];
+    TU upR[3][2];
+    TC kpA2[3][2];
+    TC hxpCur[2], hxpPrev[2];
+    bool bad;
 
-    const int t = threadIdx.x;
-    const int tl = t > 0 ? t - 1 : 0;
-    const int tr = t < BLOCK - 1 ? t + 1 : BLOCK - 1;
-    const int nx = p.nx, ny = p.ny;
-    const size_t plane = (size_t)p.plane;
-
-    // Output strips start on multiples of strip_w, which the host keeps a
-    // multiple of the 128-byte line, so row writes cover whole lines; the
-    // threads outside [halo_a, halo_a + strip_w) only feed the halo.
-    const int x0 = strip * p.strip_w;
-    const int xc = x0 - p.halo_a + t;
-    int gx = xc % nx;
-    if (gx < 0) gx += nx;
-    const bool out_col = (t >= p.halo_a) && (t < p.halo_a + p.strip_w) && (xc < nx);
-    const int y0 = (int)((long long)seg * ny / p.n_segs);
-    const int y1 = (int)((long long)(seg + 1) * ny / p.n_segs);
-
-    constexpr bool walled = WALLED;
-    const int bc_lo = p.bc_lo, bc_hi = p.bc_hi;
-    const TC omega = TC(p.omega), lam = TC(p.lam), mu = TC(p.mu);
-    const TC bx = TC(p.bx), by = TC(p.by);
-    const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
-    // wall displacement u_w = j* t (lattice units) at t = n and t = n+1
-    const double tn = (double)p.step;
-    const TU uw_lo_n[2] = {TU(p.val_lo[0] * tn), TU(p.val_lo[1] * tn)};
-    const TU uw_hi_n[2] = {TU(p.val_hi[0] * tn), TU(p.val_hi[1] * tn)};
-    const TU uw_lo_p[2] = {TU(p.val_lo[0] * (tn + 1)), TU(p.val_lo[1] * (tn + 1))};
-    const TU uw_hi_p[2] = {TU(p.val_hi[0] * (tn + 1)), TU(p.val_hi[1] * (tn + 1))};
-
-    auto is_node = [&](int r) { return !walled || (r >= 0 && r < ny); };
-    // row for a load: wrapped (periodic) or clamped into the plate (walls)
-    auto rowc = [&](int r) {
-        if (!walled) {
-            r %= ny;
-            if (r < 0) r += ny;
-            return r;
+    __device__ __forceinline__ Pipe(Lds &lds, const StepParams &p, long long step, int t_, int y0_, int y1_,
+                                    bool out_col_)
+        : L(lds), t(t_), tl(t_ > 0 ? t_ - 1 : 0), tr(t_ < BLOCK - 1 ? t_ + 1 : BLOCK - 1), ny(p.ny), y0(y0_),
+          y1(y1_), out_col(out_col_), bc_lo(p.bc_lo), bc_hi(p.bc_hi), omega(TC(p.omega)), lam(TC(p.lam)),
+          mu(TC(p.mu)), bx(TC(p.bx)), by(TC(p.by)), val_lo(p.val_lo), val_hi(p.val_hi), bad(false)
+    {
+        // wall displacement u_w = j* t (lattice units) at t = n and t = n+1
+        const double tn = (double)step;
+        for (int a = 0; a < 2; ++a) {
+            uw_lo_n[a] = TU(p.val_lo[a] * tn);
+            uw_hi_n[a] = TU(p.val_hi[a] * tn);
+            uw_lo_p[a] = TU(p.val_lo[a] * (tn + 1));
+            uw_hi_p[a] = TU(p.val_hi[a] * (tn + 1));
         }
-        return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
-    };
-    auto rowi = [&](int r) {
-        if (!walled) {
-            r %= ny;
-            if (r < 0) r += ny;
+#pragma unroll
+        for (int k = 0; k < NU; ++k) uR[k][0] = uR[k][1] = TU(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            kA2[k][0] = kA2[k][1] = jfR[k][0] = jfR[k][1] = kpA2[k][0] = kpA2[k][1] = TC(0);
+            upR[k][0] = upR[k][1] = TU(0);
         }
-        return r;
-    };
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) jN[k][0] = jN[k][1] = TC(0);
+        sN[0][0] = sN[0][1] = sN[1][0] = sN[1][1] = TC(0);
+        hxCur[0] = hxCur[1] = hxPrev[0] = hxPrev[1] = TC(0);
+        hxpCur[0] = hxpCur[1] = hxpPrev[0] = hxpPrev[1] = TC(0);
+        o0[0] = o0[1] = o2[0] = o2[1] = o2[2] = o4 = TC(0);
+        n1 = n3 = n5[0] = n5[1] = n6[0] = n6[1] = TC(0);
+    }
+
+    __device__ __forceinline__ bool is_node(int r) const { return !WALLED || (r >= 0 && r < ny); }
+
     // ghost rows above the top wall from the two rows below it
-    auto ghost_hi = [&](int which, TU a, TU b, TU uw) -> TU {
+    __device__ __forceinline__ TU ghost_hi(int which, TU a, TU b, TU uw) const
+    {
         if (bc_hi == BC_NEUMANN) return a;
         return which == 0 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
-    };
+    }
     // first ghost row below the bottom wall from rows 0 and 1
-    auto ghost_lo = [&](TU a, TU b, TU uw) -> TU {
+    __device__ __forceinline__ TU ghost_lo(TU a, TU b, TU uw) const
+    {
         if (bc_lo == BC_NEUMANN) return a;
         return TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3);
-    };
+    }
     // stress sum in the ghost row below the bottom wall, from rows 0 and 1:
     // own values u0, u1 and x-derivatives hx0, hx1 (du_x/dx, du_y/dx)
-    auto ghost_lo_K = [&](const TU u0[2], const TU u1[2], const TC hx0[2], const TC hx1[2], const TU uw[2],
-                          TC &k12, TC &k22) {
+    __device__ __forceinline__ void ghost_lo_K(const TU u0[2], const TU u1[2], const TC hx0[2], const TC hx1[2],
+                                               const TU uw[2], TC &k12, TC &k22) const
+    {
         TC H[4], K[4];
         if (bc_lo == BC_NEUMANN) {
             H[0] = hx0[0];
@@ -240,63 +249,19 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         stress_sum(H, lam, mu, K);
         k12 = K[1];
         k22 = K[3];
-    };
-
-    // register rings: index k holds row (current stage row) - k
-    TU uR[NU][2];
-    TC kA2[3][2];
-    TC sN[2][2];
-    TC jN[NJ][2];
-    TC hxCur[2] = {0, 0}, hxPrev[2] = {0, 0};
-    TC o0[2] = {0, 0}, o2[3] = {0, 0, 0}, o4 = 0;
-    TC n1 = 0, n3 = 0, n5[2] = {0, 0}, n6[2] = {0, 0};
-    TC jfR[3][2];
-    TU upR[3][2];
-    TC kpA2[3][2];
-    TC hxpCur[2] = {0, 0}, hxpPrev[2] = {0, 0};
-#pragma unroll
-    for (int k = 0; k < NU; ++k) uR[k][0] = uR[k][1] = TU(0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        kA2[k][0] = kA2[k][1] = TC(0);
-        jfR[k][0] = jfR[k][1] = kpA2[k][0] = kpA2[k][1] = TC(0);
-        upR[k][0] = upR[k][1] = TU(0);
     }
-#pragma unroll
-    for (int k = 0; k < NJ; ++k) jN[k][0] = jN[k][1] = TC(0);
-    sN[0][0] = sN[0][1] = sN[1][0] = sN[1][1] = TC(0);
 
-    bool bad = false;
-    const int n_iter = (y1 - y0) + (PC ? 11 : 7);
-    const int Rstart = y0 - HX;
-
-
-    for (int it = 0; it < n_iter; ++it) {
-        const int R = Rstart + it;
-        const int b = it & 1, pb = b ^ 1;
-
-        // Loads of this iteration (u_n at row R for stage A, f_n and j_n at
-        // row R-2 for stage C) are issued first; stages D-F, which only use
-        // earlier rows, run while they are in flight. Rows beyond a wall are
-        // clamped to a valid address and their values discarded.
-        const int rA = R, rC = R - 2;
-        const bool nodeA = is_node(rA), nodeC = is_node(rC);
-        const size_t oA = (size_t)rowc(rA) * nx + gx;
-        const size_t oC = (size_t)rowc(rC) * nx + gx;
-        const TU la0 = uin[oA], la1 = uin[plane + oA];
-        TF lf[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
-        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
-
-        // ---------------- stage D: pull row R-4, moments
-        // (rings not yet advanced this iteration: uR[k] = row R-1-k,
-        //  sN[k] = row R-3-k, jN[k] = row R-3-k)
+    // ---------------- stages D, E, F (rings not yet advanced this
+    // iteration: uR[k] = row R-1-k, sN[k] = row R-3-k, jN[k] = row R-3-k).
+    // fn: f_{n+1} at row R-4. PC: unew, jnew at row R-6 (meaningful when
+    // that row is a node). Explicit: unew, jnew at row R-4.
+    __device__ __forceinline__ void def(const int R, const int b, TC fn[9], TU unew[2], TC jnew[2])
+    {
+        const int pb = b ^ 1;
         const int rD = R - 4;
         {
-            const TC a1 = s_f[pb][0][tl], a3 = s_f[pb][1][tr], a5 = s_f[pb][2][tl];
-            const TC a6 = s_f[pb][3][tr], a7 = s_f[pb][4][tr], a8 = s_f[pb][5][tl];
-            TC fn[9];
+            const TC a1 = L.f[pb][0][tl], a3 = L.f[pb][1][tr], a5 = L.f[pb][2][tl];
+            const TC a6 = L.f[pb][3][tr], a7 = L.f[pb][4][tr], a8 = L.f[pb][5][tl];
             fn[0] = o0[1];
             fn[1] = n1;
             fn[2] = o2[2];
@@ -306,15 +271,15 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             fn[6] = n6[1];
             fn[7] = a7;
             fn[8] = a8;
-            if (walled && rD == 0) {
-                fn[2] = s_wall[0][0][t];
-                fn[5] = s_wall[0][1][t];
-                fn[6] = s_wall[0][2][t];
+            if (WALLED && rD == 0) {
+                fn[2] = L.wall[0][0][t];
+                fn[5] = L.wall[0][1][t];
+                fn[6] = L.wall[0][2][t];
             }
-            if (walled && rD == ny - 1) {
-                fn[4] = s_wall[1][0][t];
-                fn[7] = s_wall[1][1][t];
-                fn[8] = s_wall[1][2][t];
+            if (WALLED && rD == ny - 1) {
+                fn[4] = L.wall[WALLED ? 1 : 0][0][t];
+                fn[7] = L.wall[WALLED ? 1 : 0][1][t];
+                fn[8] = L.wall[WALLED ? 1 : 0][2][t];
             }
             n5[1] = n5[0];
             n5[0] = a5;
@@ -326,11 +291,6 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             const bool nodeD = is_node(rD);
             const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
             const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
-            if (nodeD && out_col && rD >= y0 && rD < y1) {
-                const size_t o = (size_t)rowi(rD) * nx + gx;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn[i], f_scale);
-            }
             if constexpr (PC) {
                 const TC jpx = jfx + TC(0.5) * sN[1][0];
                 const TC jpy = jfy + TC(0.5) * sN[1][1];
@@ -358,24 +318,14 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
                 upR[0][1] = upy;
                 jfR[0][0] = jfx;
                 jfR[0][1] = jfy;
-                s_up[b][0][t] = upx;
-                s_up[b][1][t] = upy;
+                L.up[b][0][t] = upx;
+                L.up[b][1][t] = upy;
             } else {
                 // explicit: the source at t also serves the moment step
-                if (nodeD && out_col && rD >= y0 && rD < y1) {
-                    const TC jx = jfx + TC(0.5) * sN[1][0];
-                    const TC jy = jfy + TC(0.5) * sN[1][1];
-                    const TU ux = uR[3][0] + TU(TC(0.5) * (jx + jN[1][0]));
-                    const TU uy = uR[3][1] + TU(TC(0.5) * (jy + jN[1][1]));
-                    const size_t o = (size_t)rowi(rD) * nx + gx;
-                    uout[o] = ux;
-                    uout[plane + o] = uy;
-                    jout[o] = TJ(jx);
-                    jout[plane + o] = TJ(jy);
-                    if (!isfinite((double)ux) || !isfinite((double)uy) || !isfinite((double)jx) ||
-                        !isfinite((double)jy))
-                        bad = true;
-                }
+                jnew[0] = jfx + TC(0.5) * sN[1][0];
+                jnew[1] = jfy + TC(0.5) * sN[1][1];
+                unew[0] = uR[3][0] + TU(TC(0.5) * (jnew[0] + jN[1][0]));
+                unew[1] = uR[3][1] + TU(TC(0.5) * (jnew[1] + jN[1][1]));
             }
         }
 
@@ -383,18 +333,18 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             // ---------------- stage E: K^p at row R-5
             {
                 TC H[4], K[4];
-                H[0] = TC((s_up[pb][0][tr] - s_up[pb][0][tl]) * TU(0.5));
-                H[2] = TC((s_up[pb][1][tr] - s_up[pb][1][tl]) * TU(0.5));
+                H[0] = TC((L.up[pb][0][tr] - L.up[pb][0][tl]) * TU(0.5));
+                H[2] = TC((L.up[pb][1][tr] - L.up[pb][1][tl]) * TU(0.5));
                 TU um0 = upR[2][0], um1 = upR[2][1];
-                if (walled && R - 5 == 0) {
+                if (WALLED && R - 5 == 0) {
                     um0 = ghost_lo(upR[1][0], upR[0][0], uw_lo_p[0]);
                     um1 = ghost_lo(upR[1][1], upR[0][1], uw_lo_p[1]);
                 }
                 H[1] = TC((upR[0][0] - um0) * TU(0.5));
                 H[3] = TC((upR[0][1] - um1) * TU(0.5));
                 stress_sum(H, lam, mu, K);
-                s_kp[b][0][t] = K[0];
-                s_kp[b][1][t] = K[2];
+                L.kp[b][0][t] = K[0];
+                L.kp[b][1][t] = K[2];
 #pragma unroll
                 for (int k = 2; k > 0; --k) {
                     kpA2[k][0] = kpA2[k - 1][0];
@@ -409,34 +359,36 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             }
             // ---------------- stage F: S^p at row R-6, new j and u
             const int rF = R - 6;
-            if (is_node(rF) && out_col && rF >= y0 && rF < y1) {
+            if (is_node(rF)) {
                 TC k12d = kpA2[2][0], k22d = kpA2[2][1];
-                if (walled && rF == 0) ghost_lo_K(upR[2], upR[1], hxpPrev, hxpCur, uw_lo_p, k12d, k22d);
-                const TC Sx = bx + TC(0.5) * (s_kp[pb][0][tr] - s_kp[pb][0][tl]) + TC(0.5) * (kpA2[0][0] - k12d);
-                const TC Sy = by + TC(0.5) * (s_kp[pb][1][tr] - s_kp[pb][1][tl]) + TC(0.5) * (kpA2[0][1] - k22d);
-                const TC jx = jfR[2][0] + TC(0.5) * Sx;
-                const TC jy = jfR[2][1] + TC(0.5) * Sy;
-                const TU ux = uR[5][0] + TU(TC(0.5) * (jx + jN[3][0]));
-                const TU uy = uR[5][1] + TU(TC(0.5) * (jy + jN[3][1]));
-                const size_t o = (size_t)rowi(rF) * nx + gx;
-                uout[o] = ux;
-                uout[plane + o] = uy;
-                jout[o] = TJ(jx);
-                jout[plane + o] = TJ(jy);
-                if (!isfinite((double)ux) || !isfinite((double)uy) || !isfinite((double)jx) || !isfinite((double)jy))
-                    bad = true;
+                if (WALLED && rF == 0) ghost_lo_K(upR[2], upR[1], hxpPrev, hxpCur, uw_lo_p, k12d, k22d);
+                const TC Sx = bx + TC(0.5) * (L.kp[pb][0][tr] - L.kp[pb][0][tl]) + TC(0.5) * (kpA2[0][0] - k12d);
+                const TC Sy = by + TC(0.5) * (L.kp[pb][1][tr] - L.kp[pb][1][tl]) + TC(0.5) * (kpA2[0][1] - k22d);
+                jnew[0] = jfR[2][0] + TC(0.5) * Sx;
+                jnew[1] = jfR[2][1] + TC(0.5) * Sy;
+                unew[0] = uR[5 < NU ? 5 : 0][0] + TU(TC(0.5) * (jnew[0] + jN[3 < NJ ? 3 : 0][0]));
+                unew[1] = uR[5 < NU ? 5 : 0][1] + TU(TC(0.5) * (jnew[1] + jN[3 < NJ ? 3 : 0][1]));
+            } else {
+                jnew[0] = jnew[1] = TC(0);
+                unew[0] = unew[1] = TU(0);
             }
         }
+    }
 
-        // ---------------- stage A: u_n at row R
+    // ---------------- stages A, B, C with this iteration's inputs
+    __device__ __forceinline__ void abc(const int R, const int b, const bool nodeA, const TU ua0, const TU ua1,
+                                        const bool nodeC, const TC f[9], const TC jx, const TC jy)
+    {
+        const int pb = b ^ 1;
+        // stage A: u_n at row R
 #pragma unroll
         for (int k = NU - 1; k > 0; --k) {
             uR[k][0] = uR[k - 1][0];
             uR[k][1] = uR[k - 1][1];
         }
         if (nodeA) {
-            uR[0][0] = la0;
-            uR[0][1] = la1;
+            uR[0][0] = ua0;
+            uR[0][1] = ua1;
         } else if (R == ny && bc_hi != BC_PERIODIC) {
             uR[0][0] = ghost_hi(0, uR[1][0], uR[2][0], uw_hi_n[0]);
             uR[0][1] = ghost_hi(0, uR[1][1], uR[2][1], uw_hi_n[1]);
@@ -446,17 +398,17 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         } else {
             uR[0][0] = uR[0][1] = TU(0);
         }
-        s_u[b][0][t] = uR[0][0];
-        s_u[b][1][t] = uR[0][1];
+        L.u[b][0][t] = uR[0][0];
+        L.u[b][1][t] = uR[0][1];
 
-        // ---------------- stage B: K at row R-1
+        // stage B: K at row R-1
         {
             TC H[4], K[4];
-            H[0] = TC((s_u[pb][0][tr] - s_u[pb][0][tl]) * TU(0.5));
-            H[2] = TC((s_u[pb][1][tr] - s_u[pb][1][tl]) * TU(0.5));
+            H[0] = TC((L.u[pb][0][tr] - L.u[pb][0][tl]) * TU(0.5));
+            H[2] = TC((L.u[pb][1][tr] - L.u[pb][1][tl]) * TU(0.5));
             const int rB = R - 1;
             TU um0 = uR[2][0], um1 = uR[2][1];
-            if (walled && rB == 0) {
+            if (WALLED && rB == 0) {
                 um0 = ghost_lo(uR[1][0], uR[0][0], uw_lo_n[0]);
                 um1 = ghost_lo(uR[1][1], uR[0][1], uw_lo_n[1]);
             }
@@ -464,8 +416,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             H[3] = TC((uR[0][1] - um1) * TU(0.5));
             const TC J = stress_sum(H, lam, mu, K);
             if (out_col && rB >= y0 && rB < y1 && !(J > TC(0))) bad = true;
-            s_k[b][0][t] = K[0];
-            s_k[b][1][t] = K[2];
+            L.k[b][0][t] = K[0];
+            L.k[b][1][t] = K[2];
 #pragma unroll
             for (int k = 2; k > 0; --k) {
                 kA2[k][0] = kA2[k - 1][0];
@@ -479,67 +431,278 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
             hxCur[1] = H[2];
         }
 
-        // ---------------- stage C: S_n at row R-2, collision
-        {
-            TC fc[9];
-            TC k12d = kA2[2][0], k22d = kA2[2][1];
-            if (walled && rC == 0) ghost_lo_K(uR[2], uR[1], hxPrev, hxCur, uw_lo_n, k12d, k22d);
-            const TC Sx = bx + TC(0.5) * (s_k[pb][0][tr] - s_k[pb][0][tl]) + TC(0.5) * (kA2[0][0] - k12d);
-            const TC Sy = by + TC(0.5) * (s_k[pb][1][tr] - s_k[pb][1][tl]) + TC(0.5) * (kA2[0][1] - k22d);
-            sN[1][0] = sN[0][0];
-            sN[1][1] = sN[0][1];
-            sN[0][0] = Sx;
-            sN[0][1] = Sy;
+        // stage C: S_n at row R-2, collision
+        const int rC = R - 2;
+        TC fc[9];
+        TC k12d = kA2[2][0], k22d = kA2[2][1];
+        if (WALLED && rC == 0) ghost_lo_K(uR[2], uR[1], hxPrev, hxCur, uw_lo_n, k12d, k22d);
+        const TC Sx = bx + TC(0.5) * (L.k[pb][0][tr] - L.k[pb][0][tl]) + TC(0.5) * (kA2[0][0] - k12d);
+        const TC Sy = by + TC(0.5) * (L.k[pb][1][tr] - L.k[pb][1][tl]) + TC(0.5) * (kA2[0][1] - k22d);
+        sN[1][0] = sN[0][0];
+        sN[1][1] = sN[0][1];
+        sN[0][0] = Sx;
+        sN[0][1] = Sy;
 #pragma unroll
-            for (int k = NJ - 1; k > 0; --k) {
-                jN[k][0] = jN[k - 1][0];
-                jN[k][1] = jN[k - 1][1];
-            }
-            if (nodeC) {
-                TC f[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
-                const TC jx = TC(lj0), jy = TC(lj1);
-                jN[0][0] = jx;
-                jN[0][1] = jy;
-                TC r, pxx;
-                collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
-                if (walled && rC == 0) {
-                    TC w[3];
-                    wall_populations(false, bc_lo, fc, p.val_lo, r, pxx, kA2[1][0], kA2[1][1], w);
-                    s_wall[0][0][t] = w[0];
-                    s_wall[0][1][t] = w[1];
-                    s_wall[0][2][t] = w[2];
-                }
-                if (walled && rC == ny - 1) {
-                    TC w[3];
-                    wall_populations(true, bc_hi, fc, p.val_hi, r, pxx, kA2[1][0], kA2[1][1], w);
-                    s_wall[1][0][t] = w[0];
-                    s_wall[1][1][t] = w[1];
-                    s_wall[1][2][t] = w[2];
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) fc[i] = TC(0);
-                jN[0][0] = jN[0][1] = TC(0);
-            }
-            s_f[b][0][t] = fc[1];
-            s_f[b][1][t] = fc[3];
-            s_f[b][2][t] = fc[5];
-            s_f[b][3][t] = fc[6];
-            s_f[b][4][t] = fc[7];
-            s_f[b][5][t] = fc[8];
-            // own-column collision rings of the pull
-            o2[2] = o2[1];
-            o2[1] = o2[0];
-            o2[0] = fc[2];
-            o0[1] = o0[0];
-            o0[0] = fc[0];
-            o4 = fc[4];
+        for (int k = NJ - 1; k > 0; --k) {
+            jN[k][0] = jN[k - 1][0];
+            jN[k][1] = jN[k - 1][1];
         }
+        if (nodeC) {
+            jN[0][0] = jx;
+            jN[0][1] = jy;
+            TC r, pxx;
+            collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
+            if (WALLED && rC == 0) {
+                TC w[3];
+                wall_populations(false, bc_lo, fc, val_lo, r, pxx, kA2[1][0], kA2[1][1], w);
+                L.wall[0][0][t] = w[0];
+                L.wall[0][1][t] = w[1];
+                L.wall[0][2][t] = w[2];
+            }
+            if (WALLED && rC == ny - 1) {
+                TC w[3];
+                wall_populations(true, bc_hi, fc, val_hi, r, pxx, kA2[1][0], kA2[1][1], w);
+                L.wall[WALLED ? 1 : 0][0][t] = w[0];
+                L.wall[WALLED ? 1 : 0][1][t] = w[1];
+                L.wall[WALLED ? 1 : 0][2][t] = w[2];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fc[i] = TC(0);
+            jN[0][0] = jN[0][1] = TC(0);
+        }
+        L.f[b][0][t] = fc[1];
+        L.f[b][1][t] = fc[3];
+        L.f[b][2][t] = fc[5];
+        L.f[b][3][t] = fc[6];
+        L.f[b][4][t] = fc[7];
+        L.f[b][5][t] = fc[8];
+        // own-column collision rings of the pull
+        o2[2] = o2[1];
+        o2[1] = o2[0];
+        o2[0] = fc[2];
+        o0[1] = o0[0];
+        o0[0] = fc[0];
+        o4 = fc[4];
+    }
+};
+
+// Column/row geometry of one tile. Output strips start on multiples of
+// strip_w, which the host keeps a multiple of the 128-byte line, so row
+// writes cover whole lines; the threads outside [halo_a, halo_a + strip_w)
+// only feed the halo.
+struct TileGeom {
+    int gx, y0, y1;
+    bool out_col;
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const StepParams &p, int strip, int seg)
+{
+    TileGeom g;
+    const int t = threadIdx.x;
+    const int x0 = strip * p.strip_w;
+    const int xc = x0 - p.halo_a + t;
+    g.gx = xc % p.nx;
+    if (g.gx < 0) g.gx += p.nx;
+    g.out_col = (t >= p.halo_a) && (t < p.halo_a + p.strip_w) && (xc < p.nx);
+    g.y0 = (int)((long long)seg * p.ny / p.n_segs);
+    g.y1 = (int)((long long)(seg + 1) * p.ny / p.n_segs);
+    return g;
+}
+
+// row of a load: wrapped (periodic) or clamped into the plate (walls)
+template <bool WALLED>
+__device__ __forceinline__ int row_load(int r, int ny)
+{
+    if (!WALLED) {
+        r %= ny;
+        return r < 0 ? r + ny : r;
+    }
+    return r < 0 ? 0 : (r >= ny ? ny - 1 : r);
+}
+
+// row of a store (the caller has checked that r is a node)
+template <bool WALLED>
+__device__ __forceinline__ int row_store(int r, int ny)
+{
+    if (!WALLED) {
+        r %= ny;
+        return r < 0 ? r + ny : r;
+    }
+    return r;
+}
+
+// One tile (column strip `strip`, row segment `seg`) of one plate for one
+// time step. Called by every thread of a block; ends with a barrier.
+template <class PR, int BLOCK, bool PC, bool WALLED>
+__device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    using P = Pipe<PR, BLOCK, PC, WALLED>;
+    constexpr int HX = PC ? 5 : 3;
+    __shared__ typename P::Lds lds;
+
+    const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
+    TF *__restrict__ fout = static_cast<TF *>(p.f_out);
+    const TU *__restrict__ uin = static_cast<const TU *>(p.u_in);
+    TU *__restrict__ uout = static_cast<TU *>(p.u_out);
+    const TJ *__restrict__ jin = static_cast<const TJ *>(p.j_in);
+    TJ *__restrict__ jout = static_cast<TJ *>(p.j_out);
+    const int nx = p.nx, ny = p.ny;
+    const size_t plane = (size_t)p.plane;
+    const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
+    const TileGeom g = tile_geom(p, strip, seg);
+    P pipe(lds, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
+
+    const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7);
+    const int Rstart = g.y0 - HX;
+    for (int it = 0; it < n_iter; ++it) {
+        const int R = Rstart + it;
+        const int b = it & 1;
+        // Loads of this iteration (u_n at row R, f_n and j_n at row R-2) are
+        // issued first; stages D-F, which only use earlier rows, run while
+        // they are in flight. Rows beyond a wall are clamped to a valid
+        // address and their values discarded.
+        const size_t oA = (size_t)row_load<WALLED>(R, ny) * nx + g.gx;
+        const size_t oC = (size_t)row_load<WALLED>(R - 2, ny) * nx + g.gx;
+        const TU la0 = uin[oA], la1 = uin[plane + oA];
+        TF lf[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
+        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
+
+        TC fn[9], jnew[2];
+        TU unew[2];
+        pipe.def(R, b, fn, unew, jnew);
+        const int rD = R - 4, rF = PC ? R - 6 : R - 4;
+        if (pipe.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
+            const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn[i], f_scale);
+        }
+        if (pipe.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
+            const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
+            uout[o] = unew[0];
+            uout[plane + o] = unew[1];
+            jout[o] = TJ(jnew[0]);
+            jout[plane + o] = TJ(jnew[1]);
+            if (!isfinite((double)unew[0]) || !isfinite((double)unew[1]) || !isfinite((double)jnew[0]) ||
+                !isfinite((double)jnew[1]))
+                pipe.bad = true;
+        }
+
+        TC f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
+        pipe.abc(R, b, pipe.is_node(R), la0, la1, pipe.is_node(R - 2), f, TC(lj0), TC(lj1));
         __syncthreads();
     }
-    if (bad) p.flag[0] = 1u;
+    if (pipe.bad) p.flag[0] = 1u;
+}
+
+// Two time steps of one tile in one pass (predictor-corrector only): a second
+// pipeline takes the first one's outputs six rows behind it -- u_{n+1} at
+// its row R2 = R - 6 as it is produced, f_{n+1} and j_{n+1} at row R2 - 2
+// from short delay rings -- so the state is read and written once per two
+// steps. Needs a halo of 10 columns and 10 rows; the halo work of the first
+// step is recomputed, never exchanged. The values handed over pass through
+// the storage precision, so the result equals two single steps bitwise.
+template <class PR, int BLOCK, bool WALLED>
+__device__ __forceinline__ void step2_tile(const StepParams &p, const int strip, const int seg)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    using P = Pipe<PR, BLOCK, true, WALLED>;
+    __shared__ typename P::Lds lds1, lds2;
+
+    const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
+    TF *__restrict__ fout = static_cast<TF *>(p.f_out);
+    const TU *__restrict__ uin = static_cast<const TU *>(p.u_in);
+    TU *__restrict__ uout = static_cast<TU *>(p.u_out);
+    const TJ *__restrict__ jin = static_cast<const TJ *>(p.j_in);
+    TJ *__restrict__ jout = static_cast<TJ *>(p.j_out);
+    const int nx = p.nx, ny = p.ny;
+    const size_t plane = (size_t)p.plane;
+    const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
+    const TileGeom g = tile_geom(p, strip, seg);
+    P p1(lds1, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
+    P p2(lds2, p, p.step + 1, (int)threadIdx.x, g.y0, g.y1, g.out_col);
+
+    // f_{n+1} of rows R-4 .. R-7 and j_{n+1} of rows R-6, R-7 (after the shift)
+    TC fd[4][9], jd[2][2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fd[k][i] = TC(0);
+    jd[0][0] = jd[0][1] = jd[1][0] = jd[1][1] = TC(0);
+
+    const int n_iter = (g.y1 - g.y0) + 22;
+    const int Rstart = g.y0 - 10;
+    for (int it = 0; it < n_iter; ++it) {
+        const int R = Rstart + it;
+        const int b = it & 1;
+        const size_t oA = (size_t)row_load<WALLED>(R, ny) * nx + g.gx;
+        const size_t oC = (size_t)row_load<WALLED>(R - 2, ny) * nx + g.gx;
+        const TU la0 = uin[oA], la1 = uin[plane + oA];
+        TF lf[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
+        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
+
+        // first step: f_{n+1} at row R-4, u_{n+1} and j_{n+1} at row R-6
+        TC fn1[9], j1[2];
+        TU u1[2];
+        p1.def(R, b, fn1, u1, j1);
+
+        // second step at row R2 = R - 6
+        const int R2 = R - 6;
+        TC fn2[9], j2[2];
+        TU u2[2];
+        p2.def(R2, b, fn2, u2, j2);
+        const int rD = R2 - 4, rF = R2 - 6;
+        if (p2.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
+            const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn2[i], f_scale);
+        }
+        if (p2.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
+            const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
+            uout[o] = u2[0];
+            uout[plane + o] = u2[1];
+            jout[o] = TJ(j2[0]);
+            jout[plane + o] = TJ(j2[1]);
+            if (!isfinite((double)u2[0]) || !isfinite((double)u2[1]) || !isfinite((double)j2[0]) ||
+                !isfinite((double)j2[1]))
+                p2.bad = true;
+        }
+        // inputs of the second step: u_{n+1}(R2) now, f and j_{n+1}(R2 - 2) delayed
+        p2.abc(R2, b, p2.is_node(R2), u1[0], u1[1], p2.is_node(R2 - 2), fd[3], jd[1][0], jd[1][1]);
+#pragma unroll
+        for (int k = 3; k > 0; --k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fd[k][i] = fd[k - 1][i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fd[0][i] = FS::roundtrip(fn1[i], f_scale, f_inv);
+        jd[1][0] = jd[0][0];
+        jd[1][1] = jd[0][1];
+        jd[0][0] = TC(TJ(j1[0]));
+        jd[0][1] = TC(TJ(j1[1]));
+
+        // first step's own inputs
+        TC f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
+        p1.abc(R, b, p1.is_node(R), la0, la1, p1.is_node(R - 2), f, TC(lj0), TC(lj1));
+        __syncthreads();
+    }
+    if (p1.bad || p2.bad) p.flag[0] = 1u;
 }
 
 // Single-plate step: one block per tile. Blocks are dealt round-robin to the
@@ -556,6 +719,20 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int strip = logical / p.n_segs;
     const int seg = logical - strip * p.n_segs;
     step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg);
+}
+
+// Two steps per launch, one block per tile (same tile order as step_kernel).
+template <class PR, int BLOCK, bool WALLED>
+__global__ void __launch_bounds__(BLOCK) step2_kernel(const StepParams p)
+{
+    const int nb = p.n_strips * p.n_segs;
+    const int bid = blockIdx.x;
+    const int xq = nb >> 3, xr = nb & 7;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int logical = xcd * xq + min(xcd, xr) + loc;
+    const int strip = logical / p.n_segs;
+    const int seg = logical - strip * p.n_segs;
+    step2_tile<PR, BLOCK, WALLED>(p, strip, seg);
 }
 
 }  // namespace lbm

@@ -16,9 +16,9 @@ Workloads (all units physical, dX = rho0 = 1 unless stated):
 * ``plate_batch``: plates for a batched run -- side N = round(64 * 16**U),
   U ~ U[0, 1) (log-uniform over 64..1024), lam ~ U[0.05, 0.2],
   mu ~ U[0.02, 0.1], all from one seeded PCG64 stream.
-* ``top_pulse``: a downward velocity pulse at the top edge of a plate,
-  v_y = -amp exp(-(d / w)^2) (1 - cos(2 pi x / N)) / 2 with d the distance in
-  cells from the top node row and w = max(2, N / 32).
+* ``top_pulse``: a downward velocity pulse at the top edge of a plate of N
+  rows and Nx columns, v_y = -amp exp(-(d / w)^2) (1 - cos(2 pi x / Nx)) / 2
+  with d the distance in cells from the top node row and w = max(2, N / 32).
 """
 from __future__ import annotations
 
@@ -83,13 +83,15 @@ def plate_batch(count: int, seed: int, n_min: int = 64, n_max: int = 1024):
     return plates
 
 
-def top_pulse(n: int, amp: float):
-    x = np.arange(n, dtype=np.float64)
+def top_pulse(n: int, amp: float, nx: int | None = None):
+    """Plate of n rows (and nx columns, default n) with the pulse at its top."""
+    nx = n if nx is None else nx
+    x = np.arange(nx, dtype=np.float64)
     y = np.arange(n, dtype=np.float64)
     d = (n - 1) - y
     w = max(2.0, n / 32.0)
-    prof = np.exp(-(d / w) ** 2)[:, None] * (0.5 * (1.0 - np.cos(2.0 * np.pi * x / n)))[None, :]
-    u0 = np.zeros((2, n, n))
-    v0 = np.zeros((2, n, n))
+    prof = np.exp(-(d / w) ** 2)[:, None] * (0.5 * (1.0 - np.cos(2.0 * np.pi * x / nx)))[None, :]
+    u0 = np.zeros((2, n, nx))
+    v0 = np.zeros((2, n, nx))
     v0[1] = -amp * prof
     return u0, v0

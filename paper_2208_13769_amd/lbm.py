@@ -32,7 +32,8 @@ EXPORTED_EXTRA: list = []
 EXPORTED = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_material", "lbm_set_body_force", "lbm_set_boundary",
     "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
-    "lbm_set_tiling", "lbm_get_tiling",
+    "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
+    "lbm_resident_blocks",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
     "lbm_batch_destroy", "lbm_batch_last_error",
@@ -96,6 +97,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_set_tiling.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.lbm_get_tiling.restype = ctypes.c_int
     lib.lbm_get_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.lbm_set_steps_per_launch.restype = ctypes.c_int
+    lib.lbm_set_steps_per_launch.argtypes = [vp, ctypes.c_int]
+    lib.lbm_get_steps_per_launch.restype = ctypes.c_int
+    lib.lbm_get_steps_per_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.lbm_resident_blocks.restype = ctypes.c_int
+    lib.lbm_resident_blocks.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_last_error.argtypes = [vp]
     _lib = lib
@@ -177,6 +184,22 @@ def lbm_get_tiling(h):
     return b.value, n.value
 
 
+def lbm_set_steps_per_launch(h, k: int):
+    _check(load_library().lbm_set_steps_per_launch(h, int(k)), h)
+
+
+def lbm_resident_blocks(h, block: int, steps_per_launch: int) -> int:
+    out = ctypes.c_int()
+    _check(load_library().lbm_resident_blocks(h, int(block), int(steps_per_launch), ctypes.byref(out)), h)
+    return out.value
+
+
+def lbm_get_steps_per_launch(h) -> int:
+    out = ctypes.c_int()
+    _check(load_library().lbm_get_steps_per_launch(h, ctypes.byref(out)), h)
+    return out.value
+
+
 def lbm_destroy(h):
     load_library().lbm_destroy(h)
 
@@ -249,6 +272,15 @@ class Solver:
 
     def tiling(self):
         return lbm_get_tiling(self.h)
+
+    def set_steps_per_launch(self, k: int):
+        lbm_set_steps_per_launch(self.h, k)
+
+    def steps_per_launch(self) -> int:
+        return lbm_get_steps_per_launch(self.h)
+
+    def resident_blocks(self, block: int, steps_per_launch: int) -> int:
+        return lbm_resident_blocks(self.h, block, steps_per_launch)
 
     @property
     def dt(self) -> float:

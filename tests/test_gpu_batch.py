@@ -11,8 +11,7 @@ pytestmark = pytest.mark.gpu
 
 def _plate_inputs(n, ny, seed, walled):
     if walled:
-        u0, v0 = inputs.top_pulse(max(n, ny), 0.01)
-        u0, v0 = u0[:, :ny, :n].copy(), v0[:, :ny, :n].copy()
+        u0, v0 = inputs.top_pulse(ny, 0.01, nx=n)
         v0 = v0 + inputs.filtered_random_velocity(n, ny, 2.0, seed, 0.002)[1]
     else:
         u0, v0 = inputs.filtered_random_velocity(n, ny, 3.0, seed, 0.03)

@@ -149,3 +149,62 @@ def test_16bit_storage_short_run(gpu, precision, tol):
     """16-bit population storage against the FP64 oracle, 200 steps of the
     config-1 wave (errors per dtype are reported by the benchmark suite)."""
     _compare(config1_case(), 200, tol, tol, precision=precision)
+
+
+@pytest.mark.parametrize("precision,walled", [("fp32", False), ("fp32", True), ("fp16", False), ("fp16", True),
+                                              ("fp64", False)])
+def test_two_steps_per_launch_bitwise(gpu, precision, walled):
+    """Two fused steps per launch give the single-step results bitwise, for an
+    odd step count (the remainder runs as one step) and several tilings."""
+    from paper_2208_13769_amd import lbm
+
+    nx, ny = 300, 90
+    if walled:
+        u0, v0 = inputs.top_pulse(ny, 0.01, nx=nx)
+        v0 = v0 + inputs.filtered_random_velocity(nx, ny, 2.0, 22, 0.002)[1]
+    else:
+        u0, v0, _, _ = random_case(nx, ny, 21, 0.05)
+    outs = []
+    for spl, block, segs in [(1, 256, 5), (2, 256, 5), (2, 128, 3), (2, 64, 7), (2, 256, 1)]:
+        s = lbm.Solver(nx, ny, 1.0, precision, "pc")
+        s.set_material(1.0, 0.1, 0.05, 0.8)
+        if walled:
+            s.set_boundary(lbm.LBM_EDGE_YMIN, lbm.LBM_BC_DIRICHLET_J, (0.0, 0.0))
+            s.set_boundary(lbm.LBM_EDGE_YMAX, lbm.LBM_BC_NEUMANN_T, (0.0, 0.001))
+        s.set_steps_per_launch(spl)
+        s.set_tiling(block, segs)
+        s.set_fields(u0, v0)
+        s.step(31)
+        u, v, P, d, st = s.read()
+        s.close()
+        assert st == 0 and d.steps == 31
+        outs.append((u, v, P))
+    for u, v, P in outs[1:]:
+        assert np.array_equal(u, outs[0][0]) and np.array_equal(v, outs[0][1]) and np.array_equal(P, outs[0][2])
+
+
+def test_resident_blocks_and_default_tiling(gpu):
+    """The occupancy query gives a whole number of blocks per compute unit for
+    every launchable shape and 0 for the shapes that cannot be launched; the
+    default tiling fills at most one wave of resident blocks."""
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.autotune import strips
+
+    import torch
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    s = lbm.Solver(1000, 700, 1.0, "fp32", "pc")
+    for block in (64, 128, 256, 512):
+        for spl in (1, 2):
+            r = s.resident_blocks(block, spl)
+            if spl == 2 and block == 512:
+                assert r == 0
+            else:
+                assert r > 0 and r % cus == 0, (block, spl, r)
+    assert s.resident_blocks(96, 1) == 0
+    block, segs = s.tiling()
+    assert strips(1000, block, "fp32", "pc", 1) * segs <= s.resident_blocks(block, 1)
+    s.close()
+    e = lbm.Solver(300, 90, 1.0, "fp32", "explicit")
+    assert e.resident_blocks(128, 1) > 0 and e.resident_blocks(128, 2) == 0
+    e.close()
