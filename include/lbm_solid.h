@@ -65,6 +65,14 @@ typedef enum {
  *   momentum in float, arithmetic in float. */
 typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_STORE = 2, LBM_BF16_STORE = 3 } lbm_precision;
 
+/* Rounding of 16-bit population stores. NEAREST: round to nearest even.
+ * STOCHASTIC: round up or down with probability given by the distance to
+ * the two neighbours (unbiased), with random bits from a counter-based hash
+ * of (seed, step index of the state written, site, population), so a run is
+ * reproducible for a seed and independent of launch shape, steps per launch
+ * and batching. 32- and 64-bit storage always rounds to nearest. */
+typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
+
 /* Time level of the source in the moment step (Sec. 5). */
 typedef enum { LBM_SCHEME_PC = 0, LBM_SCHEME_EXPLICIT = 1 } lbm_scheme;
 
@@ -148,6 +156,11 @@ lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k);
  * chosen with it. Writes 0 for a shape the handle cannot launch. */
 lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_launch, int *blocks);
 
+/* Rounding of the populations written by later steps (the start state of
+ * lbm_set_fields always rounds to nearest). STOCHASTIC needs FP16_STORE or
+ * BF16_STORE (LBM_ERR_UNSUPPORTED otherwise). */
+lbm_status lbm_set_rounding(lbm_solver *h, lbm_rounding r, uint64_t seed);
+
 /* Time step dt of the handle's material. */
 lbm_status lbm_get_dt(const lbm_solver *h, double *dt);
 
@@ -184,6 +197,8 @@ typedef struct {
     double body[2];
     lbm_bc bc_ymin, bc_ymax;
     double val_ymin[2], val_ymax[2];
+    lbm_rounding rounding;  /* as lbm_set_rounding; STOCHASTIC needs 16-bit storage */
+    uint64_t seed;
 } lbm_plate_desc;
 
 /* Arena bytes one plate of nx * ny sites uses at precision p. */

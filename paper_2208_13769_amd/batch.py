@@ -23,6 +23,7 @@ class lbm_plate_desc(ctypes.Structure):
         ("body", ctypes.c_double * 2),
         ("bc_ymin", ctypes.c_int), ("bc_ymax", ctypes.c_int),
         ("val_ymin", ctypes.c_double * 2), ("val_ymax", ctypes.c_double * 2),
+        ("rounding", ctypes.c_int), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -159,6 +160,8 @@ class PlateSpec:
     bc_ymax: int = lbm.LBM_BC_PERIODIC
     val_ymin: tuple = (0.0, 0.0)
     val_ymax: tuple = (0.0, 0.0)
+    rounding: str = "nearest"
+    seed: int = 0
 
     def c(self) -> lbm_plate_desc:
         d = lbm_plate_desc()
@@ -168,6 +171,8 @@ class PlateSpec:
         d.bc_ymin, d.bc_ymax = self.bc_ymin, self.bc_ymax
         d.val_ymin[0], d.val_ymin[1] = self.val_ymin
         d.val_ymax[0], d.val_ymax[1] = self.val_ymax
+        d.rounding = lbm.ROUNDINGS.get(self.rounding, self.rounding)
+        d.seed = int(self.seed) & ((1 << 64) - 1)
         return d
 
 

@@ -26,6 +26,8 @@ struct PlateDesc {
     int parity0;      // copy holding that state
     int nsteps;       // steps of this plate in the chunk (0: idle)
     unsigned *flag;   // this plate's unstable flag
+    int sr;           // stochastic rounding of 16-bit populations
+    unsigned long long seed;
 };
 
 struct TileDesc {
@@ -72,6 +74,8 @@ __global__ void __launch_bounds__(BLOCK)
         sp.halo_a = pd.halo_a;
         sp.flag = pd.flag;
         sp.step = pd.step0 + k;
+        sp.sr = pd.sr;
+        sp.seed = pd.seed;
         step_tile<PR, BLOCK, PC, WALLED>(sp, td.strip, td.seg);
     }
 }

@@ -32,6 +32,72 @@ using PrecF32 = Prec<float, float, float, float>;
 using PrecF16 = Prec<__half, double, float, float>;
 using PrecBF16 = Prec<__hip_bfloat16, double, float, float>;
 
+// ---------------------------------------------------------------- rounding
+
+// Stochastic rounding of 16-bit population stores draws its random bits from
+// a counter-based hash: the integer mixer "lowbias32" (C. Wellons, 2018:
+// xorshift 16, multiply 0x7feb352d, xorshift 15, multiply 0x846ca68b,
+// xorshift 16), a bijection of 32-bit words. The counter is (site index,
+// population pair) and the key is derived from the plate's seed and the index
+// of the state being written, so the bits of a stored value do not depend on
+// the block, launch or batch that computes it.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// key of the state with index `state` (the step count after the update)
+__host__ __device__ __forceinline__ uint32_t sr_key(unsigned long long seed, long long state)
+{
+    const uint32_t s = mix32((uint32_t)state ^ mix32((uint32_t)((unsigned long long)state >> 32) + 0x9e3779b9u));
+    return mix32(s ^ (uint32_t)seed) ^ mix32((uint32_t)(seed >> 32) ^ s);
+}
+
+// 32 random bits for populations 2q and 2q+1 (q = 0..4) of a site: the low
+// half word rounds the first, the high half word the second.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t key, uint32_t site, int q)
+{
+    return mix32((site * 5u + (uint32_t)q) ^ key);
+}
+
+// x rounded to binary16 up or down (toward or away from zero) with
+// probability given by its distance to the two neighbours, using the low 13
+// bits of r: adding r below the 13 dropped mantissa bits of |x| and then
+// truncating carries into the kept bits exactly in that fraction of the
+// 2^13 equally likely values. Applies to the normal binary16 range; smaller
+// magnitudes (below 2^-14, far under the scaled population range) and
+// non-finite values round to nearest.
+__device__ __forceinline__ __half half_sr(float x, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(x);
+    const uint32_t mag = b & 0x7fffffffu;
+    if (mag >= 0x38800000u && mag < 0x477fe000u) {  // [2^-14, 65504)
+        const uint32_t m = mag + (r & 0x1fffu);
+        const unsigned short h = (unsigned short)(((b >> 16) & 0x8000u) | ((m >> 13) - (112u << 10)));
+        return __ushort_as_half(h);
+    }
+    return __float2half_rn(x);
+}
+
+// the same for bfloat16 with the low 16 bits of r (16 dropped bits); exact
+// for every finite magnitude up to the largest bfloat16
+__device__ __forceinline__ __hip_bfloat16 bf16_sr(float x, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(x);
+    const uint32_t mag = b & 0x7fffffffu;
+    if (mag < 0x7f7f0000u) {
+        const uint32_t m = mag + (r & 0xffffu);
+        const unsigned short h = (unsigned short)(((b >> 16) & 0x8000u) | (m >> 16));
+        return __ushort_as_bfloat16(h);
+    }
+    return __float2bfloat16(x);
+}
+
 // Populations in 16-bit storage are kept multiplied by a per-plate power of
 // two so that their range sits well inside the format; 32/64-bit storage is
 // unscaled.
@@ -44,6 +110,9 @@ struct FStore<double> {
     __device__ static double cvt(double v, double) { return v; }
     __device__ static double roundtrip(double v, double, double) { return v; }
     __device__ static void store(double *p, size_t i, double v, double) { p[i] = v; }
+    static constexpr bool kStochastic = false;
+    __device__ static double roundtrip_sr(double v, double, double, uint32_t) { return v; }
+    __device__ static void store_sr(double *p, size_t i, double v, double, uint32_t) { p[i] = v; }
 };
 template <>
 struct FStore<float> {
@@ -51,6 +120,9 @@ struct FStore<float> {
     __device__ static float cvt(float v, float) { return v; }
     __device__ static float roundtrip(float v, float, float) { return v; }
     __device__ static void store(float *p, size_t i, float v, float) { p[i] = v; }
+    static constexpr bool kStochastic = false;
+    __device__ static float roundtrip_sr(float v, float, float, uint32_t) { return v; }
+    __device__ static void store_sr(float *p, size_t i, float v, float, uint32_t) { p[i] = v; }
 };
 template <>
 struct FStore<__half> {
@@ -68,6 +140,26 @@ struct FStore<__half> {
     {
         p[i] = __float2half_rn(v * scale);
     }
+    // stochastic rounding with the random word r
+    static constexpr bool kStochastic = true;
+    __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
+    {
+        return __half2float(half_sr(v * scale, r)) * inv_scale;
+    }
+    __device__ static void store_sr(__half *p, size_t i, float v, float scale, uint32_t r)
+    {
+        p[i] = half_sr(v * scale, r);
+    }
+    // the stored bit pattern, and the value a bit pattern loads as
+    __device__ static uint32_t bits(float v, float scale) { return __half_as_ushort(__float2half_rn(v * scale)); }
+    __device__ static uint32_t bits_sr(float v, float scale, uint32_t r)
+    {
+        return __half_as_ushort(half_sr(v * scale, r));
+    }
+    __device__ static float from_bits(uint32_t b, float inv_scale)
+    {
+        return __half2float(__ushort_as_half((unsigned short)b)) * inv_scale;
+    }
 };
 template <>
 struct FStore<__hip_bfloat16> {
@@ -83,6 +175,27 @@ struct FStore<__hip_bfloat16> {
     __device__ static void store(__hip_bfloat16 *p, size_t i, float v, float scale)
     {
         p[i] = __float2bfloat16(v * scale);
+    }
+    static constexpr bool kStochastic = true;
+    __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
+    {
+        return __bfloat162float(bf16_sr(v * scale, r)) * inv_scale;
+    }
+    __device__ static void store_sr(__hip_bfloat16 *p, size_t i, float v, float scale, uint32_t r)
+    {
+        p[i] = bf16_sr(v * scale, r);
+    }
+    __device__ static uint32_t bits(float v, float scale)
+    {
+        return __bfloat16_as_ushort(__float2bfloat16(v * scale));
+    }
+    __device__ static uint32_t bits_sr(float v, float scale, uint32_t r)
+    {
+        return __bfloat16_as_ushort(bf16_sr(v * scale, r));
+    }
+    __device__ static float from_bits(uint32_t b, float inv_scale)
+    {
+        return __bfloat162float(__ushort_as_bfloat16((unsigned short)b)) * inv_scale;
     }
 };
 

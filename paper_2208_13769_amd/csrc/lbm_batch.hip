@@ -42,6 +42,8 @@ struct Slot {
     int parity = 0;
     int64_t done = 0, target = 0;
     double f_scale = 1.0;
+    int sr = 0;
+    unsigned long long seed = 0;
 };
 
 struct BatchLayout {
@@ -265,6 +267,8 @@ PlateDesc describe(const lbm_batch *b, int s, int nsteps)
     d.parity0 = sl.parity;
     d.nsteps = nsteps;
     d.flag = b->d_flags() + s;
+    d.sr = sl.sr;
+    d.seed = sl.seed;
     return d;
 }
 
@@ -398,6 +402,10 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
         d->bc_ymax > LBM_BC_NEUMANN_T)
         return bfail(b, LBM_ERR_ARG, "unknown boundary rule");
     if (pw != b->walled) return bfail(b, LBM_ERR_UNSUPPORTED, "plate edges do not match the batch (walled or periodic)");
+    if (d->rounding != LBM_ROUND_NEAREST && d->rounding != LBM_ROUND_STOCHASTIC)
+        return bfail(b, LBM_ERR_ARG, "unknown rounding");
+    if (d->rounding == LBM_ROUND_STOCHASTIC && b->prec != LBM_FP16_STORE && b->prec != LBM_BF16_STORE)
+        return bfail(b, LBM_ERR_UNSUPPORTED, "stochastic rounding needs 16-bit population storage");
     int s = -1;
     for (int i = 0; i < b->max_plates; ++i)
         if (!b->slots[i].live) {
@@ -417,6 +425,8 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
     sl.ny = d->ny;
     sl.U = Units{d->dx, d->rho0, d->lambda, d->mu};
     sl.tau = d->tau_over_dt;
+    sl.sr = d->rounding == LBM_ROUND_STOCHASTIC;
+    sl.seed = d->seed;
     sl.body[0] = d->body[0];
     sl.body[1] = d->body[1];
     sl.bc_lo = d->bc_ymin;

@@ -60,6 +60,8 @@ struct lbm_solver {
     int64_t steps = 0;
     Shape shape{};
     int spl = 1;  // time steps per launch (1, or 2 with the predictor-corrector)
+    int sr = 0;   // stochastic rounding of 16-bit populations
+    unsigned long long seed = 0;
     std::string err;
 
     void *fptr(int c) const { return ws + L.state.f[c]; }
@@ -283,6 +285,17 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
     return LBM_OK;
 }
 
+lbm_status lbm_set_rounding(lbm_solver *h, lbm_rounding r, uint64_t seed)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (r != LBM_ROUND_NEAREST && r != LBM_ROUND_STOCHASTIC) return fail(h, LBM_ERR_ARG, "unknown rounding");
+    if (r == LBM_ROUND_STOCHASTIC && h->prec != LBM_FP16_STORE && h->prec != LBM_BF16_STORE)
+        return fail(h, LBM_ERR_UNSUPPORTED, "stochastic rounding needs 16-bit population storage");
+    h->sr = r == LBM_ROUND_STOCHASTIC;
+    h->seed = seed;
+    return LBM_OK;
+}
+
 lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k)
 {
     if (!h || !k) return LBM_ERR_ARG;
@@ -343,6 +356,8 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
     sp.n_strips = h->shape.n_strips;
     sp.n_segs = h->shape.n_segs;
     sp.flag = h->flag();
+    sp.sr = h->sr;
+    sp.seed = h->seed;
     const int nblocks = h->shape.n_strips * h->shape.n_segs;
     const bool pc = h->scheme == LBM_SCHEME_PC;
     int64_t k = 0;

@@ -61,7 +61,51 @@ struct StepParams {
     int halo_a;             // threads left of the first output column (>= the stencil halo)
     unsigned int *flag;     // set to 1 on J <= 0 or a non-finite value
     long long step;         // index n of the input state
+    int sr;                 // 16-bit populations: 1 = stochastic rounding, 0 = to nearest
+    unsigned long long seed;  // key of the stochastic rounding
 };
+
+// Store the nine populations of site o (plane-major), rounded to the storage
+// type to nearest or, for 16-bit storage with sr set, stochastically with the
+// bits of (key, o).
+template <class FS, class TF, class TC>
+__device__ __forceinline__ void store_site(TF *__restrict__ f, size_t plane, size_t o, const TC fn[9], TC scale,
+                                           bool sr, uint32_t key)
+{
+    if constexpr (FS::kStochastic) {
+        if (sr) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const uint32_t r = sr_bits(key, (uint32_t)o, q);
+                FS::store_sr(f, (size_t)(2 * q) * plane + o, fn[2 * q], scale, r);
+                if (q < 4) FS::store_sr(f, (size_t)(2 * q + 1) * plane + o, fn[2 * q + 1], scale, r >> 16);
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) FS::store(f, i * plane + o, fn[i], scale);
+}
+
+// The values store_site would write for site o, read back.
+template <class FS, class TC>
+__device__ __forceinline__ void roundtrip_site(size_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key,
+                                               TC out[9])
+{
+    if constexpr (FS::kStochastic) {
+        if (sr) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const uint32_t r = sr_bits(key, (uint32_t)o, q);
+                out[2 * q] = FS::roundtrip_sr(fn[2 * q], scale, inv, r);
+                if (q < 4) out[2 * q + 1] = FS::roundtrip_sr(fn[2 * q + 1], scale, inv, r >> 16);
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i] = FS::roundtrip(fn[i], scale, inv);
+}
 
 template <class TC>
 __device__ __forceinline__ void collide(const TC f[9], TC jx, TC jy, TC Sx, TC Sy, TC omega,
@@ -557,6 +601,8 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
     const TileGeom g = tile_geom(p, strip, seg);
     P pipe(lds, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
+    const bool sr = FS::kStochastic && p.sr;
+    const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
 
     const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7);
     const int Rstart = g.y0 - HX;
@@ -581,8 +627,7 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         const int rD = R - 4, rF = PC ? R - 6 : R - 4;
         if (pipe.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
             const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn[i], f_scale);
+            store_site<FS>(fout, plane, o, fn, f_scale, sr, key);
         }
         if (pipe.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
             const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
@@ -603,6 +648,72 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     }
     if (pipe.bad) p.flag[0] = 1u;
 }
+
+// Delay line that hands the first step's populations f_{n+1} (rows R-4 ..
+// R-7) to the second step, holding each value as the storage type would:
+// 32/64-bit storage keeps the values, 16-bit storage keeps the stored bit
+// patterns two to a word (20 registers instead of 36).
+template <class FS, class TC, bool PACKED = FS::kStochastic>
+struct FDelay {
+    TC v[4][9];
+    __device__ __forceinline__ FDelay()
+    {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[k][i] = TC(0);
+    }
+    __device__ __forceinline__ void push(size_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key)
+    {
+#pragma unroll
+        for (int k = 3; k > 0; --k)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[k][i] = v[k - 1][i];
+        roundtrip_site<FS>(o, fn, scale, inv, sr, key, v[0]);
+    }
+    __device__ __forceinline__ void oldest(TC out[9], TC) const
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[i] = v[3][i];
+    }
+};
+
+template <class FS, class TC>
+struct FDelay<FS, TC, true> {
+    uint32_t w[4][5];
+    __device__ __forceinline__ FDelay()
+    {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) w[k][q] = 0u;
+    }
+    __device__ __forceinline__ void push(size_t o, const TC fn[9], TC scale, TC, bool sr, uint32_t key)
+    {
+#pragma unroll
+        for (int k = 3; k > 0; --k)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) w[k][q] = w[k - 1][q];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            uint32_t lo, hi = 0u;
+            if (sr) {
+                const uint32_t r = sr_bits(key, (uint32_t)o, q);
+                lo = FS::bits_sr(fn[2 * q], scale, r);
+                if (q < 4) hi = FS::bits_sr(fn[2 * q + 1], scale, r >> 16);
+            } else {
+                lo = FS::bits(fn[2 * q], scale);
+                if (q < 4) hi = FS::bits(fn[2 * q + 1], scale);
+            }
+            w[0][q] = lo | (hi << 16);
+        }
+    }
+    __device__ __forceinline__ void oldest(TC out[9], TC inv) const
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[i] = FS::from_bits((w[3][i >> 1] >> (16 * (i & 1))) & 0xffffu, inv);
+    }
+};
 
 // Two time steps of one tile in one pass (predictor-corrector only): a second
 // pipeline takes the first one's outputs six rows behind it -- u_{n+1} at
@@ -634,13 +745,13 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
     const TileGeom g = tile_geom(p, strip, seg);
     P p1(lds1, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
     P p2(lds2, p, p.step + 1, (int)threadIdx.x, g.y0, g.y1, g.out_col);
+    const bool sr = FS::kStochastic && p.sr;
+    const uint32_t key1 = sr ? sr_key(p.seed, p.step + 1) : 0u;
+    const uint32_t key2 = sr ? sr_key(p.seed, p.step + 2) : 0u;
 
     // f_{n+1} of rows R-4 .. R-7 and j_{n+1} of rows R-6, R-7 (after the shift)
-    TC fd[4][9], jd[2][2];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fd[k][i] = TC(0);
+    FDelay<FS, TC> fd;
+    TC jd[2][2];
     jd[0][0] = jd[0][1] = jd[1][0] = jd[1][1] = TC(0);
 
     const int n_iter = (g.y1 - g.y0) + 22;
@@ -669,8 +780,7 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
         const int rD = R2 - 4, rF = R2 - 6;
         if (p2.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
             const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) FS::store(fout, i * plane + o, fn2[i], f_scale);
+            store_site<FS>(fout, plane, o, fn2, f_scale, sr, key2);
         }
         if (p2.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
             const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
@@ -683,13 +793,13 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
                 p2.bad = true;
         }
         // inputs of the second step: u_{n+1}(R2) now, f and j_{n+1}(R2 - 2) delayed
-        p2.abc(R2, b, p2.is_node(R2), u1[0], u1[1], p2.is_node(R2 - 2), fd[3], jd[1][0], jd[1][1]);
-#pragma unroll
-        for (int k = 3; k > 0; --k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fd[k][i] = fd[k - 1][i];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fd[0][i] = FS::roundtrip(fn1[i], f_scale, f_inv);
+        {
+            TC f2[9];
+            fd.oldest(f2, f_inv);
+            p2.abc(R2, b, p2.is_node(R2), u1[0], u1[1], p2.is_node(R2 - 2), f2, jd[1][0], jd[1][1]);
+        }
+        // (the site the first step's row R-4 value belongs to, as a store would index it)
+        fd.push((size_t)row_load<WALLED>(R - 4, ny) * nx + g.gx, fn1, f_scale, f_inv, sr, key1);
         jd[1][0] = jd[0][0];
         jd[1][1] = jd[0][1];
         jd[0][0] = TC(TJ(j1[0]));

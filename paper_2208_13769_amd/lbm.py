@@ -24,16 +24,18 @@ LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE = 0, 1, 2, 3
 LBM_SCHEME_PC, LBM_SCHEME_EXPLICIT = 0, 1
 LBM_EDGE_XMIN, LBM_EDGE_XMAX, LBM_EDGE_YMIN, LBM_EDGE_YMAX = 0, 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_DIRICHLET_J, LBM_BC_NEUMANN_T = 0, 1, 2
+LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_STORE, "bf16": LBM_BF16_STORE}
 SCHEMES = {"pc": LBM_SCHEME_PC, "explicit": LBM_SCHEME_EXPLICIT}
+ROUNDINGS = {"nearest": LBM_ROUND_NEAREST, "stochastic": LBM_ROUND_STOCHASTIC}
 
 EXPORTED_EXTRA: list = []
 EXPORTED = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_material", "lbm_set_body_force", "lbm_set_boundary",
     "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
     "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
-    "lbm_resident_blocks",
+    "lbm_resident_blocks", "lbm_set_rounding",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
     "lbm_batch_destroy", "lbm_batch_last_error",
@@ -101,6 +103,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_set_steps_per_launch.argtypes = [vp, ctypes.c_int]
     lib.lbm_get_steps_per_launch.restype = ctypes.c_int
     lib.lbm_get_steps_per_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.lbm_set_rounding.restype = ctypes.c_int
+    lib.lbm_set_rounding.argtypes = [vp, ctypes.c_int, ctypes.c_uint64]
     lib.lbm_resident_blocks.restype = ctypes.c_int
     lib.lbm_resident_blocks.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -186,6 +190,10 @@ def lbm_get_tiling(h):
 
 def lbm_set_steps_per_launch(h, k: int):
     _check(load_library().lbm_set_steps_per_launch(h, int(k)), h)
+
+
+def lbm_set_rounding(h, rounding: int, seed: int = 0):
+    _check(load_library().lbm_set_rounding(h, int(rounding), int(seed) & ((1 << 64) - 1)), h)
 
 
 def lbm_resident_blocks(h, block: int, steps_per_launch: int) -> int:
@@ -278,6 +286,10 @@ class Solver:
 
     def steps_per_launch(self) -> int:
         return lbm_get_steps_per_launch(self.h)
+
+    def set_rounding(self, rounding, seed: int = 0):
+        """rounding: "nearest" / "stochastic" or LBM_ROUND_*."""
+        lbm_set_rounding(self.h, ROUNDINGS.get(rounding, rounding), seed)
 
     def resident_blocks(self, block: int, steps_per_launch: int) -> int:
         return lbm_resident_blocks(self.h, block, steps_per_launch)
