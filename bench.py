@@ -107,8 +107,8 @@ def cpu_baseline(wl, steps: int):
 
 
 def bench_config4(args):
-    """256 plates of uneven sizes in one batch (one persistent launch per
-    step, graph-captured chunks), FP16 populations, 2000 steps each."""
+    """256 plates of uneven sizes in one batch (one persistent launch per one
+    or two steps, graph-captured chunks), FP16 populations, 2000 steps each."""
     import torch
 
     from paper_2208_13769_amd import inputs, lbm
@@ -126,6 +126,8 @@ def bench_config4(args):
     def run_batch(precision):
         arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, precision) for sp in specs) + (64 << 20)
         b = Batch(max_plates=len(specs), arena_bytes=arena, precision=precision, walled=True)
+        if args.batch_spl:
+            b.set_steps_per_launch(args.batch_spl)
         slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
         b.step(args.chunk)  # warm-up chunk: graph capture, first touch
         torch.cuda.synchronize()
@@ -146,6 +148,7 @@ def bench_config4(args):
         return b, slots, ms
 
     b16, s16, ms16 = run_batch("fp16")
+    b16_spl = b16.steps_per_launch()
     bad = [i for i, s_ in enumerate(s16) if b16.query(s_)[2]]
     done_sites = sum(specs[i].nx * specs[i].ny for i in range(len(specs)) if i not in bad)
     mlups16 = done_sites * steps / (ms16 / 1e3) / 1e6
@@ -183,8 +186,10 @@ def bench_config4(args):
         "vs_baseline": None, "dtype": DTYPE["fp16"], "data": "synthetic",
         "config": {"workload": "256 plates, side log-uniform 64..1024 (seed 4), lam U[0.05,0.2], mu U[0.02,0.1], "
                                "tau/dt=0.8, periodic in x, clamped bottom, traction-free top, initial top "
-                               "velocity pulse 0.01; FP16 populations; one batch, one launch per step",
-                   "plates": len(specs), "sites": sites, "chunk": args.chunk},
+                               "velocity pulse 0.01; FP16 populations; one batch, one persistent launch per "
+                               "one or two steps",
+                   "plates": len(specs), "sites": sites, "chunk": args.chunk,
+                   "steps_per_launch": b16_spl},
         "diverged_plates": len(bad),
         "diverged_lam_over_mu": sorted(round(specs[i].lam / specs[i].mu, 2) for i in bad),
         "error_vs_fp64": {"median_rel_l2_u": float(np.median(errs_u)), "max_rel_l2_u": float(np.max(errs_u)),
@@ -211,6 +216,8 @@ def main():
                          "write) three times: its HBM counter readings calibrate the step kernel's")
     ap.add_argument("--plate-steps", type=int, default=2000, help="config4: steps per plate")
     ap.add_argument("--chunk", type=int, default=200, help="config4: steps per graph-captured chunk")
+    ap.add_argument("--batch-spl", type=int, default=0,
+                    help="config4: time steps per batch launch (1 or 2; 0 = the batch's default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "

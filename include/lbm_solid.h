@@ -179,7 +179,8 @@ const char *lbm_last_error(const lbm_solver *h);
  * admission by device-memory footprint -- and keep their state resident
  * until retired. lbm_batch_step advances every admitted plate that has steps
  * left by up to nsteps, in one persistent launch per time step for all
- * plates, enqueued as a HIP graph of nsteps launches. All plates of a batch
+ * plates (or two steps per launch, see lbm_batch_set_steps_per_launch),
+ * enqueued as a HIP graph of those launches. All plates of a batch
  * share the precision, the scheme and the kind of y edges (all periodic, or
  * all walls with per-plate rules and values); x edges are periodic.
  * The batch uses 256-thread blocks; plates are cut into column strips and
@@ -226,6 +227,15 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
 /* Enqueue up to nsteps steps (at most 2^20) for every plate with steps
  * left; a plate stops when it has done its nsteps. Returns at once. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Time steps per launch of the batch kernel: 1, or 2 with the
+ * predictor-corrector scheme (the default when the two-step kernel of the
+ * batch's precision and edges keeps two waves per SIMD). With 2, a launch advances
+ * every running plate by two steps in one pass over its state, or by one
+ * step when that is the plate's last; results equal one step per launch
+ * bitwise. Changing it synchronises the stream and re-plans the tiles. */
+lbm_status lbm_batch_set_steps_per_launch(lbm_batch *b, int k);
+lbm_status lbm_batch_get_steps_per_launch(const lbm_batch *b, int *k);
 
 /* Steps done and left and the unstable flag of a plate. Synchronises. */
 lbm_status lbm_batch_query(lbm_batch *b, int slot, int64_t *steps_done, int64_t *steps_left, int *unstable);

@@ -60,6 +60,10 @@ def _lib():
         lib.lbm_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.lbm_batch_destroy.restype = None
         lib.lbm_batch_destroy.argtypes = [vp]
+        lib.lbm_batch_set_steps_per_launch.restype = ctypes.c_int
+        lib.lbm_batch_set_steps_per_launch.argtypes = [vp, ctypes.c_int]
+        lib.lbm_batch_get_steps_per_launch.restype = ctypes.c_int
+        lib.lbm_batch_get_steps_per_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         lib.lbm_batch_last_error.restype = ctypes.c_char_p
         lib.lbm_batch_last_error.argtypes = [vp]
         _configured = True
@@ -114,6 +118,16 @@ def lbm_batch_add(h, desc: lbm_plate_desc, u0, v0, nsteps):
 
 def lbm_batch_step(h, nsteps):
     _check(_lib().lbm_batch_step(h, int(nsteps)), h)
+
+
+def lbm_batch_set_steps_per_launch(h, k):
+    _check(_lib().lbm_batch_set_steps_per_launch(h, int(k)), h)
+
+
+def lbm_batch_get_steps_per_launch(h):
+    k = ctypes.c_int()
+    _check(_lib().lbm_batch_get_steps_per_launch(h, ctypes.byref(k)), h)
+    return k.value
 
 
 def lbm_batch_query(h, slot):
@@ -223,6 +237,12 @@ class Batch:
 
     def query(self, slot):
         return lbm_batch_query(self.h, slot)
+
+    def set_steps_per_launch(self, k: int):
+        lbm_batch_set_steps_per_launch(self.h, k)
+
+    def steps_per_launch(self) -> int:
+        return lbm_batch_get_steps_per_launch(self.h)
 
     def read(self, slot, want_fields: bool = True):
         sp = self.specs[slot]

@@ -110,6 +110,7 @@ struct FStore<double> {
     __device__ static double cvt(double v, double) { return v; }
     __device__ static double roundtrip(double v, double, double) { return v; }
     __device__ static void store(double *p, size_t i, double v, double) { p[i] = v; }
+    __device__ static double conv(double v, double) { return v; }
     static constexpr bool kStochastic = false;
     __device__ static double roundtrip_sr(double v, double, double, uint32_t) { return v; }
     __device__ static void store_sr(double *p, size_t i, double v, double, uint32_t) { p[i] = v; }
@@ -120,6 +121,7 @@ struct FStore<float> {
     __device__ static float cvt(float v, float) { return v; }
     __device__ static float roundtrip(float v, float, float) { return v; }
     __device__ static void store(float *p, size_t i, float v, float) { p[i] = v; }
+    __device__ static float conv(float v, float) { return v; }
     static constexpr bool kStochastic = false;
     __device__ static float roundtrip_sr(float v, float, float, uint32_t) { return v; }
     __device__ static void store_sr(float *p, size_t i, float v, float, uint32_t) { p[i] = v; }
@@ -140,7 +142,9 @@ struct FStore<__half> {
     {
         p[i] = __float2half_rn(v * scale);
     }
-    // stochastic rounding with the random word r
+    // the stored value of v, to nearest and stochastically with the random word r
+    __device__ static __half conv(float v, float scale) { return __float2half_rn(v * scale); }
+    __device__ static __half conv_sr(float v, float scale, uint32_t r) { return half_sr(v * scale, r); }
     static constexpr bool kStochastic = true;
     __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
     {
@@ -176,6 +180,8 @@ struct FStore<__hip_bfloat16> {
     {
         p[i] = __float2bfloat16(v * scale);
     }
+    __device__ static __hip_bfloat16 conv(float v, float scale) { return __float2bfloat16(v * scale); }
+    __device__ static __hip_bfloat16 conv_sr(float v, float scale, uint32_t r) { return bf16_sr(v * scale, r); }
     static constexpr bool kStochastic = true;
     __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
     {

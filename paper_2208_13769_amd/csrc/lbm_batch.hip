@@ -25,8 +25,9 @@ using namespace lbm;
 namespace {
 
 constexpr int kBatchBlock = 256;
-constexpr int kSegRowsMax = 64;  // rows per segment when the batch is full
 constexpr int kSegRowsMin = 16;  // shortest segment when few plates run
+// rows per segment when the batch is full (the two-step halo is twice as deep)
+constexpr int seg_rows_max(int spl) { return spl == 2 ? 128 : 64; }
 
 struct Slot {
     bool live = false;
@@ -75,16 +76,21 @@ BatchLayout batch_layout(int max_plates, int max_tiles, size_t arena_bytes)
     return B;
 }
 
-Shape batch_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int seg_rows)
+Shape batch_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int seg_rows, int spl)
 {
-    return make_shape(nx, ny, p, s, kBatchBlock, std::max(1, (ny + seg_rows / 2) / seg_rows));
+    return make_shape(nx, ny, p, s, kBatchBlock, std::max(1, (ny + seg_rows / 2) / seg_rows), spl);
 }
 
-// Tile-table entries a plate may need (at the shortest segments).
+// Tile-table entries a plate may need (at the shortest segments, either
+// number of steps per launch).
 int max_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s)
 {
-    const Shape sh = batch_shape(nx, ny, p, s, kSegRowsMin);
-    return sh.n_strips * sh.n_segs;
+    int n = 0;
+    for (int spl = 1; spl <= (s == LBM_SCHEME_PC ? 2 : 1); ++spl) {
+        const Shape sh = batch_shape(nx, ny, p, s, kSegRowsMin, spl);
+        n = std::max(n, sh.n_strips * sh.n_segs);
+    }
+    return n;
 }
 
 }  // namespace
@@ -110,7 +116,9 @@ struct lbm_batch {
     int buf = 0;
     std::vector<int> running;  // slots in the uploaded tile table
     bool tables_valid = false;
-    std::map<int, hipGraphExec_t> graphs;
+    std::map<long long, hipGraphExec_t> graphs;  // key: chunk steps * 2 + (steps per launch - 1)
+    int spl = 1;              // time steps per launch
+    int grid_for[3] = {0, 0, 0};  // persistent grid of the one- and two-step kernels
     int grid = 0;
     int tiles_used = 0;
     std::string err;
@@ -209,25 +217,28 @@ void arena_free(lbm_batch *b, size_t off, size_t bytes)
 }
 
 template <class PR, bool PC, bool W>
-const void *batch_kernel_ptr()
+const void *batch_kernel_ptr(int spl)
 {
+    if constexpr (PC) {
+        if (spl == 2) return reinterpret_cast<const void *>(&batch_step2_kernel<PR, kBatchBlock, W>);
+    }
     return reinterpret_cast<const void *>(&batch_step_kernel<PR, kBatchBlock, PC, W>);
 }
 
 template <class PR>
-const void *batch_kernel_for(bool pc, bool walled)
+const void *batch_kernel_for(bool pc, bool walled, int spl)
 {
-    if (pc) return walled ? batch_kernel_ptr<PR, true, true>() : batch_kernel_ptr<PR, true, false>();
-    return walled ? batch_kernel_ptr<PR, false, true>() : batch_kernel_ptr<PR, false, false>();
+    if (pc) return walled ? batch_kernel_ptr<PR, true, true>(spl) : batch_kernel_ptr<PR, true, false>(spl);
+    return walled ? batch_kernel_ptr<PR, false, true>(spl) : batch_kernel_ptr<PR, false, false>(spl);
 }
 
-const void *batch_kernel(lbm_precision p, bool pc, bool walled)
+const void *batch_kernel(lbm_precision p, bool pc, bool walled, int spl)
 {
     switch (p) {
-    case LBM_FP64: return batch_kernel_for<PrecF64>(pc, walled);
-    case LBM_FP32: return batch_kernel_for<PrecF32>(pc, walled);
-    case LBM_FP16_STORE: return batch_kernel_for<PrecF16>(pc, walled);
-    default: return batch_kernel_for<PrecBF16>(pc, walled);
+    case LBM_FP64: return batch_kernel_for<PrecF64>(pc, walled, spl);
+    case LBM_FP32: return batch_kernel_for<PrecF32>(pc, walled, spl);
+    case LBM_FP16_STORE: return batch_kernel_for<PrecF16>(pc, walled, spl);
+    default: return batch_kernel_for<PrecBF16>(pc, walled, spl);
     }
 }
 
@@ -272,21 +283,25 @@ PlateDesc describe(const lbm_batch *b, int s, int nsteps)
     return d;
 }
 
+// Graph of the launches that advance a chunk of K steps: K one-step
+// launches, or (K + 1) / 2 two-step launches.
 hipError_t get_graph(lbm_batch *b, int K, hipGraphExec_t *out)
 {
-    auto it = b->graphs.find(K);
+    const long long key = 2LL * K + (b->spl - 1);
+    auto it = b->graphs.find(key);
     if (it != b->graphs.end()) {
         *out = it->second;
         return hipSuccess;
     }
-    const void *fn = batch_kernel(b->prec, b->scheme == LBM_SCHEME_PC, b->walled);
+    const void *fn = batch_kernel(b->prec, b->scheme == LBM_SCHEME_PC, b->walled, b->spl);
+    const int launches = b->spl == 2 ? (K + 1) / 2 : K;
     // captured on the batch's own stream, launched on the caller's
     hipError_t e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed);
     if (e) return e;
     const PlateDesc *plates = b->d_plates();
     const TileDesc *tiles = b->d_tiles();
     const int *nt = b->d_ntiles();
-    for (int k = 0; k < K && e == hipSuccess; ++k) {
+    for (int k = 0; k < launches && e == hipSuccess; ++k) {
         void *args[] = {(void *)&plates, (void *)&tiles, (void *)&nt, (void *)&k};
         e = hipLaunchKernel(fn, dim3(b->grid), dim3(kBatchBlock), args, 0, b->capture);
     }
@@ -301,7 +316,7 @@ hipError_t get_graph(lbm_batch *b, int K, hipGraphExec_t *out)
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e) return e;
-    b->graphs[K] = ex;
+    b->graphs[key] = ex;
     *out = ex;
     return hipSuccess;
 }
@@ -362,17 +377,24 @@ lbm_status lbm_batch_create(int max_plates, int max_tiles, lbm_precision p, lbm_
         if (!e) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
     }
     if (!e) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-    int dev = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0;
     if (!e) e = hipGetDevice(&dev);
     if (!e) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (!e)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel(p, s == LBM_SCHEME_PC, b->walled),
-                                                          kBatchBlock, 0);
+    int per_cu[3] = {0, 0, 0};
+    for (int k = 1; k <= (s == LBM_SCHEME_PC ? 2 : 1) && !e; ++k) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[k], batch_kernel(p, s == LBM_SCHEME_PC, b->walled, k),
+                                                         kBatchBlock, 0);
+        b->grid_for[k] = std::max(1, cus * std::max(1, per_cu[k]));
+    }
     if (e) {
         lbm_batch_destroy(b);
         return bfail(nullptr, LBM_ERR_HIP, std::string("batch set-up: ") + hipGetErrorString(e));
     }
-    b->grid = std::max(1, cus * std::max(1, per_cu));
+    // Two steps per launch by default with the predictor-corrector when the
+    // two-step kernel keeps at least two waves per SIMD (two 256-thread blocks
+    // per CU); with fewer it cannot hide its latency and one step is faster.
+    b->spl = (s == LBM_SCHEME_PC && per_cu[2] >= 2) ? 2 : 1;
+    b->grid = b->grid_for[b->spl];
     // zero the plate flags and the tile count
     e = hipMemsetAsync(b->d_flags(), 0, sizeof(unsigned) * max_plates, b->stream);
     if (!e) e = hipMemsetAsync(b->d_ntiles(), 0, sizeof(int), b->stream);
@@ -391,7 +413,7 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
     if (!b) return LBM_ERR_ARG;
     if (!d || !u0 || !v0 || !slot) return bfail(b, LBM_ERR_ARG, "NULL argument");
     if (d->nx < 5 || d->ny < 5) return bfail(b, LBM_ERR_ARG, "nx and ny must be >= 5");
-    if ((long long)d->nx * d->ny > (1LL << 31)) return bfail(b, LBM_ERR_UNSUPPORTED, "more than 2^31 sites");
+    if ((long long)d->nx * d->ny > (1LL << 29)) return bfail(b, LBM_ERR_UNSUPPORTED, "more than 2^29 sites");
     if (!(d->dx > 0) || !(d->rho0 > 0) || !(d->mu > 0) || !(d->lambda + d->mu > 0) || !(d->tau_over_dt > 0.5))
         return bfail(b, LBM_ERR_ARG, "invalid spacing or material");
     if (nsteps < 0) return bfail(b, LBM_ERR_ARG, "nsteps < 0");
@@ -413,7 +435,7 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
             break;
         }
     if (s < 0) return bfail(b, LBM_ERR_NOMEM, "no free plate slot");
-    const Shape sh = batch_shape(d->nx, d->ny, b->prec, b->scheme, kSegRowsMax);
+    const Shape sh = batch_shape(d->nx, d->ny, b->prec, b->scheme, seg_rows_max(b->spl), b->spl);
     const int tmax = max_plate_tiles(d->nx, d->ny, b->prec, b->scheme);
     if (b->tiles_used + tmax > b->max_tiles) return bfail(b, LBM_ERR_NOMEM, "tile table full");
     const StateLayout L = state_layout(d->nx, d->ny, b->prec);
@@ -481,17 +503,19 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     const bool tiles_changed = !b->tables_valid || run != b->running;
     if (tiles_changed) {
         // Segment height for the running set: about two tiles per block of
-        // the persistent grid, segments between kSegRowsMin and kSegRowsMax
+        // the persistent grid, segments between kSegRowsMin and seg_rows_max
         // rows (short segments keep a step short when few plates run; long
         // ones keep the halo rows few when many do).
         long long strip_rows = 0;
         for (int i : run) {
-            const Shape one = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, 1 << 30);
+            const Shape one = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, 1 << 30, b->spl);
             strip_rows += (long long)one.n_strips * b->slots[i].ny;
         }
         const long long want = 2LL * b->grid;
-        const int seg_rows = (int)std::max<long long>(kSegRowsMin, std::min<long long>(kSegRowsMax, strip_rows / want));
-        for (int i : run) b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, seg_rows);
+        const int seg_rows = (int)std::max<long long>(
+            kSegRowsMin, std::min<long long>(seg_rows_max(b->spl), strip_rows / want));
+        for (int i : run)
+            b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, seg_rows, b->spl);
     }
     int max_slot = 0;
     for (int i : run) max_slot = std::max(max_slot, i + 1);
@@ -527,8 +551,33 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         Slot &sl = b->slots[i];
         const int64_t n = std::min<int64_t>(K, sl.target - sl.done);
         sl.done += n;
-        sl.parity ^= (int)(n & 1);
+        // each launch writes the other copy once, whatever it advanced
+        sl.parity ^= (int)((b->spl == 2 ? (n + 1) / 2 : n) & 1);
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_steps_per_launch(lbm_batch *b, int k)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (k != 1 && k != 2) return bfail(b, LBM_ERR_ARG, "steps per launch must be 1 or 2");
+    if (k == 2 && b->scheme != LBM_SCHEME_PC)
+        return bfail(b, LBM_ERR_UNSUPPORTED, "two steps per launch need the predictor-corrector scheme");
+    if (k != b->spl) {
+        // the plates' shapes carry the halo of the kernel: re-plan the tiles
+        BHIP_TRY(b, hipStreamSynchronize(b->stream));
+        b->spl = k;
+        b->grid = b->grid_for[k];
+        b->tables_valid = false;
+        b->running.clear();
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_get_steps_per_launch(const lbm_batch *b, int *k)
+{
+    if (!b || !k) return LBM_ERR_ARG;
+    *k = b->spl;
     return LBM_OK;
 }
 

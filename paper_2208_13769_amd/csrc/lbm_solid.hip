@@ -178,7 +178,7 @@ lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s, 
     if (!dev_workspace) return fail(nullptr, LBM_ERR_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return fail(nullptr, LBM_ERR_ARG, "workspace not 256-byte aligned");
-    if ((long long)nx * ny > (1LL << 31)) return fail(nullptr, LBM_ERR_UNSUPPORTED, "more than 2^31 sites");
+    if ((long long)nx * ny > (1LL << 29)) return fail(nullptr, LBM_ERR_UNSUPPORTED, "more than 2^29 sites");
     const Layout L = make_layout(nx, ny, p);
     if (ws_bytes < L.total) return fail(nullptr, LBM_ERR_NOMEM, "workspace smaller than lbm_workspace_bytes()");
     lbm_solver *h = new (std::nothrow) lbm_solver();

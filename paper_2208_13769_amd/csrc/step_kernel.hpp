@@ -38,6 +38,8 @@
 // wall is folded into the source of row 0 when that row is reached.
 #pragma once
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace lbm {
@@ -65,38 +67,64 @@ struct StepParams {
     unsigned long long seed;  // key of the stochastic rounding
 };
 
+// Element e of an array through a uniform base pointer and a 32-bit byte
+// offset: the global load/store form with the base in scalar registers and
+// one vector register per address (plates have at most 2^29 sites, so the
+// byte offset of an element of any plane fits in 32 bits).
+template <class T>
+__device__ __forceinline__ T gload(const T *__restrict__ base, uint32_t e)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + e * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *__restrict__ base, uint32_t e, T v)
+{
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + e * (uint32_t)sizeof(T)) = v;
+}
+
+// A row offset the optimiser may not rewrite: an empty asm statement (no
+// instruction, no memory access) passes it through a vector register. Without
+// it, loop strength reduction turns the affine row offsets into 64-bit
+// pointer induction variables, one register pair per plane, instead of one
+// 32-bit offset shared by all planes.
+__device__ __forceinline__ uint32_t row_offset(uint32_t e)
+{
+    asm("" : "+v"(e));
+    return e;
+}
+
 // Store the nine populations of site o (plane-major), rounded to the storage
 // type to nearest or, for 16-bit storage with sr set, stochastically with the
 // bits of (key, o).
 template <class FS, class TF, class TC>
-__device__ __forceinline__ void store_site(TF *__restrict__ f, size_t plane, size_t o, const TC fn[9], TC scale,
+__device__ __forceinline__ void store_site(TF *__restrict__ f, size_t plane, uint32_t o, const TC fn[9], TC scale,
                                            bool sr, uint32_t key)
 {
     if constexpr (FS::kStochastic) {
         if (sr) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const uint32_t r = sr_bits(key, (uint32_t)o, q);
-                FS::store_sr(f, (size_t)(2 * q) * plane + o, fn[2 * q], scale, r);
-                if (q < 4) FS::store_sr(f, (size_t)(2 * q + 1) * plane + o, fn[2 * q + 1], scale, r >> 16);
+                const uint32_t r = sr_bits(key, o, q);
+                gstore(f + (size_t)(2 * q) * plane, o, FS::conv_sr(fn[2 * q], scale, r));
+                if (q < 4) gstore(f + (size_t)(2 * q + 1) * plane, o, FS::conv_sr(fn[2 * q + 1], scale, r >> 16));
             }
             return;
         }
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) FS::store(f, i * plane + o, fn[i], scale);
+    for (int i = 0; i < 9; ++i) gstore(f + (size_t)i * plane, o, FS::conv(fn[i], scale));
 }
 
 // The values store_site would write for site o, read back.
 template <class FS, class TC>
-__device__ __forceinline__ void roundtrip_site(size_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key,
+__device__ __forceinline__ void roundtrip_site(uint32_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key,
                                                TC out[9])
 {
     if constexpr (FS::kStochastic) {
         if (sr) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const uint32_t r = sr_bits(key, (uint32_t)o, q);
+                const uint32_t r = sr_bits(key, o, q);
                 out[2 * q] = FS::roundtrip_sr(fn[2 * q], scale, inv, r);
                 if (q < 4) out[2 * q + 1] = FS::roundtrip_sr(fn[2 * q + 1], scale, inv, r >> 16);
             }
@@ -193,12 +221,90 @@ struct PipeLds {
     TC wall[WALLED ? 2 : 1][3][BLOCK];
 };
 
+// Register ring of L rows of N values for a row loop unrolled by U = 4
+// (phases 0..3). Logical row k (0 = newest) is a fixed register at each phase, so a
+// push renames instead of moving: rows 0..H-1 (H = 4, 2 or 1, a divisor of
+// the unroll) rotate through H registers, and the remaining L - H rows (at
+// most 2, again a divisor) form a second rotating part fed by one move per
+// push. at<P, K> is row K after the push of phase P (P - 1 before it).
+template <int A, int M>
+struct PMod {
+    static constexpr int v = ((A % M) + M) % M;
+};
+
+template <class T, int L, int N, int U = 4>
+struct Ring {
+    static_assert(U == 4, "rotating rings need the 4-phase unroll");
+    static constexpr int H = L >= 4 ? 4 : (L >= 2 ? 2 : 1);
+    static constexpr int TL = L - H;
+    static constexpr int TS = TL > 0 ? TL : 1;
+    static_assert(TL <= 2, "ring too long for the 4-phase unroll");
+    T h[H][N];
+    T tail[TS][N];
+
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < H; ++k)
+#pragma unroll
+            for (int c = 0; c < N; ++c) h[k][c] = T(0);
+#pragma unroll
+        for (int k = 0; k < TS; ++k)
+#pragma unroll
+            for (int c = 0; c < N; ++c) tail[k][c] = T(0);
+    }
+    template <int P, int K>
+    __device__ __forceinline__ T &at(int c)
+    {
+        static_assert(K >= 0 && K < L, "ring row out of range");
+        if constexpr (K < H)
+            return h[PMod<P - K, H>::v][c];
+        else
+            return tail[PMod<P - (K - H), TS>::v][c];
+    }
+    template <int P>
+    __device__ __forceinline__ void push(int c, T v)
+    {
+        if constexpr (TL > 0) tail[PMod<P, TS>::v][c] = h[PMod<P, H>::v][c];
+        h[PMod<P, H>::v][c] = v;
+    }
+};
+
+// Without unrolling (U = 1) a push shifts the ring by one row and the phase
+// is ignored: row k is always register k.
+template <class T, int L, int N>
+struct Ring<T, L, N, 1> {
+    T h[L][N];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int k = 0; k < L; ++k)
+#pragma unroll
+            for (int c = 0; c < N; ++c) h[k][c] = T(0);
+    }
+    template <int P, int K>
+    __device__ __forceinline__ T &at(int c)
+    {
+        static_assert(K >= 0 && K < L, "ring row out of range");
+        return h[K][c];
+    }
+    template <int P>
+    __device__ __forceinline__ void push(int c, T v)
+    {
+#pragma unroll
+        for (int k = L - 1; k > 0; --k) h[k][c] = h[k - 1][c];
+        h[0][c] = v;
+    }
+};
+
 // The y-march pipeline of one time step (state n -> n+1) for one column per
 // thread. `def` runs stages D, E, F (they use only rows of earlier
 // iterations) and hands out f_{n+1} at row R-4 and (PC) u_{n+1}, j_{n+1} at
 // row R-6; `abc` takes u_n at row R and f_n, j_n at row R-2 and runs stages
-// A, B, C. Register rings: index k holds row (current stage row) - k.
-template <class PR, int BLOCK, bool PC, bool WALLED>
+// A, B, C. Both are instantiated per phase PH of the 4-way unrolled row loop
+// (iteration index = PH mod 4) or, with U = 1, not unrolled (PH = 0 and
+// shifting rings); b is the LDS buffer of the iteration (its index & 1).
+template <class PR, int BLOCK, bool PC, bool WALLED, int U = 4>
 struct Pipe {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
@@ -214,52 +320,53 @@ struct Pipe {
     const int bc_lo, bc_hi;
     const TC omega, lam, mu, bx, by;
     const double *val_lo, *val_hi;
-    TU uw_lo_n[2], uw_hi_n[2], uw_lo_p[2], uw_hi_p[2];
+    const double tn;  // step index n of the input state
 
-    TU uR[NU][2];
-    TC kA2[3][2];
-    TC sN[2][2];
-    TC jN[NJ][2];
-    TC hxCur[2], hxPrev[2];
-    TC o0[2], o2[3], o4;
-    TC n1, n3, n5[2], n6[2];
-    TC jfR[3][2];
-    TU upR[3][2];
-    TC kpA2[3][2];
-    TC hxpCur[2], hxpPrev[2];
+    // rings (row k = k rows before the stage's current row)
+    Ring<TU, NU, 2, U> uR;   // u_n, rows R .. R-NU+1 (pushed in abc)
+    Ring<TC, 3, 2, U> kA2;   // K12, K22 of rows R-1 .. R-3 (abc)
+    Ring<TC, 2, 2, U> sN;    // source S_n of rows R-2, R-3 (abc)
+    Ring<TC, NJ, 2, U> jN;   // j_n of rows R-2 .. (abc)
+    Ring<TC, 2, 2, U> hx;    // du_x/dx, du_y/dx of rows R-1, R-2 (abc)
+    Ring<TC, 2, 1, U> o0;    // own f^col_0 of rows R-2, R-3 (abc)
+    Ring<TC, 3, 1, U> o2;    // own f^col_2 of rows R-2 .. R-4 (abc)
+    TC o4;                // own f^col_4 of row R-2 (abc)
+    TC n1, n3;            // pulled f_1, f_3 of row R-3 (def)
+    Ring<TC, 2, 1, U> n5, n6;  // pulled f_5, f_6 of rows R-3, R-4 (def)
+    Ring<TC, 3, 2, U> jfR;   // first moment of f_{n+1}, rows R-4 .. R-6 (def)
+    Ring<TU, 3, 2, U> upR;   // u^p, rows R-4 .. R-6 (def)
+    Ring<TC, 3, 2, U> kpA2;  // K^p_12, K^p_22 of rows R-5 .. R-7 (def)
+    Ring<TC, 2, 2, U> hxp;   // du^p/dx of rows R-5, R-6 (def)
     bool bad;
 
     __device__ __forceinline__ Pipe(Lds &lds, const StepParams &p, long long step, int t_, int y0_, int y1_,
                                     bool out_col_)
         : L(lds), t(t_), tl(t_ > 0 ? t_ - 1 : 0), tr(t_ < BLOCK - 1 ? t_ + 1 : BLOCK - 1), ny(p.ny), y0(y0_),
           y1(y1_), out_col(out_col_), bc_lo(p.bc_lo), bc_hi(p.bc_hi), omega(TC(p.omega)), lam(TC(p.lam)),
-          mu(TC(p.mu)), bx(TC(p.bx)), by(TC(p.by)), val_lo(p.val_lo), val_hi(p.val_hi), bad(false)
+          mu(TC(p.mu)), bx(TC(p.bx)), by(TC(p.by)), val_lo(p.val_lo), val_hi(p.val_hi), tn((double)step),
+          bad(false)
     {
-        // wall displacement u_w = j* t (lattice units) at t = n and t = n+1
-        const double tn = (double)step;
-        for (int a = 0; a < 2; ++a) {
-            uw_lo_n[a] = TU(p.val_lo[a] * tn);
-            uw_hi_n[a] = TU(p.val_hi[a] * tn);
-            uw_lo_p[a] = TU(p.val_lo[a] * (tn + 1));
-            uw_hi_p[a] = TU(p.val_hi[a] * (tn + 1));
-        }
-#pragma unroll
-        for (int k = 0; k < NU; ++k) uR[k][0] = uR[k][1] = TU(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            kA2[k][0] = kA2[k][1] = jfR[k][0] = jfR[k][1] = kpA2[k][0] = kpA2[k][1] = TC(0);
-            upR[k][0] = upR[k][1] = TU(0);
-        }
-#pragma unroll
-        for (int k = 0; k < NJ; ++k) jN[k][0] = jN[k][1] = TC(0);
-        sN[0][0] = sN[0][1] = sN[1][0] = sN[1][1] = TC(0);
-        hxCur[0] = hxCur[1] = hxPrev[0] = hxPrev[1] = TC(0);
-        hxpCur[0] = hxpCur[1] = hxpPrev[0] = hxpPrev[1] = TC(0);
-        o0[0] = o0[1] = o2[0] = o2[1] = o2[2] = o4 = TC(0);
-        n1 = n3 = n5[0] = n5[1] = n6[0] = n6[1] = TC(0);
+        uR.zero();
+        kA2.zero();
+        sN.zero();
+        jN.zero();
+        hx.zero();
+        o0.zero();
+        o2.zero();
+        o4 = n1 = n3 = TC(0);
+        n5.zero();
+        n6.zero();
+        jfR.zero();
+        upR.zero();
+        kpA2.zero();
+        hxp.zero();
     }
 
     __device__ __forceinline__ bool is_node(int r) const { return !WALLED || (r >= 0 && r < ny); }
+
+    // wall displacement u_w = j* t (lattice units) at t = n + dn
+    __device__ __forceinline__ TU uw_lo(int a, int dn) const { return TU(val_lo[a] * (tn + dn)); }
+    __device__ __forceinline__ TU uw_hi(int a, int dn) const { return TU(val_hi[a] * (tn + dn)); }
 
     // ghost rows above the top wall from the two rows below it
     __device__ __forceinline__ TU ghost_hi(int which, TU a, TU b, TU uw) const
@@ -295,24 +402,26 @@ struct Pipe {
         k22 = K[3];
     }
 
-    // ---------------- stages D, E, F (rings not yet advanced this
-    // iteration: uR[k] = row R-1-k, sN[k] = row R-3-k, jN[k] = row R-3-k).
+    // ---------------- stages D, E, F. Before this iteration's pushes (phase
+    // Q = PH - 1): uR row k = R-1-k, sN row k = R-3-k, jN row k = R-3-k.
     // fn: f_{n+1} at row R-4. PC: unew, jnew at row R-6 (meaningful when
     // that row is a node). Explicit: unew, jnew at row R-4.
+    template <int PH>
     __device__ __forceinline__ void def(const int R, const int b, TC fn[9], TU unew[2], TC jnew[2])
     {
+        constexpr int Q = PH - 1;
         const int pb = b ^ 1;
         const int rD = R - 4;
         {
             const TC a1 = L.f[pb][0][tl], a3 = L.f[pb][1][tr], a5 = L.f[pb][2][tl];
             const TC a6 = L.f[pb][3][tr], a7 = L.f[pb][4][tr], a8 = L.f[pb][5][tl];
-            fn[0] = o0[1];
+            fn[0] = o0.template at<Q, 1>(0);
             fn[1] = n1;
-            fn[2] = o2[2];
+            fn[2] = o2.template at<Q, 2>(0);
             fn[3] = n3;
             fn[4] = o4;
-            fn[5] = n5[1];
-            fn[6] = n6[1];
+            fn[5] = n5.template at<Q, 1>(0);
+            fn[6] = n6.template at<Q, 1>(0);
             fn[7] = a7;
             fn[8] = a8;
             if (WALLED && rD == 0) {
@@ -325,10 +434,8 @@ struct Pipe {
                 fn[7] = L.wall[WALLED ? 1 : 0][1][t];
                 fn[8] = L.wall[WALLED ? 1 : 0][2][t];
             }
-            n5[1] = n5[0];
-            n5[0] = a5;
-            n6[1] = n6[0];
-            n6[0] = a6;
+            n5.template push<PH>(0, a5);
+            n6.template push<PH>(0, a6);
             n1 = a1;
             n3 = a3;
 
@@ -336,40 +443,33 @@ struct Pipe {
             const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
             const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
             if constexpr (PC) {
-                const TC jpx = jfx + TC(0.5) * sN[1][0];
-                const TC jpy = jfy + TC(0.5) * sN[1][1];
+                const TC jpx = jfx + TC(0.5) * sN.template at<Q, 1>(0);
+                const TC jpy = jfy + TC(0.5) * sN.template at<Q, 1>(1);
                 TU upx, upy;
                 if (nodeD) {
-                    upx = uR[3][0] + TU(TC(0.5) * (jpx + jN[1][0]));
-                    upy = uR[3][1] + TU(TC(0.5) * (jpy + jN[1][1]));
+                    upx = uR.template at<Q, 3>(0) + TU(TC(0.5) * (jpx + jN.template at<Q, 1>(0)));
+                    upy = uR.template at<Q, 3>(1) + TU(TC(0.5) * (jpy + jN.template at<Q, 1>(1)));
                 } else if (rD == ny && bc_hi != BC_PERIODIC) {
-                    upx = ghost_hi(0, upR[0][0], upR[1][0], uw_hi_p[0]);
-                    upy = ghost_hi(0, upR[0][1], upR[1][1], uw_hi_p[1]);
+                    upx = ghost_hi(0, upR.template at<Q, 0>(0), upR.template at<Q, 1>(0), uw_hi(0, 1));
+                    upy = ghost_hi(0, upR.template at<Q, 0>(1), upR.template at<Q, 1>(1), uw_hi(1, 1));
                 } else if (rD == ny + 1 && bc_hi != BC_PERIODIC) {
-                    upx = ghost_hi(1, upR[1][0], upR[2][0], uw_hi_p[0]);
-                    upy = ghost_hi(1, upR[1][1], upR[2][1], uw_hi_p[1]);
+                    upx = ghost_hi(1, upR.template at<Q, 1>(0), upR.template at<Q, 2>(0), uw_hi(0, 1));
+                    upy = ghost_hi(1, upR.template at<Q, 1>(1), upR.template at<Q, 2>(1), uw_hi(1, 1));
                 } else {
                     upx = upy = TU(0);
                 }
-#pragma unroll
-                for (int k = 2; k > 0; --k) {
-                    upR[k][0] = upR[k - 1][0];
-                    upR[k][1] = upR[k - 1][1];
-                    jfR[k][0] = jfR[k - 1][0];
-                    jfR[k][1] = jfR[k - 1][1];
-                }
-                upR[0][0] = upx;
-                upR[0][1] = upy;
-                jfR[0][0] = jfx;
-                jfR[0][1] = jfy;
+                upR.template push<PH>(0, upx);
+                upR.template push<PH>(1, upy);
+                jfR.template push<PH>(0, jfx);
+                jfR.template push<PH>(1, jfy);
                 L.up[b][0][t] = upx;
                 L.up[b][1][t] = upy;
             } else {
                 // explicit: the source at t also serves the moment step
-                jnew[0] = jfx + TC(0.5) * sN[1][0];
-                jnew[1] = jfy + TC(0.5) * sN[1][1];
-                unew[0] = uR[3][0] + TU(TC(0.5) * (jnew[0] + jN[1][0]));
-                unew[1] = uR[3][1] + TU(TC(0.5) * (jnew[1] + jN[1][1]));
+                jnew[0] = jfx + TC(0.5) * sN.template at<Q, 1>(0);
+                jnew[1] = jfy + TC(0.5) * sN.template at<Q, 1>(1);
+                unew[0] = uR.template at<Q, 3>(0) + TU(TC(0.5) * (jnew[0] + jN.template at<Q, 1>(0)));
+                unew[1] = uR.template at<Q, 3>(1) + TU(TC(0.5) * (jnew[1] + jN.template at<Q, 1>(1)));
             }
         }
 
@@ -379,39 +479,41 @@ struct Pipe {
                 TC H[4], K[4];
                 H[0] = TC((L.up[pb][0][tr] - L.up[pb][0][tl]) * TU(0.5));
                 H[2] = TC((L.up[pb][1][tr] - L.up[pb][1][tl]) * TU(0.5));
-                TU um0 = upR[2][0], um1 = upR[2][1];
+                TU um0 = upR.template at<PH, 2>(0), um1 = upR.template at<PH, 2>(1);
                 if (WALLED && R - 5 == 0) {
-                    um0 = ghost_lo(upR[1][0], upR[0][0], uw_lo_p[0]);
-                    um1 = ghost_lo(upR[1][1], upR[0][1], uw_lo_p[1]);
+                    um0 = ghost_lo(upR.template at<PH, 1>(0), upR.template at<PH, 0>(0), uw_lo(0, 1));
+                    um1 = ghost_lo(upR.template at<PH, 1>(1), upR.template at<PH, 0>(1), uw_lo(1, 1));
                 }
-                H[1] = TC((upR[0][0] - um0) * TU(0.5));
-                H[3] = TC((upR[0][1] - um1) * TU(0.5));
+                H[1] = TC((upR.template at<PH, 0>(0) - um0) * TU(0.5));
+                H[3] = TC((upR.template at<PH, 0>(1) - um1) * TU(0.5));
                 stress_sum(H, lam, mu, K);
                 L.kp[b][0][t] = K[0];
                 L.kp[b][1][t] = K[2];
-#pragma unroll
-                for (int k = 2; k > 0; --k) {
-                    kpA2[k][0] = kpA2[k - 1][0];
-                    kpA2[k][1] = kpA2[k - 1][1];
-                }
-                kpA2[0][0] = K[1];
-                kpA2[0][1] = K[3];
-                hxpPrev[0] = hxpCur[0];
-                hxpPrev[1] = hxpCur[1];
-                hxpCur[0] = H[0];
-                hxpCur[1] = H[2];
+                kpA2.template push<PH>(0, K[1]);
+                kpA2.template push<PH>(1, K[3]);
+                hxp.template push<PH>(0, H[0]);
+                hxp.template push<PH>(1, H[2]);
             }
             // ---------------- stage F: S^p at row R-6, new j and u
             const int rF = R - 6;
             if (is_node(rF)) {
-                TC k12d = kpA2[2][0], k22d = kpA2[2][1];
-                if (WALLED && rF == 0) ghost_lo_K(upR[2], upR[1], hxpPrev, hxpCur, uw_lo_p, k12d, k22d);
-                const TC Sx = bx + TC(0.5) * (L.kp[pb][0][tr] - L.kp[pb][0][tl]) + TC(0.5) * (kpA2[0][0] - k12d);
-                const TC Sy = by + TC(0.5) * (L.kp[pb][1][tr] - L.kp[pb][1][tl]) + TC(0.5) * (kpA2[0][1] - k22d);
-                jnew[0] = jfR[2][0] + TC(0.5) * Sx;
-                jnew[1] = jfR[2][1] + TC(0.5) * Sy;
-                unew[0] = uR[5 < NU ? 5 : 0][0] + TU(TC(0.5) * (jnew[0] + jN[3 < NJ ? 3 : 0][0]));
-                unew[1] = uR[5 < NU ? 5 : 0][1] + TU(TC(0.5) * (jnew[1] + jN[3 < NJ ? 3 : 0][1]));
+                TC k12d = kpA2.template at<PH, 2>(0), k22d = kpA2.template at<PH, 2>(1);
+                if (WALLED && rF == 0) {
+                    const TU u0[2] = {upR.template at<PH, 2>(0), upR.template at<PH, 2>(1)};
+                    const TU u1[2] = {upR.template at<PH, 1>(0), upR.template at<PH, 1>(1)};
+                    const TC h0[2] = {hxp.template at<PH, 1>(0), hxp.template at<PH, 1>(1)};
+                    const TC h1[2] = {hxp.template at<PH, 0>(0), hxp.template at<PH, 0>(1)};
+                    const TU uw[2] = {uw_lo(0, 1), uw_lo(1, 1)};
+                    ghost_lo_K(u0, u1, h0, h1, uw, k12d, k22d);
+                }
+                const TC Sx = bx + TC(0.5) * (L.kp[pb][0][tr] - L.kp[pb][0][tl]) +
+                              TC(0.5) * (kpA2.template at<PH, 0>(0) - k12d);
+                const TC Sy = by + TC(0.5) * (L.kp[pb][1][tr] - L.kp[pb][1][tl]) +
+                              TC(0.5) * (kpA2.template at<PH, 0>(1) - k22d);
+                jnew[0] = jfR.template at<PH, 2>(0) + TC(0.5) * Sx;
+                jnew[1] = jfR.template at<PH, 2>(1) + TC(0.5) * Sy;
+                unew[0] = uR.template at<Q, (PC ? 5 : 0)>(0) + TU(TC(0.5) * (jnew[0] + jN.template at<Q, (PC ? 3 : 0)>(0)));
+                unew[1] = uR.template at<Q, (PC ? 5 : 0)>(1) + TU(TC(0.5) * (jnew[1] + jN.template at<Q, (PC ? 3 : 0)>(1)));
             } else {
                 jnew[0] = jnew[1] = TC(0);
                 unew[0] = unew[1] = TU(0);
@@ -420,30 +522,30 @@ struct Pipe {
     }
 
     // ---------------- stages A, B, C with this iteration's inputs
+    template <int PH>
     __device__ __forceinline__ void abc(const int R, const int b, const bool nodeA, const TU ua0, const TU ua1,
                                         const bool nodeC, const TC f[9], const TC jx, const TC jy)
     {
+        constexpr int Q = PH - 1;
         const int pb = b ^ 1;
         // stage A: u_n at row R
-#pragma unroll
-        for (int k = NU - 1; k > 0; --k) {
-            uR[k][0] = uR[k - 1][0];
-            uR[k][1] = uR[k - 1][1];
-        }
+        TU un0, un1;
         if (nodeA) {
-            uR[0][0] = ua0;
-            uR[0][1] = ua1;
+            un0 = ua0;
+            un1 = ua1;
         } else if (R == ny && bc_hi != BC_PERIODIC) {
-            uR[0][0] = ghost_hi(0, uR[1][0], uR[2][0], uw_hi_n[0]);
-            uR[0][1] = ghost_hi(0, uR[1][1], uR[2][1], uw_hi_n[1]);
+            un0 = ghost_hi(0, uR.template at<Q, 0>(0), uR.template at<Q, 1>(0), uw_hi(0, 0));
+            un1 = ghost_hi(0, uR.template at<Q, 0>(1), uR.template at<Q, 1>(1), uw_hi(1, 0));
         } else if (R == ny + 1 && bc_hi != BC_PERIODIC) {
-            uR[0][0] = ghost_hi(1, uR[2][0], uR[3][0], uw_hi_n[0]);
-            uR[0][1] = ghost_hi(1, uR[2][1], uR[3][1], uw_hi_n[1]);
+            un0 = ghost_hi(1, uR.template at<Q, 1>(0), uR.template at<Q, 2>(0), uw_hi(0, 0));
+            un1 = ghost_hi(1, uR.template at<Q, 1>(1), uR.template at<Q, 2>(1), uw_hi(1, 0));
         } else {
-            uR[0][0] = uR[0][1] = TU(0);
+            un0 = un1 = TU(0);
         }
-        L.u[b][0][t] = uR[0][0];
-        L.u[b][1][t] = uR[0][1];
+        uR.template push<PH>(0, un0);
+        uR.template push<PH>(1, un1);
+        L.u[b][0][t] = un0;
+        L.u[b][1][t] = un1;
 
         // stage B: K at row R-1
         {
@@ -451,61 +553,56 @@ struct Pipe {
             H[0] = TC((L.u[pb][0][tr] - L.u[pb][0][tl]) * TU(0.5));
             H[2] = TC((L.u[pb][1][tr] - L.u[pb][1][tl]) * TU(0.5));
             const int rB = R - 1;
-            TU um0 = uR[2][0], um1 = uR[2][1];
+            TU um0 = uR.template at<PH, 2>(0), um1 = uR.template at<PH, 2>(1);
             if (WALLED && rB == 0) {
-                um0 = ghost_lo(uR[1][0], uR[0][0], uw_lo_n[0]);
-                um1 = ghost_lo(uR[1][1], uR[0][1], uw_lo_n[1]);
+                um0 = ghost_lo(uR.template at<PH, 1>(0), uR.template at<PH, 0>(0), uw_lo(0, 0));
+                um1 = ghost_lo(uR.template at<PH, 1>(1), uR.template at<PH, 0>(1), uw_lo(1, 0));
             }
-            H[1] = TC((uR[0][0] - um0) * TU(0.5));
-            H[3] = TC((uR[0][1] - um1) * TU(0.5));
+            H[1] = TC((uR.template at<PH, 0>(0) - um0) * TU(0.5));
+            H[3] = TC((uR.template at<PH, 0>(1) - um1) * TU(0.5));
             const TC J = stress_sum(H, lam, mu, K);
             if (out_col && rB >= y0 && rB < y1 && !(J > TC(0))) bad = true;
             L.k[b][0][t] = K[0];
             L.k[b][1][t] = K[2];
-#pragma unroll
-            for (int k = 2; k > 0; --k) {
-                kA2[k][0] = kA2[k - 1][0];
-                kA2[k][1] = kA2[k - 1][1];
-            }
-            kA2[0][0] = K[1];
-            kA2[0][1] = K[3];
-            hxPrev[0] = hxCur[0];
-            hxPrev[1] = hxCur[1];
-            hxCur[0] = H[0];
-            hxCur[1] = H[2];
+            kA2.template push<PH>(0, K[1]);
+            kA2.template push<PH>(1, K[3]);
+            hx.template push<PH>(0, H[0]);
+            hx.template push<PH>(1, H[2]);
         }
 
         // stage C: S_n at row R-2, collision
         const int rC = R - 2;
         TC fc[9];
-        TC k12d = kA2[2][0], k22d = kA2[2][1];
-        if (WALLED && rC == 0) ghost_lo_K(uR[2], uR[1], hxPrev, hxCur, uw_lo_n, k12d, k22d);
-        const TC Sx = bx + TC(0.5) * (L.k[pb][0][tr] - L.k[pb][0][tl]) + TC(0.5) * (kA2[0][0] - k12d);
-        const TC Sy = by + TC(0.5) * (L.k[pb][1][tr] - L.k[pb][1][tl]) + TC(0.5) * (kA2[0][1] - k22d);
-        sN[1][0] = sN[0][0];
-        sN[1][1] = sN[0][1];
-        sN[0][0] = Sx;
-        sN[0][1] = Sy;
-#pragma unroll
-        for (int k = NJ - 1; k > 0; --k) {
-            jN[k][0] = jN[k - 1][0];
-            jN[k][1] = jN[k - 1][1];
+        TC k12d = kA2.template at<PH, 2>(0), k22d = kA2.template at<PH, 2>(1);
+        if (WALLED && rC == 0) {
+            const TU u0[2] = {uR.template at<PH, 2>(0), uR.template at<PH, 2>(1)};
+            const TU u1[2] = {uR.template at<PH, 1>(0), uR.template at<PH, 1>(1)};
+            const TC h0[2] = {hx.template at<PH, 1>(0), hx.template at<PH, 1>(1)};
+            const TC h1[2] = {hx.template at<PH, 0>(0), hx.template at<PH, 0>(1)};
+            const TU uw[2] = {uw_lo(0, 0), uw_lo(1, 0)};
+            ghost_lo_K(u0, u1, h0, h1, uw, k12d, k22d);
         }
+        const TC Sx = bx + TC(0.5) * (L.k[pb][0][tr] - L.k[pb][0][tl]) + TC(0.5) * (kA2.template at<PH, 0>(0) - k12d);
+        const TC Sy = by + TC(0.5) * (L.k[pb][1][tr] - L.k[pb][1][tl]) + TC(0.5) * (kA2.template at<PH, 0>(1) - k22d);
+        sN.template push<PH>(0, Sx);
+        sN.template push<PH>(1, Sy);
         if (nodeC) {
-            jN[0][0] = jx;
-            jN[0][1] = jy;
+            jN.template push<PH>(0, jx);
+            jN.template push<PH>(1, jy);
             TC r, pxx;
             collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
             if (WALLED && rC == 0) {
                 TC w[3];
-                wall_populations(false, bc_lo, fc, val_lo, r, pxx, kA2[1][0], kA2[1][1], w);
+                wall_populations(false, bc_lo, fc, val_lo, r, pxx, kA2.template at<PH, 1>(0),
+                                 kA2.template at<PH, 1>(1), w);
                 L.wall[0][0][t] = w[0];
                 L.wall[0][1][t] = w[1];
                 L.wall[0][2][t] = w[2];
             }
             if (WALLED && rC == ny - 1) {
                 TC w[3];
-                wall_populations(true, bc_hi, fc, val_hi, r, pxx, kA2[1][0], kA2[1][1], w);
+                wall_populations(true, bc_hi, fc, val_hi, r, pxx, kA2.template at<PH, 1>(0),
+                                 kA2.template at<PH, 1>(1), w);
                 L.wall[WALLED ? 1 : 0][0][t] = w[0];
                 L.wall[WALLED ? 1 : 0][1][t] = w[1];
                 L.wall[WALLED ? 1 : 0][2][t] = w[2];
@@ -513,7 +610,8 @@ struct Pipe {
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i) fc[i] = TC(0);
-            jN[0][0] = jN[0][1] = TC(0);
+            jN.template push<PH>(0, TC(0));
+            jN.template push<PH>(1, TC(0));
         }
         L.f[b][0][t] = fc[1];
         L.f[b][1][t] = fc[3];
@@ -522,11 +620,8 @@ struct Pipe {
         L.f[b][4][t] = fc[7];
         L.f[b][5][t] = fc[8];
         // own-column collision rings of the pull
-        o2[2] = o2[1];
-        o2[1] = o2[0];
-        o2[0] = fc[2];
-        o0[1] = o0[0];
-        o0[0] = fc[0];
+        o2.template push<PH>(0, fc[2]);
+        o0.template push<PH>(0, fc[0]);
         o4 = fc[4];
     }
 };
@@ -576,10 +671,21 @@ __device__ __forceinline__ int row_store(int r, int ny)
     return r;
 }
 
-// One tile (column strip `strip`, row segment `seg`) of one plate for one
-// time step. Called by every thread of a block; ends with a barrier.
+// LDS of one pipeline (one time step of one tile)
 template <class PR, int BLOCK, bool PC, bool WALLED>
-__device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg)
+using TileLds = typename Pipe<PR, BLOCK, PC, WALLED>::Lds;
+
+template <int V>
+using Phase = std::integral_constant<int, V>;
+
+// One tile (column strip `strip`, row segment `seg`) of one plate for one
+// time step. Called by every thread of a block; ends with a barrier. The row
+// loop is unrolled by four so the register rings rotate by renaming; the row
+// count is rounded up to a multiple of four, and the extra rows lie past the
+// segment's last output row, where nothing is stored or checked.
+template <class PR, int BLOCK, bool PC, bool WALLED>
+__device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg,
+                                          TileLds<PR, BLOCK, PC, WALLED> &lds)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
@@ -588,7 +694,6 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     using FS = FStore<TF>;
     using P = Pipe<PR, BLOCK, PC, WALLED>;
     constexpr int HX = PC ? 5 : 3;
-    __shared__ typename P::Lds lds;
 
     const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
     TF *__restrict__ fout = static_cast<TF *>(p.f_out);
@@ -604,37 +709,34 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     const bool sr = FS::kStochastic && p.sr;
     const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
 
-    const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7);
-    const int Rstart = g.y0 - HX;
-    for (int it = 0; it < n_iter; ++it) {
-        const int R = Rstart + it;
-        const int b = it & 1;
+    auto row = [&](auto phase, const int R) {
+        constexpr int PH = decltype(phase)::value;
         // Loads of this iteration (u_n at row R, f_n and j_n at row R-2) are
         // issued first; stages D-F, which only use earlier rows, run while
         // they are in flight. Rows beyond a wall are clamped to a valid
         // address and their values discarded.
-        const size_t oA = (size_t)row_load<WALLED>(R, ny) * nx + g.gx;
-        const size_t oC = (size_t)row_load<WALLED>(R - 2, ny) * nx + g.gx;
-        const TU la0 = uin[oA], la1 = uin[plane + oA];
+        const uint32_t oA = row_offset((uint32_t)row_load<WALLED>(R, ny) * (uint32_t)nx + (uint32_t)g.gx);
+        const uint32_t oC = row_offset((uint32_t)row_load<WALLED>(R - 2, ny) * (uint32_t)nx + (uint32_t)g.gx);
+        const TU la0 = gload(uin, oA), la1 = gload(uin + plane, oA);
         TF lf[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
-        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
+        for (int i = 0; i < 9; ++i) lf[i] = gload(fin + (size_t)i * plane, oC);
+        const TJ lj0 = gload(jin, oC), lj1 = gload(jin + plane, oC);
 
         TC fn[9], jnew[2];
         TU unew[2];
-        pipe.def(R, b, fn, unew, jnew);
+        pipe.template def<PH>(R, PH & 1, fn, unew, jnew);
         const int rD = R - 4, rF = PC ? R - 6 : R - 4;
         if (pipe.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
-            const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
+            const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rD, ny) * (uint32_t)nx + (uint32_t)g.gx);
             store_site<FS>(fout, plane, o, fn, f_scale, sr, key);
         }
         if (pipe.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
-            const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
-            uout[o] = unew[0];
-            uout[plane + o] = unew[1];
-            jout[o] = TJ(jnew[0]);
-            jout[plane + o] = TJ(jnew[1]);
+            const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rF, ny) * (uint32_t)nx + (uint32_t)g.gx);
+            gstore(uout, o, unew[0]);
+            gstore(uout + plane, o, unew[1]);
+            gstore(jout, o, TJ(jnew[0]));
+            gstore(jout + plane, o, TJ(jnew[1]));
             if (!isfinite((double)unew[0]) || !isfinite((double)unew[1]) || !isfinite((double)jnew[0]) ||
                 !isfinite((double)jnew[1]))
                 pipe.bad = true;
@@ -643,8 +745,18 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         TC f[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
-        pipe.abc(R, b, pipe.is_node(R), la0, la1, pipe.is_node(R - 2), f, TC(lj0), TC(lj1));
+        pipe.template abc<PH>(R, PH & 1, pipe.is_node(R), la0, la1, pipe.is_node(R - 2), f, TC(lj0), TC(lj1));
         __syncthreads();
+    };
+
+    const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7);
+    const int Rstart = g.y0 - HX;
+    for (int it = 0; it < n_iter; it += 4) {
+        const int R = Rstart + it;
+        row(Phase<0>{}, R);
+        row(Phase<1>{}, R + 1);
+        row(Phase<2>{}, R + 2);
+        row(Phase<3>{}, R + 3);
     }
     if (pipe.bad) p.flag[0] = 1u;
 }
@@ -652,66 +764,55 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
 // Delay line that hands the first step's populations f_{n+1} (rows R-4 ..
 // R-7) to the second step, holding each value as the storage type would:
 // 32/64-bit storage keeps the values, 16-bit storage keeps the stored bit
-// patterns two to a word (20 registers instead of 36).
-template <class FS, class TC, bool PACKED = FS::kStochastic>
+// patterns two to a word (20 registers instead of 36). A 4-row ring: the
+// oldest row is read before the push of the same phase.
+template <class FS, class TC, int U, bool PACKED = FS::kStochastic>
 struct FDelay {
-    TC v[4][9];
-    __device__ __forceinline__ FDelay()
+    Ring<TC, 4, 9, U> v;
+    __device__ __forceinline__ FDelay() { v.zero(); }
+    template <int PH>
+    __device__ __forceinline__ void push(uint32_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key)
     {
+        TC rt[9];
+        roundtrip_site<FS>(o, fn, scale, inv, sr, key, rt);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) v[k][i] = TC(0);
+        for (int i = 0; i < 9; ++i) v.template push<PH>(i, rt[i]);
     }
-    __device__ __forceinline__ void push(size_t o, const TC fn[9], TC scale, TC inv, bool sr, uint32_t key)
+    template <int PH>
+    __device__ __forceinline__ void oldest(TC out[9], TC)
     {
 #pragma unroll
-        for (int k = 3; k > 0; --k)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) v[k][i] = v[k - 1][i];
-        roundtrip_site<FS>(o, fn, scale, inv, sr, key, v[0]);
-    }
-    __device__ __forceinline__ void oldest(TC out[9], TC) const
-    {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[i] = v[3][i];
+        for (int i = 0; i < 9; ++i) out[i] = v.template at<PH - 1, 3>(i);
     }
 };
 
-template <class FS, class TC>
-struct FDelay<FS, TC, true> {
-    uint32_t w[4][5];
-    __device__ __forceinline__ FDelay()
+template <class FS, class TC, int U>
+struct FDelay<FS, TC, U, true> {
+    Ring<uint32_t, 4, 5, U> w;
+    __device__ __forceinline__ FDelay() { w.zero(); }
+    template <int PH>
+    __device__ __forceinline__ void push(uint32_t o, const TC fn[9], TC scale, TC, bool sr, uint32_t key)
     {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int q = 0; q < 5; ++q) w[k][q] = 0u;
-    }
-    __device__ __forceinline__ void push(size_t o, const TC fn[9], TC scale, TC, bool sr, uint32_t key)
-    {
-#pragma unroll
-        for (int k = 3; k > 0; --k)
-#pragma unroll
-            for (int q = 0; q < 5; ++q) w[k][q] = w[k - 1][q];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             uint32_t lo, hi = 0u;
             if (sr) {
-                const uint32_t r = sr_bits(key, (uint32_t)o, q);
+                const uint32_t r = sr_bits(key, o, q);
                 lo = FS::bits_sr(fn[2 * q], scale, r);
                 if (q < 4) hi = FS::bits_sr(fn[2 * q + 1], scale, r >> 16);
             } else {
                 lo = FS::bits(fn[2 * q], scale);
                 if (q < 4) hi = FS::bits(fn[2 * q + 1], scale);
             }
-            w[0][q] = lo | (hi << 16);
+            w.template push<PH>(q, lo | (hi << 16));
         }
     }
-    __device__ __forceinline__ void oldest(TC out[9], TC inv) const
+    template <int PH>
+    __device__ __forceinline__ void oldest(TC out[9], TC inv)
     {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out[i] = FS::from_bits((w[3][i >> 1] >> (16 * (i & 1))) & 0xffffu, inv);
+        for (int i = 0; i < 9; ++i)
+            out[i] = FS::from_bits((w.template at<PH - 1, 3>(i >> 1) >> (16 * (i & 1))) & 0xffffu, inv);
     }
 };
 
@@ -722,16 +823,24 @@ struct FDelay<FS, TC, true> {
 // steps. Needs a halo of 10 columns and 10 rows; the halo work of the first
 // step is recomputed, never exchanged. The values handed over pass through
 // the storage precision, so the result equals two single steps bitwise.
+// Row-loop unroll of the two-step tile: 4, except with 16-bit storage, whose
+// double-precision displacement rings leave no registers for the values the
+// unrolled schedule keeps live (it would drop to one wave per SIMD).
+template <class PR>
+constexpr int step2_unroll() { return sizeof(typename PR::TF) == 2 ? 1 : 4; }
+
 template <class PR, int BLOCK, bool WALLED>
-__device__ __forceinline__ void step2_tile(const StepParams &p, const int strip, const int seg)
+__device__ __forceinline__ void step2_tile(const StepParams &p, const int strip, const int seg,
+                                           TileLds<PR, BLOCK, true, WALLED> &lds1,
+                                           TileLds<PR, BLOCK, true, WALLED> &lds2)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
     using TJ = typename PR::TJ;
     using TC = typename PR::TC;
     using FS = FStore<TF>;
-    using P = Pipe<PR, BLOCK, true, WALLED>;
-    __shared__ typename P::Lds lds1, lds2;
+    constexpr int U = step2_unroll<PR>();
+    using P = Pipe<PR, BLOCK, true, WALLED, U>;
 
     const TF *__restrict__ fin = static_cast<const TF *>(p.f_in);
     TF *__restrict__ fout = static_cast<TF *>(p.f_out);
@@ -749,45 +858,42 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
     const uint32_t key1 = sr ? sr_key(p.seed, p.step + 1) : 0u;
     const uint32_t key2 = sr ? sr_key(p.seed, p.step + 2) : 0u;
 
-    // f_{n+1} of rows R-4 .. R-7 and j_{n+1} of rows R-6, R-7 (after the shift)
-    FDelay<FS, TC> fd;
-    TC jd[2][2];
-    jd[0][0] = jd[0][1] = jd[1][0] = jd[1][1] = TC(0);
+    // f_{n+1} of rows R-4 .. R-7 and j_{n+1} of rows R-6, R-7
+    FDelay<FS, TC, U> fd;
+    Ring<TC, 2, 2, U> jd;
+    jd.zero();
 
-    const int n_iter = (g.y1 - g.y0) + 22;
-    const int Rstart = g.y0 - 10;
-    for (int it = 0; it < n_iter; ++it) {
-        const int R = Rstart + it;
-        const int b = it & 1;
-        const size_t oA = (size_t)row_load<WALLED>(R, ny) * nx + g.gx;
-        const size_t oC = (size_t)row_load<WALLED>(R - 2, ny) * nx + g.gx;
-        const TU la0 = uin[oA], la1 = uin[plane + oA];
+    auto row = [&](auto phase, const int R, const int b) {
+        constexpr int PH = decltype(phase)::value;
+        const uint32_t oA = row_offset((uint32_t)row_load<WALLED>(R, ny) * (uint32_t)nx + (uint32_t)g.gx);
+        const uint32_t oC = row_offset((uint32_t)row_load<WALLED>(R - 2, ny) * (uint32_t)nx + (uint32_t)g.gx);
+        const TU la0 = gload(uin, oA), la1 = gload(uin + plane, oA);
         TF lf[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lf[i] = fin[i * plane + oC];
-        const TJ lj0 = jin[oC], lj1 = jin[plane + oC];
+        for (int i = 0; i < 9; ++i) lf[i] = gload(fin + (size_t)i * plane, oC);
+        const TJ lj0 = gload(jin, oC), lj1 = gload(jin + plane, oC);
 
         // first step: f_{n+1} at row R-4, u_{n+1} and j_{n+1} at row R-6
         TC fn1[9], j1[2];
         TU u1[2];
-        p1.def(R, b, fn1, u1, j1);
+        p1.template def<PH>(R, b, fn1, u1, j1);
 
         // second step at row R2 = R - 6
         const int R2 = R - 6;
         TC fn2[9], j2[2];
         TU u2[2];
-        p2.def(R2, b, fn2, u2, j2);
+        p2.template def<PH>(R2, b, fn2, u2, j2);
         const int rD = R2 - 4, rF = R2 - 6;
         if (p2.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
-            const size_t o = (size_t)row_store<WALLED>(rD, ny) * nx + g.gx;
+            const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rD, ny) * (uint32_t)nx + (uint32_t)g.gx);
             store_site<FS>(fout, plane, o, fn2, f_scale, sr, key2);
         }
         if (p2.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
-            const size_t o = (size_t)row_store<WALLED>(rF, ny) * nx + g.gx;
-            uout[o] = u2[0];
-            uout[plane + o] = u2[1];
-            jout[o] = TJ(j2[0]);
-            jout[plane + o] = TJ(j2[1]);
+            const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rF, ny) * (uint32_t)nx + (uint32_t)g.gx);
+            gstore(uout, o, u2[0]);
+            gstore(uout + plane, o, u2[1]);
+            gstore(jout, o, TJ(j2[0]));
+            gstore(jout + plane, o, TJ(j2[1]));
             if (!isfinite((double)u2[0]) || !isfinite((double)u2[1]) || !isfinite((double)j2[0]) ||
                 !isfinite((double)j2[1]))
                 p2.bad = true;
@@ -795,22 +901,36 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
         // inputs of the second step: u_{n+1}(R2) now, f and j_{n+1}(R2 - 2) delayed
         {
             TC f2[9];
-            fd.oldest(f2, f_inv);
-            p2.abc(R2, b, p2.is_node(R2), u1[0], u1[1], p2.is_node(R2 - 2), f2, jd[1][0], jd[1][1]);
+            fd.template oldest<PH>(f2, f_inv);
+            p2.template abc<PH>(R2, b, p2.is_node(R2), u1[0], u1[1], p2.is_node(R2 - 2), f2,
+                                jd.template at<PH - 1, 1>(0), jd.template at<PH - 1, 1>(1));
         }
         // (the site the first step's row R-4 value belongs to, as a store would index it)
-        fd.push((size_t)row_load<WALLED>(R - 4, ny) * nx + g.gx, fn1, f_scale, f_inv, sr, key1);
-        jd[1][0] = jd[0][0];
-        jd[1][1] = jd[0][1];
-        jd[0][0] = TC(TJ(j1[0]));
-        jd[0][1] = TC(TJ(j1[1]));
+        fd.template push<PH>((uint32_t)row_load<WALLED>(R - 4, ny) * (uint32_t)nx + (uint32_t)g.gx, fn1, f_scale,
+                             f_inv, sr, key1);
+        jd.template push<PH>(0, TC(TJ(j1[0])));
+        jd.template push<PH>(1, TC(TJ(j1[1])));
 
         // first step's own inputs
         TC f[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = FS::cvt(lf[i], f_inv);
-        p1.abc(R, b, p1.is_node(R), la0, la1, p1.is_node(R - 2), f, TC(lj0), TC(lj1));
+        p1.template abc<PH>(R, b, p1.is_node(R), la0, la1, p1.is_node(R - 2), f, TC(lj0), TC(lj1));
         __syncthreads();
+    };
+
+    const int n_iter = (g.y1 - g.y0) + 22;
+    const int Rstart = g.y0 - 10;
+    if constexpr (U == 4) {
+        for (int it = 0; it < n_iter; it += 4) {
+            const int R = Rstart + it;
+            row(Phase<0>{}, R, 0);
+            row(Phase<1>{}, R + 1, 1);
+            row(Phase<2>{}, R + 2, 0);
+            row(Phase<3>{}, R + 3, 1);
+        }
+    } else {
+        for (int it = 0; it < n_iter; ++it) row(Phase<0>{}, Rstart + it, it & 1);
     }
     if (p1.bad || p2.bad) p.flag[0] = 1u;
 }
@@ -828,7 +948,8 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int logical = xcd * xq + min(xcd, xr) + loc;
     const int strip = logical / p.n_segs;
     const int seg = logical - strip * p.n_segs;
-    step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg);
+    __shared__ TileLds<PR, BLOCK, PC, WALLED> lds;
+    step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg, lds);
 }
 
 // Two steps per launch, one block per tile (same tile order as step_kernel).
@@ -842,7 +963,8 @@ __global__ void __launch_bounds__(BLOCK) step2_kernel(const StepParams p)
     const int logical = xcd * xq + min(xcd, xr) + loc;
     const int strip = logical / p.n_segs;
     const int seg = logical - strip * p.n_segs;
-    step2_tile<PR, BLOCK, WALLED>(p, strip, seg);
+    __shared__ TileLds<PR, BLOCK, true, WALLED> lds[2];
+    step2_tile<PR, BLOCK, WALLED>(p, strip, seg, lds[0], lds[1]);
 }
 
 }  // namespace lbm

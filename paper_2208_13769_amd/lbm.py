@@ -38,7 +38,8 @@ EXPORTED = [
     "lbm_resident_blocks", "lbm_set_rounding",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
-    "lbm_batch_destroy", "lbm_batch_last_error",
+    "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_set_steps_per_launch",
+    "lbm_batch_get_steps_per_launch",
 ]
 
 

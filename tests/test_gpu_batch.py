@@ -49,16 +49,20 @@ def _specs(walled):
     return specs
 
 
-@pytest.mark.parametrize("precision,walled", [("fp16", True), ("fp32", False), ("fp64", True)])
-def test_batch_equals_plates_alone(gpu, precision, walled):
+@pytest.mark.parametrize("precision,walled,spl", [("fp16", True, 2), ("fp32", False, 2), ("fp64", True, 2),
+                                                  ("fp16", True, 1), ("fp32", False, 1)])
+def test_batch_equals_plates_alone(gpu, precision, walled, spl):
     """Every plate of a mixed batch equals the same plate run alone, bitwise,
     after each of several graph-replayed chunks (eager reads in between);
-    plates with fewer steps stop at their own count."""
+    plates with fewer steps stop at their own count. Chunks of odd length and
+    odd step counts exercise the single last step of the two-step kernel."""
     from paper_2208_13769_amd.batch import Batch
 
     specs = _specs(walled)
-    targets = [60, 60, 35, 60, 50, 60]
+    targets = [60, 60, 35, 60, 51, 60]
     b = Batch(max_plates=8, arena_bytes=256 << 20, precision=precision, walled=walled)
+    b.set_steps_per_launch(spl)
+    assert b.steps_per_launch() == spl
     slots, ins = [], []
     for k, sp in enumerate(specs):
         u0, v0 = _plate_inputs(sp.nx, sp.ny, 30 + k, walled)
@@ -66,7 +70,7 @@ def test_batch_equals_plates_alone(gpu, precision, walled):
         slots.append(b.add(sp, u0, v0, targets[k]))
     assert None not in slots
     done = 0
-    for chunk in (20, 20, 20):
+    for chunk in (20, 13, 27):
         b.step(chunk)
         done += chunk
         for k, sp in enumerate(specs):
