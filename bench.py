@@ -3,7 +3,9 @@
 
 Default workload (the large-strain periodic plate): a 4096 x 4096 D2Q9 grid,
 dX = rho0 = 1, neo-Hooke lam = 0.1, mu = 0.05, tau/dt = 0.8, predictor-
-corrector source, FP32 storage and arithmetic; u0 = 0 and a seeded
+corrector source, FP32 storage and arithmetic with the displacement stored
+and accumulated in FP64 (plain FP32 misses the 1e-5 bound on P after 500
+steps; --precision fp32 runs it); u0 = 0 and a seeded
 Gaussian-filtered velocity field (sigma = 32 cells, seed 2) scaled to the
 calibrated peak velocity (tests/golden/config2_amplitude.json). A "step" is
 one time step of the whole grid; the fused step kernel advances one or two
@@ -38,9 +40,11 @@ METRIC = "MLUPS (fp64/fp32/fp16-storage) at stated error vs FP64 oracle; p50/p99
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per site per pass over the state: f (9), u (2), j (2)
 # read once and written once
-BYTES_PER_SITE_PASS = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
+BYTES_PER_SITE_PASS = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp32u64": 2 * (9 * 4 + 2 * 8 + 2 * 4),
+                       "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
                        "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
-DTYPE = {"fp64": "f64", "fp32": "f32", "fp16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
+DTYPE = {"fp64": "f64", "fp32": "f32", "fp32u64": "f32 (f64 displacement)", "fp16": "f16-storage/f32",
+         "bf16": "bf16-storage/f32"}
 
 
 def kernel_source_hash() -> str:
@@ -63,9 +67,10 @@ def workload(name: str):
     if name == "config2":
         n = 4096
         u0, v0 = inputs.filtered_random_velocity(n, n, 32.0, 2, config2_amplitude())
-        return dict(nx=n, ny=n, precision="fp32", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
+        return dict(nx=n, ny=n, precision="fp32u64", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
                     desc="periodic 4096x4096 D2Q9, neo-Hooke lam=0.1 mu=0.05, tau/dt=0.8, "
-                         "predictor-corrector, FP32; v0 Gaussian-filtered (sigma 32 cells, seed 2), "
+                         "predictor-corrector, FP32 arithmetic and storage with the displacement "
+                         "accumulated in FP64; v0 Gaussian-filtered (sigma 32 cells, seed 2), "
                          "peak strain ~0.2 within 200 steps")
     if name == "fp16-4096":
         n = 4096
@@ -208,6 +213,8 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="config2")
+    ap.add_argument("--precision", default=None,
+                    help="override the workload's precision (fp64, fp32, fp32u64, fp16, bf16)")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default="auto", help="auto | default | BLOCK,NSEGS,STEPS_PER_LAUNCH")
@@ -233,6 +240,9 @@ def main():
         bench_config4(args)
         return
     wl = workload(args.workload)
+    if args.precision:
+        wl["precision"] = args.precision
+        wl["desc"] += f" (storage form {args.precision})"
     nx, ny, prec = wl["nx"], wl["ny"], wl["precision"]
     s = lbm.Solver(nx, ny, 1.0, prec, "pc")
     s.set_material(1.0, wl["lam"], wl["mu"], wl["tau"])

@@ -60,10 +60,12 @@ typedef enum {
 /* Storage and arithmetic precision.
  * FP64: populations, displacement, momentum and arithmetic in double.
  * FP32: all in float.
+ * FP32_U64: as FP32 with the displacement stored and accumulated in double
+ *   (the accumulator of eq. (24) then adds no float rounding per step).
  * FP16_STORE / BF16_STORE: populations stored in half / bfloat16, scaled by a
  *   per-plate power of two chosen at lbm_set_fields; displacement in double,
  *   momentum in float, arithmetic in float. */
-typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_STORE = 2, LBM_BF16_STORE = 3 } lbm_precision;
+typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_STORE = 2, LBM_BF16_STORE = 3, LBM_FP32_U64 = 4 } lbm_precision;
 
 /* Rounding of 16-bit population stores. NEAREST: round to nearest even.
  * STOCHASTIC: round up or down with probability given by the distance to

@@ -30,11 +30,12 @@ inline ElemSizes elem_sizes(lbm_precision p)
     case LBM_FP32: return {4, 4, 4};
     case LBM_FP16_STORE:
     case LBM_BF16_STORE: return {2, 8, 4};
+    case LBM_FP32_U64: return {4, 8, 4};
     }
     return {0, 0, 0};
 }
 
-inline bool valid_precision(int p) { return p >= LBM_FP64 && p <= LBM_BF16_STORE; }
+inline bool valid_precision(int p) { return p >= LBM_FP64 && p <= LBM_FP32_U64; }
 
 // Offsets of the two state copies (f, u, j) of one plate from its base.
 struct StateLayout {
@@ -237,6 +238,7 @@ struct Kernels {
         case LBM_FP64: { using PR = PrecF64; return expr_with_PR; }        \
         case LBM_FP32: { using PR = PrecF32; return expr_with_PR; }        \
         case LBM_FP16_STORE: { using PR = PrecF16; return expr_with_PR; }  \
+        case LBM_FP32_U64: { using PR = PrecF32U64; return expr_with_PR; } \
         default: { using PR = PrecBF16; return expr_with_PR; }            \
         }                                                                 \
     }()

@@ -31,6 +31,7 @@ using PrecF64 = Prec<double, double, double, double>;
 using PrecF32 = Prec<float, float, float, float>;
 using PrecF16 = Prec<__half, double, float, float>;
 using PrecBF16 = Prec<__hip_bfloat16, double, float, float>;
+using PrecF32U64 = Prec<float, double, float, float>;
 
 // ---------------------------------------------------------------- rounding
 

@@ -238,6 +238,7 @@ const void *batch_kernel(lbm_precision p, bool pc, bool walled, int spl)
     case LBM_FP64: return batch_kernel_for<PrecF64>(pc, walled, spl);
     case LBM_FP32: return batch_kernel_for<PrecF32>(pc, walled, spl);
     case LBM_FP16_STORE: return batch_kernel_for<PrecF16>(pc, walled, spl);
+    case LBM_FP32_U64: return batch_kernel_for<PrecF32U64>(pc, walled, spl);
     default: return batch_kernel_for<PrecBF16>(pc, walled, spl);
     }
 }

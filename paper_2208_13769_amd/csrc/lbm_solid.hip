@@ -133,6 +133,7 @@ int resident_blocks(const lbm_solver *h, int block, int spl)
     case LBM_FP64: per_cu = Kernels<PrecF64>::resident_per_cu(block, spl, pc, walled); break;
     case LBM_FP32: per_cu = Kernels<PrecF32>::resident_per_cu(block, spl, pc, walled); break;
     case LBM_FP16_STORE: per_cu = Kernels<PrecF16>::resident_per_cu(block, spl, pc, walled); break;
+    case LBM_FP32_U64: per_cu = Kernels<PrecF32U64>::resident_per_cu(block, spl, pc, walled); break;
     default: per_cu = Kernels<PrecBF16>::resident_per_cu(block, spl, pc, walled); break;
     }
     return per_cu * cus;

@@ -823,11 +823,15 @@ struct FDelay<FS, TC, U, true> {
 // steps. Needs a halo of 10 columns and 10 rows; the halo work of the first
 // step is recomputed, never exchanged. The values handed over pass through
 // the storage precision, so the result equals two single steps bitwise.
-// Row-loop unroll of the two-step tile: 4, except with 16-bit storage, whose
-// double-precision displacement rings leave no registers for the values the
-// unrolled schedule keeps live (it would drop to one wave per SIMD).
+// Row-loop unroll of the two-step tile: 4, except with float arithmetic on a
+// double-precision displacement (16-bit storage, FP32_U64), whose double
+// rings leave no registers for the values the unrolled schedule keeps live
+// (it would drop to one wave per SIMD).
 template <class PR>
-constexpr int step2_unroll() { return sizeof(typename PR::TF) == 2 ? 1 : 4; }
+constexpr int step2_unroll()
+{
+    return (sizeof(typename PR::TU) == 8 && sizeof(typename PR::TC) == 4) ? 1 : 4;
+}
 
 template <class PR, int BLOCK, bool WALLED>
 __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip, const int seg,

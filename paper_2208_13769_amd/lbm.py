@@ -20,13 +20,14 @@ LIB_PATH = os.path.join(_HERE, "liblbm_solid.so")
 
 LBM_OK, LBM_ERR_ARG, LBM_ERR_NOMEM, LBM_ERR_HIP, LBM_ERR_STATE, LBM_ERR_UNSTABLE, LBM_ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
-LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE = 0, 1, 2, 3
+LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE, LBM_FP32_U64 = 0, 1, 2, 3, 4
 LBM_SCHEME_PC, LBM_SCHEME_EXPLICIT = 0, 1
 LBM_EDGE_XMIN, LBM_EDGE_XMAX, LBM_EDGE_YMIN, LBM_EDGE_YMAX = 0, 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_DIRICHLET_J, LBM_BC_NEUMANN_T = 0, 1, 2
 LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 
-PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_STORE, "bf16": LBM_BF16_STORE}
+PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_STORE, "bf16": LBM_BF16_STORE,
+              "fp32u64": LBM_FP32_U64}
 SCHEMES = {"pc": LBM_SCHEME_PC, "explicit": LBM_SCHEME_EXPLICIT}
 ROUNDINGS = {"nearest": LBM_ROUND_NEAREST, "stochastic": LBM_ROUND_STOCHASTIC}
 

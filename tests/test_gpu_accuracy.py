@@ -13,7 +13,14 @@ stands after 5000 steps, which is longer than the parity tests' runs:
 - stochastic rounding removes the drift (u within 1e-3 for both), but its
   zero-mean noise in u is amplified by the difference quotient in P, which
   stays at the 1e-2 (FP16) and 1e-1 (BF16) level;
-- FP32 accumulates displacement in float and reaches about 1e-4.
+- FP32 drifts the same way at the float level: about 6e-5 in u; P (1.8e-4)
+  also carries the float rounding of the accumulated displacement, which
+  FP32_U64 (double displacement) removes (P 6e-5, u unchanged).
+
+A second case is the large-strain workload at a quarter of its size: a
+1024 x 1024 periodic plate, the same calibrated peak velocity (a wave's
+strain is about v / c, whatever its length) with the Gaussian filter width
+scaled to 8 cells, 500 steps, peak Green-Lagrange strain about 0.2.
 """
 import numpy as np
 import pytest
@@ -44,8 +51,8 @@ def errors(gpu, reference):
     def rel(x, r):
         return float(np.linalg.norm(x - r) / (np.linalg.norm(r) * np.sqrt(x.shape[-2])))
 
-    for prec, rnd in [("fp64", "nearest"), ("fp32", "nearest"), ("fp16", "nearest"), ("fp16", "stochastic"),
-                      ("bf16", "nearest"), ("bf16", "stochastic")]:
+    for prec, rnd in [("fp64", "nearest"), ("fp32", "nearest"), ("fp32u64", "nearest"), ("fp16", "nearest"),
+                      ("fp16", "stochastic"), ("bf16", "nearest"), ("bf16", "stochastic")]:
         s = lbm.Solver(N, N, 1.0, prec, "pc")
         s.set_material(1.0, 0.1, 0.05, 0.8)
         s.set_rounding(rnd, 2024)
@@ -62,6 +69,7 @@ def errors(gpu, reference):
 @pytest.mark.parametrize("prec,rnd,tol_u,tol_P", [
     ("fp64", "nearest", 3e-11, 3e-11),
     ("fp32", "nearest", 3e-4, 6e-4),
+    ("fp32u64", "nearest", 1.5e-4, 1.5e-4),
     ("fp16", "nearest", 4e-2, 4e-2),
     ("fp16", "stochastic", 5e-4, 4e-2),
     ("bf16", "nearest", 0.4, 0.4),
@@ -75,3 +83,40 @@ def test_storage_precision_error_after_5000_steps(errors, prec, rnd, tol_u, tol_
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_stochastic_rounding_removes_the_drift(errors, prec):
     assert errors[prec, "stochastic"][0] < 0.1 * errors[prec, "nearest"][0]
+
+
+def _large_strain_case():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "config2_amplitude.json")
+    with open(path) as fh:
+        peak = float(json.load(fh)["peak_velocity"])
+    return inputs.filtered_random_velocity(1024, 1024, 8.0, 2, peak)
+
+
+@pytest.fixture(scope="module")
+def large_strain_reference():
+    u0, v0 = _large_strain_case()
+    u, v, P, d = oracle_run(1024, 1024, u0, v0, 500)
+    return u, v, P
+
+
+@pytest.mark.parametrize("prec,tol_u,tol_P", [("fp32", 1e-5, 2e-4), ("fp32u64", 1e-5, 1e-5)])
+def test_large_strain_500_steps(gpu, large_strain_reference, prec, tol_u, tol_P):
+    from paper_2208_13769_amd import lbm
+
+    ru, rv, rP = large_strain_reference
+    u0, v0 = _large_strain_case()
+    s = lbm.Solver(1024, 1024, 1.0, prec, "pc")
+    s.set_material(1.0, 0.1, 0.05, 0.8)
+    s.set_fields(u0, v0)
+    s.step(500)
+    u, v, P, d, st = s.read()
+    s.close()
+    assert st == 0
+    eu, ev, eP = (float(np.linalg.norm(x - r) / np.linalg.norm(r)) for x, r in ((u, ru), (v, rv), (P, rP)))
+    print(prec, "large strain 500 steps: max strain %.3f rel-L2 u %.3e v %.3e P %.3e" % (d.max_strain, eu, ev, eP),
+          flush=True)
+    assert d.max_strain > 0.1
+    assert eu < tol_u and eP < tol_P

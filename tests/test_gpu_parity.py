@@ -50,8 +50,9 @@ def test_ragged_nonlinear_fp64(gpu, scheme):
     _compare(random_case(517, 77, 7, 0.05), 60, 1e-12, 1e-12, 1e-12, scheme=scheme, lam=0.1, mu=0.05)
 
 
-def test_ragged_nonlinear_fp32(gpu):
-    _compare(random_case(517, 77, 8, 0.05), 60, 1e-5, 1e-5, precision="fp32", lam=0.1, mu=0.05)
+@pytest.mark.parametrize("precision", ["fp32", "fp32u64"])
+def test_ragged_nonlinear_fp32(gpu, precision):
+    _compare(random_case(517, 77, 8, 0.05), 60, 1e-5, 1e-5, precision=precision, lam=0.1, mu=0.05)
 
 
 def test_small_block_widths(gpu):
@@ -84,10 +85,11 @@ def test_walls_loaded_fp64(gpu, scheme):
              bc_lo=("neumann", (0.0, 0.002)), bc_hi=("dirichlet", (-0.001, 0.0)))
 
 
-def test_walls_fp32(gpu):
+@pytest.mark.parametrize("precision", ["fp32", "fp32u64"])
+def test_walls_fp32(gpu, precision):
     n = 70
     u0, v0 = inputs.top_pulse(n, 0.01)
-    _compare((u0, v0, n, n), 150, 1e-5, 1e-5, precision="fp32",
+    _compare((u0, v0, n, n), 150, 1e-5, 1e-5, precision=precision,
              bc_lo=("dirichlet", (0.0, 0.0)), bc_hi=("neumann", (0.0, 0.0)))
 
 
@@ -103,7 +105,7 @@ def test_diagnostics_match_oracle(gpu):
     assert not dg.unstable and dg.steps == 40
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32u64"])
 def test_tiling_does_not_change_results(gpu, precision):
     """Bitwise identical results for different blocks and row segmentations
     (catches halo and barrier mistakes at tile seams)."""
@@ -152,7 +154,7 @@ def test_16bit_storage_short_run(gpu, precision, tol):
 
 
 @pytest.mark.parametrize("precision,walled", [("fp32", False), ("fp32", True), ("fp16", False), ("fp16", True),
-                                              ("fp64", False)])
+                                              ("fp64", False), ("fp32u64", False), ("fp32u64", True)])
 def test_two_steps_per_launch_bitwise(gpu, precision, walled):
     """Two fused steps per launch give the single-step results bitwise, for an
     odd step count (the remainder runs as one step) and several tilings."""
