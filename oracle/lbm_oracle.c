@@ -117,6 +117,35 @@ double oracle_strain_energy(double lam, double mu, const double H[4])
     return 0.5 * mu * (IC - 2.0) + 0.25 * lam * (J * J - 1.0) - 0.5 * lam * log(J) - mu * log(J);
 }
 
+/* Cauchy stress sigma = J^-1 P F^T (Sec. 7, the stress read out at the
+ * plate-with-hole points), written out as the product of the two matrices. */
+void oracle_cauchy(double lam, double mu, const double H[4], double sig[4])
+{
+    double P[4];
+    oracle_piola(lam, mu, H, P);
+    double F[4] = {1.0 + H[0], H[1], H[2], 1.0 + H[3]};
+    double J = F[0] * F[3] - F[1] * F[2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            /* (P F^T)_ab = sum_k P_ak F_bk */
+            double s = 0.0;
+            for (int k = 0; k < 2; ++k) s += P[2 * a + k] * F[2 * b + k];
+            sig[2 * a + b] = s / J;
+        }
+}
+
+/* Green-Lagrange strain E = (F^T F - I) / 2 */
+void oracle_green_lagrange(const double H[4], double E[4])
+{
+    double F[4] = {1.0 + H[0], H[1], H[2], 1.0 + H[3]};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 2; ++k) s += F[2 * k + a] * F[2 * k + b]; /* (F^T F)_ab */
+            E[2 * a + b] = 0.5 * (s - (a == b ? 1.0 : 0.0));
+        }
+}
+
 /* Poisson stress Pbar(H) = -mu (H + H^T + tr H I), eq. (15) */
 void oracle_poisson(double mu, const double H[4], double Pb[4])
 {
@@ -514,6 +543,35 @@ int oracle_fields(const oracle_params *p, const double *u, const double *j, doub
             for (int c = 0; c < 4; ++c) P[c * N + s] = PP[c];
             v[s] = j[s] / p->rho0;
             v[N + s] = j[N + s] / p->rho0;
+        }
+    free(ue);
+    return 0;
+}
+
+/* Derived fields of the displacement: Cauchy stress sig[a][b][y][x],
+ * Green-Lagrange strain E[a][b][y][x] and strain-energy density W[y][x], all
+ * from the same central-difference H(u) as the Piola stress of
+ * oracle_fields. Any output may be NULL. */
+int oracle_derived(const oracle_params *p, const double *u, double t, double *sig, double *E, double *W)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t N = plane(p);
+    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    extend_u(p, u, t, ue);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            size_t s = at(p, y, x);
+            double H[4], T[4];
+            grad_u(p, ue, y, x, H);
+            if (sig) {
+                oracle_cauchy(p->lam, p->mu, H, T);
+                for (int c = 0; c < 4; ++c) sig[c * N + s] = T[c];
+            }
+            if (E) {
+                oracle_green_lagrange(H, T);
+                for (int c = 0; c < 4; ++c) E[c * N + s] = T[c];
+            }
+            if (W) W[s] = oracle_strain_energy(p->lam, p->mu, H);
         }
     free(ue);
     return 0;

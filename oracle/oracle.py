@@ -67,6 +67,9 @@ def lib():
         _lib.oracle_diagnostics.argtypes = [pp, dp, dp, dp, ctypes.c_double, dp]
         _lib.oracle_piola.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.oracle_poisson.argtypes = [ctypes.c_double, dp, dp]
+        _lib.oracle_cauchy.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        _lib.oracle_green_lagrange.argtypes = [dp, dp]
+        _lib.oracle_derived.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
         _lib.oracle_strain_energy.restype = ctypes.c_double
         _lib.oracle_strain_energy.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib.oracle_equilibrium.argtypes = [pp, ctypes.c_double, dp, dp, dp]
@@ -154,6 +157,16 @@ class Solver:
         lib().oracle_fields(ctypes.byref(self._pc), _ptr(self.u), _ptr(self.j), self.t, _ptr(v), _ptr(P))
         return self.u.copy(), v, P
 
+    def derived(self):
+        """Return (sigma, E, W): Cauchy stress and Green-Lagrange strain
+        [2][2][ny][nx] and strain-energy density [ny][nx], physical units."""
+        ny, nx = self.p.ny, self.p.nx
+        sig = np.zeros((2, 2, ny, nx))
+        E = np.zeros((2, 2, ny, nx))
+        W = np.zeros((ny, nx))
+        lib().oracle_derived(ctypes.byref(self._pc), _ptr(self.u), self.t, _ptr(sig), _ptr(E), _ptr(W))
+        return sig, E, W
+
     def diagnostics(self) -> dict:
         out = np.zeros(7)
         lib().oracle_diagnostics(ctypes.byref(self._pc), _ptr(self.f), _ptr(self.u), _ptr(self.j),
@@ -184,6 +197,20 @@ def poisson(mu: float, H) -> np.ndarray:
     P = np.zeros(4)
     lib().oracle_poisson(mu, _ptr(H), _ptr(P))
     return P.reshape(2, 2)
+
+
+def cauchy(lam: float, mu: float, H) -> np.ndarray:
+    H = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(4))
+    out = np.zeros(4)
+    lib().oracle_cauchy(lam, mu, _ptr(H), _ptr(out))
+    return out.reshape(2, 2)
+
+
+def green_lagrange(H) -> np.ndarray:
+    H = np.ascontiguousarray(np.asarray(H, dtype=np.float64).reshape(4))
+    out = np.zeros(4)
+    lib().oracle_green_lagrange(_ptr(H), _ptr(out))
+    return out.reshape(2, 2)
 
 
 def strain_energy(lam: float, mu: float, H) -> float:
