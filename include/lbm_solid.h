@@ -135,6 +135,24 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
  * LBM_ERR_UNSTABLE (after filling the outputs) if the unstable flag is set. */
 lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_diagnostics *d);
 
+/* Derived fields in physical units, from the same central-difference
+ * displacement gradient H(u) as P (Sec. 5): the Cauchy stress
+ * sigma = J^-1 P F^T ([4][ny][nx]: sigma11, sigma12, sigma21, sigma22; Sec. 7
+ * reads sigma12 and sigma22 out at points of the plate with a hole), the
+ * Green-Lagrange strain E = (F^T F - I) / 2 ([4][ny][nx]) and the
+ * strain-energy density W of eq. (27) ([ny][nx]). Any pointer may be NULL.
+ * Synchronises the stream. */
+lbm_status lbm_read_derived(lbm_solver *h, double *sigma, double *E, double *W);
+
+/* Values at n nodes (x[k], y[k]) (0 <= x < nx, 0 <= y < ny), for time series
+ * at chosen points (Sec. 7 plots displacements and stresses at nodes):
+ * out[n][17] = u (2), v (2), P (4), sigma (4), E (4), W, as lbm_read_fields and
+ * lbm_read_derived, physical units. n is limited by the read-out staging area
+ * (at least 460 nodes; about 120 000 for plates of 2^18 sites or more;
+ * LBM_ERR_ARG beyond it). Host
+ * arrays; synchronises the stream. */
+lbm_status lbm_sample(lbm_solver *h, int n, const int *x, const int *y, double *out);
+
 /* Launch shape of the step kernel: threads per block (64, 128, 256 or 512;
  * one lattice column per thread) and row segments per column strip
  * (1 <= n_segs <= ny). Results do not depend on it (bitwise); it only
@@ -244,6 +262,11 @@ lbm_status lbm_batch_query(lbm_batch *b, int slot, int64_t *steps_done, int64_t 
 
 /* Fields and diagnostics of a plate, as lbm_read_fields. Synchronises. */
 lbm_status lbm_batch_read(lbm_batch *b, int slot, double *u, double *v, double *P, lbm_diagnostics *d);
+
+/* Derived fields and node samples of a plate, as lbm_read_derived and
+ * lbm_sample. Synchronise. */
+lbm_status lbm_batch_read_derived(lbm_batch *b, int slot, double *sigma, double *E, double *W);
+lbm_status lbm_batch_sample(lbm_batch *b, int slot, int n, const int *x, const int *y, double *out);
 
 /* Free a plate's slot, arena space and tiles. Synchronises the stream. */
 lbm_status lbm_batch_retire(lbm_batch *b, int slot);

@@ -60,6 +60,11 @@ def _lib():
         lib.lbm_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.lbm_batch_destroy.restype = None
         lib.lbm_batch_destroy.argtypes = [vp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.lbm_batch_read_derived.restype = ctypes.c_int
+        lib.lbm_batch_read_derived.argtypes = [vp, ctypes.c_int, dp, dp, dp]
+        lib.lbm_batch_sample.restype = ctypes.c_int
+        lib.lbm_batch_sample.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, ip, dp]
         lib.lbm_batch_set_steps_per_launch.restype = ctypes.c_int
         lib.lbm_batch_set_steps_per_launch.argtypes = [vp, ctypes.c_int]
         lib.lbm_batch_get_steps_per_launch.restype = ctypes.c_int
@@ -142,6 +147,19 @@ def lbm_batch_read(h, slot, u=None, v=None, P=None, diag=None) -> int:
     if st not in (lbm.LBM_OK, lbm.LBM_ERR_UNSTABLE):
         _check(st, h)
     return st
+
+
+def lbm_batch_read_derived(h, slot, sigma=None, E=None, W=None):
+    _check(_lib().lbm_batch_read_derived(h, slot, _dptr(sigma), _dptr(E), _dptr(W)), h)
+
+
+def lbm_batch_sample(h, slot, xs, ys) -> np.ndarray:
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    out = np.empty((len(xs), 17))
+    ip = ctypes.POINTER(ctypes.c_int)
+    _check(_lib().lbm_batch_sample(h, slot, len(xs), xs.ctypes.data_as(ip), ys.ctypes.data_as(ip), _dptr(out)), h)
+    return out
 
 
 def lbm_batch_retire(h, slot):
@@ -255,6 +273,15 @@ class Batch:
         diag = lbm.Diagnostics(np.array(d.momentum[:]), d.mass_moment, d.energy, d.min_J, d.max_strain,
                                bool(d.unstable), int(d.steps))
         return u, v, P, diag, st
+
+    def read_derived(self, slot):
+        sp = self.specs[slot]
+        sig, E, W = np.empty((2, 2, sp.ny, sp.nx)), np.empty((2, 2, sp.ny, sp.nx)), np.empty((sp.ny, sp.nx))
+        lbm_batch_read_derived(self.h, slot, sig, E, W)
+        return sig, E, W
+
+    def sample(self, slot, xs, ys):
+        return lbm_batch_sample(self.h, slot, xs, ys)
 
     def retire(self, slot):
         lbm_batch_retire(self.h, slot)

@@ -140,13 +140,23 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
 struct ReadParams {
     FieldParams fp;
     const void *u, *j;
-    double *out;        // staging: [8][rows][nx] = u (2), v (2), P (4)
-    int y_begin, rows;
+    double *out;        // staging: [values][count]
+    int y_begin;        // first row of a row read (nodes == nullptr)
+    const int *nodes;   // or: site indices y * nx + x of the nodes sampled
+    int count;          // sites read: rows * nx, or the number of nodes
+    int what;           // bit 0: u (2), v (2), P (4); bit 1: sigma (4), E (4), W (1)
     double dx;          // u = dX u_L
     double c;           // v = c j_L
-    double stress;      // P = rho0 c^2 P_L
+    double stress;      // P, sigma, W = rho0 c^2 (lattice value)
 };
 
+// Read-out of fields at sites, in physical units, from the central-difference
+// gradient H(u) (Sec. 5):
+//   P     first Piola-Kirchhoff stress (eq. (27));
+//   sigma Cauchy stress, in the left Cauchy-Green form of the neo-Hooke law,
+//         sigma = (mu / J)(F F^T - I) + lam (J^2 - 1) / (2 J) I;
+//   E     Green-Lagrange strain (F^T F - I) / 2;
+//   W     strain-energy density of eq. (27).
 template <class PR>
 __global__ void __launch_bounds__(256) readout_kernel(const ReadParams p)
 {
@@ -154,23 +164,51 @@ __global__ void __launch_bounds__(256) readout_kernel(const ReadParams p)
     using TJ = typename PR::TJ;
     const FieldParams &fp = p.fp;
     const size_t pl = (size_t)fp.plane;
-    const long long n = (long long)fp.nx * p.rows;
-    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int yl = (int)(s / fp.nx), x = (int)(s - (long long)yl * fp.nx);
-    const int y = p.y_begin + yl;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= p.count) return;
+    int x, y;
+    if (p.nodes) {
+        const int g = p.nodes[s];
+        y = g / fp.nx;
+        x = g - y * fp.nx;
+    } else {
+        const int yl = s / fp.nx;
+        x = s - yl * fp.nx;
+        y = p.y_begin + yl;
+    }
     const TU *u = static_cast<const TU *>(p.u);
     const TJ *j = static_cast<const TJ *>(p.j);
     const size_t g = (size_t)y * fp.nx + x;
-    double H[4], P[4];
+    double H[4];
     grad_at(u, fp, x, y, H);
-    piola<double>(H, fp.lam, fp.mu, P);
-    const size_t cp = (size_t)p.rows * fp.nx;
-    p.out[0 * cp + s] = (double)u[g] * p.dx;
-    p.out[1 * cp + s] = (double)u[pl + g] * p.dx;
-    p.out[2 * cp + s] = (double)j[g] * p.c;
-    p.out[3 * cp + s] = (double)j[pl + g] * p.c;
-    for (int c = 0; c < 4; ++c) p.out[(4 + c) * cp + s] = P[c] * p.stress;
+    const size_t cp = (size_t)p.count;
+    int k = 0;
+    if (p.what & 1) {
+        double P[4];
+        piola<double>(H, fp.lam, fp.mu, P);
+        p.out[k++ * cp + s] = (double)u[g] * p.dx;
+        p.out[k++ * cp + s] = (double)u[pl + g] * p.dx;
+        p.out[k++ * cp + s] = (double)j[g] * p.c;
+        p.out[k++ * cp + s] = (double)j[pl + g] * p.c;
+        for (int c = 0; c < 4; ++c) p.out[k++ * cp + s] = P[c] * p.stress;
+    }
+    if (p.what & 2) {
+        const double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
+        const double J = F11 * F22 - F12 * F21;
+        // left Cauchy-Green B = F F^T and right C = F^T F
+        const double B11 = F11 * F11 + F12 * F12, B12 = F11 * F21 + F12 * F22, B22 = F21 * F21 + F22 * F22;
+        const double C11 = F11 * F11 + F21 * F21, C12 = F11 * F12 + F21 * F22, C22 = F12 * F12 + F22 * F22;
+        const double a = fp.mu / J, d = fp.lam * (J * J - 1.0) / (2.0 * J);
+        const double sg[4] = {a * (B11 - 1.0) + d, a * B12, a * B12, a * (B22 - 1.0) + d};
+        for (int c = 0; c < 4; ++c) p.out[k++ * cp + s] = sg[c] * p.stress;
+        p.out[k++ * cp + s] = 0.5 * (C11 - 1.0);
+        p.out[k++ * cp + s] = 0.5 * C12;
+        p.out[k++ * cp + s] = 0.5 * C12;
+        p.out[k++ * cp + s] = 0.5 * (C22 - 1.0);
+        const double lj = log(J);
+        const double W = 0.5 * fp.mu * (C11 + C22 - 2.0) + 0.25 * fp.lam * (J * J - 1.0) - 0.5 * fp.lam * lj - fp.mu * lj;
+        p.out[k++ * cp + s] = W * p.stress;
+    }
 }
 
 // ---------------------------------------------------------------- diagnostics

@@ -248,7 +248,9 @@ constexpr size_t kStagingCap = size_t(16) << 20;  // bytes of read-out staging a
 
 inline size_t staging_bytes_for(int nx, int ny)
 {
-    return std::min(8 * (size_t)nx * ny * sizeof(double), std::max(kStagingCap, 8 * (size_t)nx * sizeof(double)));
+    // 8 doubles per site, at most 16 MiB (one row at least), at least 64 KiB
+    const size_t want = std::min(8 * (size_t)nx * ny * sizeof(double), std::max(kStagingCap, 9 * (size_t)nx * sizeof(double)));
+    return std::max(want, size_t(64) << 10);
 }
 
 // Everything needed to start, read and diagnose one plate's state.
@@ -319,42 +321,92 @@ inline hipError_t plate_start(const PlateIO &io, const double *u0, const double 
 
 // u, v, P (any may be NULL) and diagnostics (out7 may be NULL) of a plate
 // after t_steps steps. Synchronises.
-inline hipError_t plate_read(const PlateIO &io, double t_steps, double *u, double *v, double *P, double *out7)
+// Values of read-out kind `what` (1: u, v, P; 2: sigma, E, W) of every site,
+// copied into the host planes dst[0 .. nv-1] ([ny][nx] each, NULL skips a
+// plane) through the staging area in row chunks. Synchronises.
+inline hipError_t plate_rows(const PlateIO &io, double t_steps, int what, double *const *dst, int nv)
 {
     const int nx = io.nx, ny = io.ny;
-    const size_t n = (size_t)nx * ny;
+    ReadParams rp{};
+    rp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+    rp.u = io.u;
+    rp.j = io.j;
+    rp.out = io.staging;
+    rp.nodes = nullptr;
+    rp.what = what;
+    rp.dx = io.U.dx;
+    rp.c = io.U.c();
+    rp.stress = io.U.stress();
+    const int rows_per =
+        (int)std::max<size_t>(1, std::min<size_t>(ny, io.staging_bytes / (nv * sizeof(double) * nx)));
+    hipError_t e;
+    for (int y = 0; y < ny; y += rows_per) {
+        const int rows = std::min(rows_per, ny - y);
+        rp.y_begin = y;
+        rp.count = rows * nx;
+        const size_t cnt = (size_t)rows * nx;
+        if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::readout(rp, (int)((cnt + 255) / 256), io.stream)))) return e;
+        for (int k = 0; k < nv; ++k) {
+            if (!dst[k]) continue;
+            if ((e = hipMemcpyAsync(dst[k] + (size_t)y * nx, rp.out + k * cnt, cnt * sizeof(double),
+                                    hipMemcpyDeviceToHost, io.stream)))
+                return e;
+        }
+        if ((e = hipStreamSynchronize(io.stream))) return e;
+    }
+    return hipSuccess;
+}
+
+// Nodes one sample call can read through the staging area.
+inline int sample_capacity(const PlateIO &io)
+{
+    return (int)std::min<size_t>(1 << 20, (io.staging_bytes - 256) / (17 * sizeof(double) + sizeof(int)));
+}
+
+// u, v, P, sigma, E, W (17 values) at the nodes (x[k], y[k]) into out[n][17].
+// The caller has checked the nodes and n <= sample_capacity(io). Synchronises.
+inline hipError_t plate_sample(const PlateIO &io, double t_steps, int n, const int *xs, const int *ys, double *out)
+{
+    if (n == 0) return hipSuccess;
+    std::vector<int> idx(n);
+    for (int k = 0; k < n; ++k) idx[k] = ys[k] * io.nx + xs[k];
+    int *d_idx = reinterpret_cast<int *>(io.staging);
+    double *vals = io.staging + align_up((size_t)n * sizeof(int)) / sizeof(double);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d_idx, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, io.stream))) return e;
+    ReadParams rp{};
+    rp.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+    rp.u = io.u;
+    rp.j = io.j;
+    rp.out = vals;
+    rp.nodes = d_idx;
+    rp.count = n;
+    rp.what = 3;
+    rp.dx = io.U.dx;
+    rp.c = io.U.c();
+    rp.stress = io.U.stress();
+    if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::readout(rp, (n + 255) / 256, io.stream)))) return e;
+    std::vector<double> tmp((size_t)17 * n);
+    if ((e = hipMemcpyAsync(tmp.data(), vals, tmp.size() * sizeof(double), hipMemcpyDeviceToHost, io.stream)))
+        return e;
+    if ((e = hipStreamSynchronize(io.stream))) return e;
+    for (int k = 0; k < n; ++k)
+        for (int c = 0; c < 17; ++c) out[(size_t)k * 17 + c] = tmp[(size_t)c * n + k];
+    return hipSuccess;
+}
+
+inline hipError_t plate_read(const PlateIO &io, double t_steps, double *u, double *v, double *P, double *out7)
+{
+    const size_t n = (size_t)io.nx * io.ny;
     hipError_t e;
     if (u || v || P) {
-        ReadParams rp{};
-        rp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
-        rp.u = io.u;
-        rp.j = io.j;
-        rp.out = io.staging;
-        rp.dx = io.U.dx;
-        rp.c = io.U.c();
-        rp.stress = io.U.stress();
-        const int rows_per =
-            (int)std::max<size_t>(1, std::min<size_t>(ny, io.staging_bytes / (8 * sizeof(double) * nx)));
-        for (int y = 0; y < ny; y += rows_per) {
-            const int rows = std::min(rows_per, ny - y);
-            rp.y_begin = y;
-            rp.rows = rows;
-            const size_t cnt = (size_t)rows * nx;
-            if ((e = LBM_DISPATCH(io.prec, Kernels<PR>::readout(rp, (int)((cnt + 255) / 256), io.stream)))) return e;
-            double *dst[8] = {u, u ? u + n : nullptr, v, v ? v + n : nullptr,
-                              P, P ? P + n : nullptr, P ? P + 2 * n : nullptr, P ? P + 3 * n : nullptr};
-            for (int k = 0; k < 8; ++k) {
-                if (!dst[k]) continue;
-                if ((e = hipMemcpyAsync(dst[k] + (size_t)y * nx, rp.out + k * cnt, cnt * sizeof(double),
-                                        hipMemcpyDeviceToHost, io.stream)))
-                    return e;
-            }
-            if ((e = hipStreamSynchronize(io.stream))) return e;
-        }
+        double *dst[8] = {u, u ? u + n : nullptr, v, v ? v + n : nullptr,
+                          P, P ? P + n : nullptr, P ? P + 2 * n : nullptr, P ? P + 3 * n : nullptr};
+        if ((e = plate_rows(io, t_steps, 1, dst, 8))) return e;
     }
     if (out7) {
         DiagParams dp{};
-        dp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+        dp.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
         dp.f = io.f;
         dp.u = io.u;
         dp.j = io.j;
@@ -373,6 +425,16 @@ inline hipError_t plate_read(const PlateIO &io, double t_steps, double *u, doubl
         if ((e = hipStreamSynchronize(io.stream))) return e;
     }
     return hipSuccess;
+}
+
+// sigma [4][ny][nx], E [4][ny][nx], W [ny][nx]; any may be NULL. Synchronises.
+inline hipError_t plate_read_derived(const PlateIO &io, double t_steps, double *sig, double *E, double *W)
+{
+    if (!sig && !E && !W) return hipSuccess;
+    const size_t n = (size_t)io.nx * io.ny;
+    double *dst[9] = {sig, sig ? sig + n : nullptr, sig ? sig + 2 * n : nullptr, sig ? sig + 3 * n : nullptr,
+                      E,   E ? E + n : nullptr,     E ? E + 2 * n : nullptr,     E ? E + 3 * n : nullptr, W};
+    return plate_rows(io, t_steps, 2, dst, 9);
 }
 
 }  // namespace lbm

@@ -622,6 +622,30 @@ lbm_status lbm_batch_read(lbm_batch *b, int slot, double *u, double *v, double *
     return LBM_OK;
 }
 
+lbm_status lbm_batch_read_derived(lbm_batch *b, int slot, double *sigma, double *E, double *W)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (slot < 0 || slot >= b->max_plates || !b->slots[slot].live) return bfail(b, LBM_ERR_ARG, "no such plate");
+    const hipError_t e = plate_read_derived(b->io(slot), (double)b->slots[slot].done, sigma, E, W);
+    if (e) return bhip(b, e, "read-out");
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_sample(lbm_batch *b, int slot, int n, const int *x, const int *y, double *out)
+{
+    if (!b) return LBM_ERR_ARG;
+    if (slot < 0 || slot >= b->max_plates || !b->slots[slot].live) return bfail(b, LBM_ERR_ARG, "no such plate");
+    if (n < 0 || (n > 0 && (!x || !y || !out))) return bfail(b, LBM_ERR_ARG, "invalid node list");
+    const Slot &sl = b->slots[slot];
+    const PlateIO io = b->io(slot);
+    if (n > sample_capacity(io)) return bfail(b, LBM_ERR_ARG, "too many nodes for one call");
+    for (int k = 0; k < n; ++k)
+        if (x[k] < 0 || x[k] >= sl.nx || y[k] < 0 || y[k] >= sl.ny) return bfail(b, LBM_ERR_ARG, "node outside the plate");
+    const hipError_t e = plate_sample(io, (double)sl.done, n, x, y, out);
+    if (e) return bhip(b, e, "sample");
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_retire(lbm_batch *b, int slot)
 {
     if (!b) return LBM_ERR_ARG;

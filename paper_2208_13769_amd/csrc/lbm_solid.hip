@@ -416,6 +416,29 @@ lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_d
     return LBM_OK;
 }
 
+lbm_status lbm_read_derived(lbm_solver *h, double *sigma, double *E, double *W)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (!h->fields) return fail(h, LBM_ERR_STATE, "no fields set");
+    const hipError_t e = plate_read_derived(h->io(), (double)h->steps, sigma, E, W);
+    if (e != hipSuccess) return hip_fail(h, e, "read-out");
+    return LBM_OK;
+}
+
+lbm_status lbm_sample(lbm_solver *h, int n, const int *x, const int *y, double *out)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (!h->fields) return fail(h, LBM_ERR_STATE, "no fields set");
+    if (n < 0 || (n > 0 && (!x || !y || !out))) return fail(h, LBM_ERR_ARG, "invalid node list");
+    const PlateIO io = h->io();
+    if (n > sample_capacity(io)) return fail(h, LBM_ERR_ARG, "too many nodes for one call");
+    for (int k = 0; k < n; ++k)
+        if (x[k] < 0 || x[k] >= h->nx || y[k] < 0 || y[k] >= h->ny) return fail(h, LBM_ERR_ARG, "node outside the plate");
+    const hipError_t e = plate_sample(io, (double)h->steps, n, x, y, out);
+    if (e != hipSuccess) return hip_fail(h, e, "sample");
+    return LBM_OK;
+}
+
 void lbm_destroy(lbm_solver *h) { delete h; }
 
 const char *lbm_last_error(const lbm_solver *h) { return h ? h->err.c_str() : g_create_error.c_str(); }

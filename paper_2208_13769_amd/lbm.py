@@ -36,7 +36,8 @@ EXPORTED = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_material", "lbm_set_body_force", "lbm_set_boundary",
     "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
     "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
-    "lbm_resident_blocks", "lbm_set_rounding",
+    "lbm_resident_blocks", "lbm_set_rounding", "lbm_read_derived", "lbm_sample", "lbm_batch_read_derived",
+    "lbm_batch_sample",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
     "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_set_steps_per_launch",
@@ -93,6 +94,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_step.argtypes = [vp, ctypes.c_int64]
     lib.lbm_read_fields.restype = ctypes.c_int
     lib.lbm_read_fields.argtypes = [vp, dp, dp, dp, ctypes.POINTER(lbm_diagnostics)]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.lbm_read_derived.restype = ctypes.c_int
+    lib.lbm_read_derived.argtypes = [vp, dp, dp, dp]
+    lib.lbm_sample.restype = ctypes.c_int
+    lib.lbm_sample.argtypes = [vp, ctypes.c_int, ip, ip, dp]
     lib.lbm_get_dt.restype = ctypes.c_int
     lib.lbm_get_dt.argtypes = [vp, dp]
     lib.lbm_destroy.restype = None
@@ -163,6 +169,27 @@ def lbm_set_fields(h, u0, v0):
 
 def lbm_step(h, nsteps: int):
     _check(load_library().lbm_step(h, int(nsteps)), h)
+
+
+SAMPLE_FIELDS = ("u_x", "u_y", "v_x", "v_y", "P11", "P12", "P21", "P22", "sigma11", "sigma12", "sigma21",
+                 "sigma22", "E11", "E12", "E21", "E22", "W")
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def lbm_read_derived(h, sigma=None, E=None, W=None):
+    _check(load_library().lbm_read_derived(h, _dptr(sigma), _dptr(E), _dptr(W)), h)
+
+
+def lbm_sample(h, xs, ys) -> np.ndarray:
+    """[n][17] values at the nodes (xs[k], ys[k]); columns as SAMPLE_FIELDS."""
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    out = np.empty((len(xs), 17))
+    _check(load_library().lbm_sample(h, len(xs), _iptr(xs), _iptr(ys), _dptr(out)), h)
+    return out
 
 
 def lbm_read_fields(h, u=None, v=None, P=None, diag: lbm_diagnostics | None = None) -> int:
@@ -299,6 +326,33 @@ class Solver:
     @property
     def dt(self) -> float:
         return lbm_get_dt(self.h)
+
+    def read_derived(self):
+        """Return (sigma, E, W): Cauchy stress and Green-Lagrange strain
+        [2][2][ny][nx] and strain-energy density [ny][nx]."""
+        ny, nx = self.ny, self.nx
+        sig, E, W = np.empty((2, 2, ny, nx)), np.empty((2, 2, ny, nx)), np.empty((ny, nx))
+        lbm_read_derived(self.h, sig, E, W)
+        return sig, E, W
+
+    def sample(self, xs, ys) -> np.ndarray:
+        return lbm_sample(self.h, xs, ys)
+
+    def sample_series(self, xs, ys, nsteps: int, every: int):
+        """Advance nsteps, sampling the nodes before the first step and after
+        every `every` steps: returns (steps since the call [m], values
+        [m][n][17])."""
+        steps, vals = [], []
+        done = 0
+        while True:
+            steps.append(done)
+            vals.append(self.sample(xs, ys))
+            if done >= nsteps:
+                break
+            k = min(every, nsteps - done)
+            self.step(k)
+            done += k
+        return np.array(steps), np.array(vals)
 
     def read(self, want_fields: bool = True):
         """Return (u, v, P, Diagnostics, status)."""
