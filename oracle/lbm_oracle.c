@@ -44,8 +44,15 @@
  * inside a component: f[i][y][x] with i in the oracle's own D2Q9 order
  * i = 3*(ey+1) + (ex+1), u[a][y][x], j[a][y][x], P[a][b][y][x] (a,b in {x,y}).
  *
- * The x direction is periodic. The y edges are periodic, momentum walls or
- * traction walls.
+ * Every edge is periodic (in pairs), a momentum wall or a traction wall.
+ *  Q20 Corners (both edges walls): the diagonal link that leaves a corner
+ *      node through both walls takes the rule of the momentum wall if one
+ *      of the two is a momentum wall (the mean j* if both are); between two
+ *      traction walls it is anti-bounced with a boundary Poisson tensor
+ *      whose normal entries come from the two walls' traction transforms
+ *      and whose off-diagonal entry is the mean of the two walls' values.
+ *      Ghost displacements beyond a corner are extrapolated across the x
+ *      wall from the ghost rows.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -65,6 +72,8 @@ typedef struct {
     int scheme;         /* 0: predictor-corrector (R2), 1: explicit (Alg. 1) */
     int bc_ymin, bc_ymax;        /* ORACLE_* kind of the bottom / top edge */
     double val_ymin[2], val_ymax[2]; /* j* (Dirichlet) or T* (Neumann) */
+    int bc_xmin, bc_xmax;        /* ORACLE_* kind of the left / right edge */
+    double val_xmin[2], val_xmax[2];
 } oracle_params;
 
 /* ---- D2Q9 lattice (Sec. 3): 9 velocities incl. the rest velocity ---- */
@@ -200,82 +209,96 @@ static size_t at(const oracle_params *p, int y, int x) { return (size_t)y * p->n
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
 static size_t plane(const oracle_params *p) { return (size_t)p->nx * p->ny; }
 
-/* Ghost displacement rows (Q11). ue holds rows -2..ny+1 (ny+4 rows), so row y
- * of the lattice is row y+2 of ue. t is the time at which u is taken; a
- * momentum wall with value j* has moved by j* t / rho0 (it starts at rest). */
+/* Extended grids: the displacement with two ghost rows and columns on every
+ * side, (ny + 4) rows of (nx + 4) values, lattice node (y, x) at (y + 2,
+ * x + 2); the stress sum with one, (ny + 2) x (nx + 2), node at (y + 1, x + 1). */
+static size_t ue_cols(const oracle_params *p) { return (size_t)p->nx + 4; }
+static size_t ue_plane(const oracle_params *p) { return ue_cols(p) * ((size_t)p->ny + 4); }
+static size_t ue_at(const oracle_params *p, int a, int y, int x)
+{
+    return (size_t)a * ue_plane(p) + (size_t)(y + 2) * ue_cols(p) + (size_t)(x + 2);
+}
+static size_t k_cols(const oracle_params *p) { return (size_t)p->nx + 2; }
+static size_t k_plane(const oracle_params *p) { return k_cols(p) * ((size_t)p->ny + 2); }
+static size_t k_at(const oracle_params *p, int c, int y, int x)
+{
+    return (size_t)c * k_plane(p) + (size_t)(y + 1) * k_cols(p) + (size_t)(x + 1);
+}
+
+/* Ghost value k = 1 or 2 spacings beyond the node u0 next to a wall (u1 the
+ * one after it, Q11): at a momentum wall the quadratic through the wall
+ * displacement uw (half a spacing beyond u0), u0 and u1; at a traction wall
+ * the value u0. */
+static double ghost(int kind, double uw, double u0, double u1, int k)
+{
+    if (kind == ORACLE_DIRICHLET_J)
+        return k == 1 ? (8.0 / 3.0) * uw - 2.0 * u0 + u1 / 3.0 : 8.0 * uw - 9.0 * u0 + 2.0 * u1;
+    return u0;
+}
+
+/* Ghost displacements (Q11, Q20) around the lattice. t is the time at which
+ * u is taken; a momentum wall with value j* has moved by j* t / rho0 (it
+ * starts at rest). Periodic edges copy the opposite side. */
 static void extend_u(const oracle_params *p, const double *u, double t, double *ue)
 {
     int nx = p->nx, ny = p->ny;
-    size_t eplane = (size_t)nx * (ny + 4);
     for (int a = 0; a < 2; ++a) {
         const double *ua = u + a * plane(p);
-        double *ea = ue + a * eplane;
         for (int y = 0; y < ny; ++y)
-            memcpy(ea + (size_t)(y + 2) * nx, ua + (size_t)y * nx, sizeof(double) * nx);
-        for (int x = 0; x < nx; ++x) {
-            double u0 = ua[at(p, 0, x)], u1 = ua[at(p, 1, x)];
-            double v0 = ua[at(p, ny - 1, x)], v1 = ua[at(p, ny - 2, x)];
-            double *lo1 = ea + (size_t)1 * nx + x, *lo2 = ea + x;           /* rows -1, -2 */
-            double *hi1 = ea + (size_t)(ny + 2) * nx + x, *hi2 = ea + (size_t)(ny + 3) * nx + x; /* ny, ny+1 */
-            /* bottom edge */
-            if (p->bc_ymin == ORACLE_PERIODIC) {
-                *lo1 = ua[at(p, ny - 1, x)];
-                *lo2 = ua[at(p, ny - 2, x)];
-            } else if (p->bc_ymin == ORACLE_DIRICHLET_J) {
-                /* quadratic through (y=-1/2, uw), (0, u0), (1, u1) */
-                double uw = p->val_ymin[a] * t / p->rho0;
-                *lo1 = (8.0 / 3.0) * uw - 2.0 * u0 + u1 / 3.0;
-                *lo2 = 8.0 * uw - 9.0 * u0 + 2.0 * u1;
-            } else {
-                /* traction wall: constant extrapolation of the first row */
-                *lo1 = u0;
-                *lo2 = u0;
+            for (int x = 0; x < nx; ++x) ue[ue_at(p, a, y, x)] = ua[at(p, y, x)];
+        /* ghost rows of the lattice columns */
+        double uwlo = p->val_ymin[a] * t / p->rho0, uwhi = p->val_ymax[a] * t / p->rho0;
+        for (int x = 0; x < nx; ++x)
+            for (int k = 1; k <= 2; ++k) {
+                if (p->bc_ymin == ORACLE_PERIODIC) {
+                    ue[ue_at(p, a, -k, x)] = ua[at(p, ny - k, x)];
+                    ue[ue_at(p, a, ny - 1 + k, x)] = ua[at(p, k - 1, x)];
+                } else {
+                    ue[ue_at(p, a, -k, x)] = ghost(p->bc_ymin, uwlo, ua[at(p, 0, x)], ua[at(p, 1, x)], k);
+                    ue[ue_at(p, a, ny - 1 + k, x)] =
+                        ghost(p->bc_ymax, uwhi, ua[at(p, ny - 1, x)], ua[at(p, ny - 2, x)], k);
+                }
             }
-            /* top edge */
-            if (p->bc_ymax == ORACLE_PERIODIC) {
-                *hi1 = ua[at(p, 0, x)];
-                *hi2 = ua[at(p, 1, x)];
-            } else if (p->bc_ymax == ORACLE_DIRICHLET_J) {
-                double uw = p->val_ymax[a] * t / p->rho0;
-                *hi1 = (8.0 / 3.0) * uw - 2.0 * v0 + v1 / 3.0;
-                *hi2 = 8.0 * uw - 9.0 * v0 + 2.0 * v1;
-            } else {
-                *hi1 = v0;
-                *hi2 = v0;
+        /* ghost columns of every extended row (corners included) */
+        double uwl = p->val_xmin[a] * t / p->rho0, uwr = p->val_xmax[a] * t / p->rho0;
+        for (int y = -2; y < ny + 2; ++y)
+            for (int k = 1; k <= 2; ++k) {
+                if (p->bc_xmin == ORACLE_PERIODIC) {
+                    ue[ue_at(p, a, y, -k)] = ue[ue_at(p, a, y, nx - k)];
+                    ue[ue_at(p, a, y, nx - 1 + k)] = ue[ue_at(p, a, y, k - 1)];
+                } else {
+                    ue[ue_at(p, a, y, -k)] = ghost(p->bc_xmin, uwl, ue[ue_at(p, a, y, 0)], ue[ue_at(p, a, y, 1)], k);
+                    ue[ue_at(p, a, y, nx - 1 + k)] =
+                        ghost(p->bc_xmax, uwr, ue[ue_at(p, a, y, nx - 1)], ue[ue_at(p, a, y, nx - 2)], k);
+                }
             }
-        }
     }
 }
 
 /* displacement gradient H_ab = d_b u_a by central differences (eq. (10),
- * Sec. 5), at lattice row y (may be -1 or ny) from the extended field. */
+ * Sec. 5), at lattice node (y, x) with -1 <= y <= ny, -1 <= x <= nx. */
 static void grad_u(const oracle_params *p, const double *ue, int y, int x, double H[4])
 {
-    int nx = p->nx, ny = p->ny;
-    size_t eplane = (size_t)nx * (ny + 4);
-    int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
     for (int a = 0; a < 2; ++a) {
-        const double *ea = ue + a * eplane;
-        double dudx = (ea[(size_t)(y + 2) * nx + xp] - ea[(size_t)(y + 2) * nx + xm]) / (2.0 * p->dx);
-        double dudy = (ea[(size_t)(y + 3) * nx + x] - ea[(size_t)(y + 1) * nx + x]) / (2.0 * p->dx);
+        double dudx = (ue[ue_at(p, a, y, x + 1)] - ue[ue_at(p, a, y, x - 1)]) / (2.0 * p->dx);
+        double dudy = (ue[ue_at(p, a, y + 1, x)] - ue[ue_at(p, a, y - 1, x)]) / (2.0 * p->dx);
         H[2 * a + 0] = dudx;
         H[2 * a + 1] = dudy;
     }
 }
 
-/* K = P(H) + Pbar(H) on rows -1..ny (ny+2 rows; row y at index y+1). */
+/* K = P(H) + Pbar(H) on the lattice and one ring of ghost nodes */
 static void stress_sum(const oracle_params *p, const double *ue, double *K)
 {
     int nx = p->nx, ny = p->ny;
-    size_t kplane = (size_t)nx * (ny + 2);
 #pragma omp parallel for schedule(static)
     for (int y = -1; y <= ny; ++y)
-        for (int x = 0; x < nx; ++x) {
+        for (int x = -1; x <= nx; ++x) {
             double H[4], P[4], Pb[4];
             grad_u(p, ue, y, x, H);
             oracle_piola(p->lam, p->mu, H, P);
             oracle_poisson(p->mu, H, Pb);
-            for (int c = 0; c < 4; ++c) K[c * kplane + (size_t)(y + 1) * nx + x] = P[c] + Pb[c];
+            for (int c = 0; c < 4; ++c) K[k_at(p, c, y, x)] = P[c] + Pb[c];
         }
 }
 
@@ -283,27 +306,22 @@ static void stress_sum(const oracle_params *p, const double *ue, double *K)
 static void source_field(const oracle_params *p, const double *K, double *S)
 {
     int nx = p->nx, ny = p->ny;
-    size_t kplane = (size_t)nx * (ny + 2);
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) {
-            int xp = wrap(x + 1, nx), xm = wrap(x - 1, nx);
+        for (int x = 0; x < nx; ++x)
             for (int a = 0; a < 2; ++a) {
-                const double *Ka1 = K + (2 * a + 0) * kplane; /* K_a1 */
-                const double *Ka2 = K + (2 * a + 1) * kplane; /* K_a2 */
-                double div = (Ka1[(size_t)(y + 1) * nx + xp] - Ka1[(size_t)(y + 1) * nx + xm]) / (2.0 * p->dx)
-                           + (Ka2[(size_t)(y + 2) * nx + x] - Ka2[(size_t)y * nx + x]) / (2.0 * p->dx);
+                /* K_a1 at the x neighbours, K_a2 at the y neighbours */
+                double div = (K[k_at(p, 2 * a + 0, y, x + 1)] - K[k_at(p, 2 * a + 0, y, x - 1)]) / (2.0 * p->dx)
+                           + (K[k_at(p, 2 * a + 1, y + 1, x)] - K[k_at(p, 2 * a + 1, y - 1, x)]) / (2.0 * p->dx);
                 S[a * plane(p) + at(p, y, x)] = p->rho0 * p->body[a] + div;
             }
-        }
 }
 
 /* source 1S(u) at time t for the whole lattice */
 static void source_of_u(const oracle_params *p, const double *u, double t, double *S)
 {
-    int nx = p->nx, ny = p->ny;
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
-    double *K = malloc(sizeof(double) * 4 * (size_t)nx * (ny + 2));
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
+    double *K = malloc(sizeof(double) * 4 * k_plane(p));
     extend_u(p, u, t, ue);
     stress_sum(p, ue, K);
     source_field(p, K, S);
@@ -327,29 +345,51 @@ static void moments_r_pi(const oracle_params *p, const double *f, size_t s, doub
     }
 }
 
-/* Boundary moments at a traction wall (Sec. 6, eq. (26) and the traction
- * transform): r_bd and Pbar* for column x. The wall lies half a spacing
- * beyond row y0; s is the outward normal sign. Every quantity is extrapolated
- * to the wall at zeroth order, i.e. taken from row y0 (reading Q11). */
-static void traction_wall_moments(const oracle_params *p, const double *f, const double *K,
-                                  int y0, int x, double s, const double T[2],
+/* Traction transform at a wall (Sec. 6) for node (y, x) next to it: the
+ * wall normal is axis n (0: x, 1: y) with outward sign s, T the traction.
+ * Pbar N = -T* + (P + Pbar) N gives the wall's normal column of the boundary
+ * Poisson tensor, q_a = Pbar*_an = (-T_a + K_an s) / s, with K = P + Pbar
+ * taken at the node (zeroth-order extrapolation, reading Q11). */
+static void traction_column(const oracle_params *p, const double *K, int y, int x, int n, double s,
+                            const double T[2], double q[2])
+{
+    for (int a = 0; a < 2; ++a) q[a] = (-T[a] + K[k_at(p, 2 * a + n, y, x)] * s) / s;
+}
+
+/* Boundary moments r_bd and Pbar* for the anti-bounce-back rule (26) at node
+ * (y, x): walls across axis x (sx = -1 or +1, 0 if none) and axis y (sy).
+ * In the wall frame the normal row and column take the transformed
+ * tractions (the tensor is symmetric); a tangential entry keeps the
+ * populations' moment Pi at the node. At a corner the normal entries come
+ * from the two walls and the off-diagonal is the mean of both (Q20). */
+static void traction_wall_moments(const oracle_params *p, const double *f, const double *K, int y, int x,
+                                  int sx, const double Tx[2], int sy, const double Ty[2],
                                   double *rbd, double Pstar[4])
 {
-    int nx = p->nx;
-    size_t kplane = (size_t)nx * (p->ny + 2);
-    double r0, Pi0[4], Kw[4];
-    moments_r_pi(p, f, at(p, y0, x), &r0, Pi0);
+    double r0, Pi0[4], qx[2], qy[2];
+    moments_r_pi(p, f, at(p, y, x), &r0, Pi0);
     *rbd = r0;
-    for (int c = 0; c < 4; ++c) Kw[c] = K[c * kplane + (size_t)(y0 + 1) * nx + x];
-    /* Pbar N = -T* + (P + Pbar) N with N = (0, s): Pbar_a2 s = -T_a + K_a2 s.
-     * In the wall frame the normal row and column take these values (the
-     * tensor is symmetric); the tangential entry keeps the moment Pi_11. */
-    double q1 = (-T[0] + Kw[1] * s) / s;
-    double q2 = (-T[1] + Kw[3] * s) / s;
     Pstar[0] = Pi0[0];
-    Pstar[1] = q1;
-    Pstar[2] = q1;
-    Pstar[3] = q2;
+    Pstar[1] = Pi0[1];
+    Pstar[2] = Pi0[2];
+    Pstar[3] = Pi0[3];
+    if (sx && sy) {
+        traction_column(p, K, y, x, 0, (double)sx, Tx, qx);
+        traction_column(p, K, y, x, 1, (double)sy, Ty, qy);
+        Pstar[0] = qx[0];
+        Pstar[3] = qy[1];
+        Pstar[1] = Pstar[2] = 0.5 * (qx[1] + qy[0]);
+    } else if (sy) {
+        traction_column(p, K, y, x, 1, (double)sy, Ty, qy);
+        Pstar[1] = qy[0];
+        Pstar[2] = qy[0];
+        Pstar[3] = qy[1];
+    } else {
+        traction_column(p, K, y, x, 0, (double)sx, Tx, qx);
+        Pstar[0] = qx[0];
+        Pstar[1] = qx[1];
+        Pstar[2] = qx[1];
+    }
 }
 
 /* anti-bounce-back value (eq. (26)) for outgoing direction i */
@@ -371,14 +411,21 @@ static double bb_term(const oracle_params *p, int i, const double jstar[2])
     return -2.0 / cs2(p) * weight(i) * (C[0] * jstar[0] + C[1] * jstar[1]);
 }
 
+/* Periodic edges come in pairs. */
+static int edges_valid(const oracle_params *p)
+{
+    return (p->bc_xmin == ORACLE_PERIODIC) == (p->bc_xmax == ORACLE_PERIODIC) &&
+           (p->bc_ymin == ORACLE_PERIODIC) == (p->bc_ymax == ORACLE_PERIODIC);
+}
+
 /* Initialisation (Algorithm 1): r0 = -rho0 div u0 (eq. (18)), j0 = rho0 v0,
  * Pbar0 = Pbar(H(u0)) (eq. (15)), f = f^eq(r0, j0, Pbar0) (eq. (20)). */
 int oracle_init(const oracle_params *p, const double *u0, const double *v0,
                 double *f, double *u, double *j)
 {
     int nx = p->nx, ny = p->ny;
-    if (nx < 5 || ny < 5) return -1;
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    if (nx < 5 || ny < 5 || !edges_valid(p)) return -1;
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     extend_u(p, u0, 0.0, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -408,8 +455,8 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
     size_t N = plane(p);
     double dt = oracle_dt(p), t = step * dt;
     double omega = 1.0 / p->tau_over_dt; /* dt / tau */
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
-    double *K = malloc(sizeof(double) * 4 * (size_t)nx * (ny + 2));
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
+    double *K = malloc(sizeof(double) * 4 * k_plane(p));
     double *S = malloc(sizeof(double) * 2 * N);
     double *fcol = malloc(sizeof(double) * 9 * N);
     double *fnew = malloc(sizeof(double) * 9 * N);
@@ -443,35 +490,47 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
         for (int y = 0; y < ny; ++y) {
             int yt = y + ey;
             if (yt < 0 || yt >= ny) {
-                int wall_kind = yt < 0 ? p->bc_ymin : p->bc_ymax;
-                if (wall_kind != ORACLE_PERIODIC) continue;
+                if (p->bc_ymin != ORACLE_PERIODIC) continue;
                 yt = wrap(yt, ny);
             }
-            for (int x = 0; x < nx; ++x)
-                fnew[i * N + at(p, yt, wrap(x + ex, nx))] = fcol[i * N + at(p, y, x)];
+            for (int x = 0; x < nx; ++x) {
+                int xt = x + ex;
+                if (xt < 0 || xt >= nx) {
+                    if (p->bc_xmin != ORACLE_PERIODIC) continue;
+                    xt = wrap(xt, nx);
+                }
+                fnew[i * N + at(p, yt, xt)] = fcol[i * N + at(p, y, x)];
+            }
         }
     }
 
-    /* 4. boundary rules at the walls (Sec. 6, eqs. (25), (26)) */
-    for (int side = 0; side < 2; ++side) {
-        int kind = side == 0 ? p->bc_ymin : p->bc_ymax;
-        if (kind == ORACLE_PERIODIC) continue;
-        int y0 = side == 0 ? 0 : ny - 1;        /* node row next to the wall */
-        int eyout = side == 0 ? -1 : 1;         /* e_y of the links that leave through the wall */
-        const double *val = side == 0 ? p->val_ymin : p->val_ymax;
-        for (int x = 0; x < nx; ++x) {
-            double rbd = 0.0, Pstar[4] = {0, 0, 0, 0};
-            if (kind == ORACLE_NEUMANN_T)
-                traction_wall_moments(p, f, K, y0, x, (double)eyout, val, &rbd, Pstar);
+    /* 4. boundary rules (Sec. 6, eqs. (25), (26)): a link that would leave
+     * through a wall returns into the opposite direction at the same node */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 9; ++i) {
-                if (ey_of(i) != eyout) continue;
-                double fc = fcol[i * N + at(p, y0, x)];
-                double v = kind == ORACLE_DIRICHLET_J ? fc + bb_term(p, i, val)
-                                                      : -fc + abb_term(p, i, rbd, Pstar);
-                fnew[opposite(i) * N + at(p, y0, x)] = v;
+                int ex = ex_of(i), ey = ey_of(i);
+                int sx = 0, sy = 0; /* walls the link crosses (outward sign) */
+                if ((x + ex < 0 || x + ex >= nx) && p->bc_xmin != ORACLE_PERIODIC) sx = ex;
+                if ((y + ey < 0 || y + ey >= ny) && p->bc_ymin != ORACLE_PERIODIC) sy = ey;
+                if (!sx && !sy) continue;
+                int kx = sx < 0 ? p->bc_xmin : p->bc_xmax, ky = sy < 0 ? p->bc_ymin : p->bc_ymax;
+                const double *vx = sx < 0 ? p->val_xmin : p->val_xmax;
+                const double *vy = sy < 0 ? p->val_ymin : p->val_ymax;
+                double fc = fcol[i * N + at(p, y, x)], v;
+                int dir_x = sx && kx == ORACLE_DIRICHLET_J, dir_y = sy && ky == ORACLE_DIRICHLET_J;
+                if (dir_x || dir_y) {
+                    double js[2];
+                    for (int a = 0; a < 2; ++a)
+                        js[a] = (dir_x && dir_y) ? 0.5 * (vx[a] + vy[a]) : (dir_x ? vx[a] : vy[a]);
+                    v = fc + bb_term(p, i, js);
+                } else {
+                    double rbd, Pstar[4];
+                    traction_wall_moments(p, f, K, y, x, sx, vx, sy, vy, &rbd, Pstar);
+                    v = -fc + abb_term(p, i, rbd, Pstar);
+                }
+                fnew[opposite(i) * N + at(p, y, x)] = v;
             }
-        }
-    }
 
     /* 5. first moment of the streamed populations, jf = sum_i C_i f_i */
 #pragma omp parallel for schedule(static)
@@ -521,7 +580,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
 
 int oracle_step(const oracle_params *p, double *f, double *u, double *j, long step0, int nsteps)
 {
-    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5) return -1;
+    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p)) return -1;
     for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, step0 + n);
     return 0;
 }
@@ -532,7 +591,7 @@ int oracle_fields(const oracle_params *p, const double *u, const double *j, doub
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     extend_u(p, u, t, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -556,7 +615,7 @@ int oracle_derived(const oracle_params *p, const double *u, double t, double *si
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     extend_u(p, u, t, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -586,7 +645,7 @@ int oracle_diagnostics(const oracle_params *p, const double *f, const double *u,
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
-    double *ue = malloc(sizeof(double) * 2 * (size_t)nx * (ny + 4));
+    double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     extend_u(p, u, t, ue);
     double sj0 = 0, sj1 = 0, sr = 0, en = 0, minJ = INFINITY, maxE = 0;
     int bad = 0;

@@ -13,6 +13,7 @@ tau/dt, body force b. Fields are numpy arrays laid out as ``u[a, y, x]``,
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -47,6 +48,8 @@ class _Params(ctypes.Structure):
         ("scheme", ctypes.c_int),
         ("bc_ymin", ctypes.c_int), ("bc_ymax", ctypes.c_int),
         ("val_ymin", ctypes.c_double * 2), ("val_ymax", ctypes.c_double * 2),
+        ("bc_xmin", ctypes.c_int), ("bc_xmax", ctypes.c_int),
+        ("val_xmin", ctypes.c_double * 2), ("val_xmax", ctypes.c_double * 2),
     ]
 
 
@@ -100,6 +103,10 @@ class Params:
     bc_ymax: int = PERIODIC
     val_ymin: tuple = (0.0, 0.0)
     val_ymax: tuple = (0.0, 0.0)
+    bc_xmin: int = PERIODIC
+    bc_xmax: int = PERIODIC
+    val_xmin: tuple = (0.0, 0.0)
+    val_xmax: tuple = (0.0, 0.0)
 
     def c(self) -> _Params:
         p = _Params()
@@ -111,6 +118,9 @@ class Params:
         p.bc_ymin, p.bc_ymax = self.bc_ymin, self.bc_ymax
         p.val_ymin[0], p.val_ymin[1] = self.val_ymin
         p.val_ymax[0], p.val_ymax[1] = self.val_ymax
+        p.bc_xmin, p.bc_xmax = self.bc_xmin, self.bc_xmax
+        p.val_xmin[0], p.val_xmin[1] = self.val_xmin
+        p.val_xmax[0], p.val_xmax[1] = self.val_xmax
         return p
 
 
@@ -148,6 +158,12 @@ class Solver:
         if rc != 0:
             raise ValueError("oracle_step rejected the parameters")
         self.step_index += int(n)
+
+    def set_boundary_value(self, edge: str, value):
+        """New j* or T* of an edge ("xmin", "xmax", "ymin", "ymax") from the
+        next step on (a load history applied step by step)."""
+        self.p = dataclasses.replace(self.p, **{"val_" + edge: tuple(value)})
+        self._pc = self.p.c()
 
     def fields(self):
         """Return (u, v, P) in physical units."""
