@@ -102,6 +102,11 @@ typedef struct {
  * (two copies of the state plus staging and reduction scratch). */
 size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p);
 
+/* Device bytes a plate needs when it may have walls on its x edges (or run
+ * the general passes): lbm_workspace_bytes plus the scratch fields of the
+ * passes (about 19 values per site). */
+size_t lbm_workspace_bytes_walled(int nx, int ny, lbm_precision p);
+
 /* Create a handle. nx, ny >= 5; dx > 0. dev_workspace: device memory of
  * ws_bytes >= lbm_workspace_bytes(nx, ny, p) bytes, 256-byte aligned.
  * hip_stream: a hipStream_t (NULL = the default stream). */
@@ -115,10 +120,16 @@ lbm_status lbm_set_material(lbm_solver *h, double rho0, double lambda, double mu
 /* Uniform body force per unit mass b (the rho0 b term of eq. (23)). */
 lbm_status lbm_set_body_force(lbm_solver *h, const double b[2]);
 
-/* Boundary rule of one edge. Periodic edges come in pairs. This build
- * supports periodic x edges only (LBM_ERR_UNSUPPORTED otherwise); the y
- * edges take any rule. value may be NULL for LBM_BC_PERIODIC. Takes effect
- * from the next lbm_step (so a load history can be applied step by step). */
+/* Boundary rule of one edge. Periodic edges come in pairs (making one edge
+ * of a periodic pair a wall turns the other into a momentum wall at rest
+ * until it is set). value may be NULL for LBM_BC_PERIODIC. Takes effect from
+ * the next lbm_step, so a load history can be applied step by step.
+ * Walls on the x edges run the general passes (walls and corners on every
+ * edge) and need a workspace of lbm_workspace_bytes_walled() bytes
+ * (LBM_ERR_NOMEM otherwise). At a corner of two walls the diagonal link takes
+ * the momentum wall's rule if either wall is one (the mean j* if both are);
+ * between two traction walls it is anti-bounced with both walls' transformed
+ * tractions, the off-diagonal entry being their mean. */
 lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double value[2]);
 
 /* Initial displacement u0 and velocity v0 (host, [2][ny][nx], physical
@@ -175,6 +186,12 @@ lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k);
  * most this many blocks runs in a single wave of blocks; n_segs can be
  * chosen with it. Writes 0 for a shape the handle cannot launch. */
 lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_launch, int *blocks);
+
+/* Run every step as the general per-site passes (1) or, when no x edge is a
+ * wall, as the fused step kernel (0, the default). The passes give the same
+ * results up to rounding; they exist for walls on the x edges and are
+ * slower. Needs a workspace of lbm_workspace_bytes_walled() bytes. */
+lbm_status lbm_set_general_path(lbm_solver *h, int on);
 
 /* Rounding of the populations written by later steps (the start state of
  * lbm_set_fields always rounds to nearest). STOCHASTIC needs FP16_STORE or

@@ -11,18 +11,19 @@ namespace lbm {
 struct FieldParams {
     int nx, ny;
     long long plane;
-    int bc_lo, bc_hi;
+    int bc_lo, bc_hi;           // y edges
     double uw_lo[2], uw_hi[2];  // wall displacement of momentum walls (lattice units)
+    int bc_left, bc_right;      // x edges
+    double uw_left[2], uw_right[2];
     double lam, mu;             // lattice units
 };
 
-// Displacement at (x, y) in lattice units, with the ghost-row rules of the
-// y walls for y = -1 and y = ny (x periodic, y periodic if bc_lo is).
+// Displacement of node (x, y), 0 <= x < nx, in lattice units, with the
+// ghost-row rules of the y walls for y = -1 and y = ny.
 template <class TU>
-__device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, int y)
+__device__ inline double u_row(const TU *u, const FieldParams &p, int a, int x, int y)
 {
     const size_t pl = (size_t)p.plane;
-    x = (x % p.nx + p.nx) % p.nx;
     if (p.bc_lo == BC_PERIODIC) {
         y = (y % p.ny + p.ny) % p.ny;
         return (double)u[a * pl + (size_t)y * p.nx + x];
@@ -37,6 +38,22 @@ __device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, i
     const double v1 = (double)u[a * pl + (size_t)(p.ny - 2) * p.nx + x];
     if (p.bc_hi == BC_NEUMANN) return v0;
     return 8.0 / 3.0 * p.uw_hi[a] - 2.0 * v0 + v1 / 3.0;
+}
+
+// Displacement at (x, y), -1 <= x <= nx, -1 <= y <= ny: beyond an x wall the
+// ghost column is extrapolated across the wall from the row values of the
+// two nearest columns (ghost rows included), as the y walls do for rows.
+template <class TU>
+__device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, int y)
+{
+    if (x >= 0 && x < p.nx) return u_row(u, p, a, x, y);
+    if (p.bc_left == BC_PERIODIC) return u_row(u, p, a, (x % p.nx + p.nx) % p.nx, y);
+    const bool left = x < 0;
+    const int kind = left ? p.bc_left : p.bc_right;
+    const double u0 = u_row(u, p, a, left ? 0 : p.nx - 1, y);
+    if (kind == BC_NEUMANN) return u0;
+    const double u1 = u_row(u, p, a, left ? 1 : p.nx - 2, y);
+    return 8.0 / 3.0 * (left ? p.uw_left[a] : p.uw_right[a]) - 2.0 * u0 + u1 / 3.0;
 }
 
 template <class TU>
@@ -85,6 +102,7 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
                 // reuse the ghost rules on the staged double array (walls at rest at t = 0)
                 FieldParams q = fp;
                 q.uw_lo[0] = q.uw_lo[1] = q.uw_hi[0] = q.uw_hi[1] = 0.0;
+                q.uw_left[0] = q.uw_left[1] = q.uw_right[0] = q.uw_right[1] = 0.0;
                 return u_at(p.u0, q, a, xx, yy) * p.inv_dx;
             };
             H[2 * a + 0] = 0.5 * (U(x + 1, y) - U(x - 1, y));

@@ -1,0 +1,382 @@
+// general_kernels.hpp -- the time step as plain per-site passes, for plates
+// with walls on any edge (Sec. 6), corners included.
+//
+// The fused step kernel marches rows with a register/LDS pipeline whose x
+// halo is periodic; walls on the x edges need ghost columns and wall rules
+// in every stage, which that pipeline cannot hold without extra barriers.
+// These kernels do one time step in four or five launches over full fields
+// instead (one thread per site):
+//   1. K = P + Pbar on the lattice and one ring of ghost nodes, from u_n and
+//      its ghost values (stress_pass);
+//   2. source S_n (central divergence of K), moments, equilibrium and BGK
+//      collision into f_col (collide_pass);
+//   3. pull streaming; a link whose source lies beyond a wall takes the
+//      wall's rule instead; moments jf of the new populations and the
+//      predictor u^p (stream_pass);
+//   4. K of u^p at t + dt (stress_pass again), then S^p, j_{n+1} and
+//      u_{n+1} (update_pass). The explicit scheme stops after pass 3.
+// Same lattice units, arithmetic and storage rounding as the fused kernel.
+#pragma once
+
+#include "step_kernel.hpp"
+
+namespace lbm {
+
+enum : int { EDGE_XMIN = 0, EDGE_XMAX = 1, EDGE_YMIN = 2, EDGE_YMAX = 3 };
+
+struct GenParams {
+    const void *f_in, *u_in, *j_in;  // state n
+    void *f_out, *u_out, *j_out;     // state n + 1
+    int nx, ny;
+    long long plane;
+    double omega, lam, mu, bx, by;  // lattice units
+    int bc[4];                      // rule of each edge (BC_*), EDGE_* order
+    double val[4][2];               // j* or T* of each edge, lattice units
+    double f_scale, f_inv_scale;
+    long long step;                 // index n of the input state
+    int sr;
+    unsigned long long seed;
+    int pc;                         // predictor-corrector (1) or explicit (0)
+    void *K;     // scratch [4][ny + 2][nx + 2] TC: stress sum with one ghost ring
+    void *fcol;  // scratch [9][ny][nx] TC: post-collision populations
+    void *S;     // scratch [2][ny][nx] TC: source S_n
+    void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
+    void *up;    // scratch [2][ny][nx] TU: predictor displacement
+    unsigned *flag;
+};
+
+// D2Q9 of this implementation (see lattice.hpp)
+__device__ constexpr int kGx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kGy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kGopp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <class TC>
+__device__ __forceinline__ TC gweight(int i)
+{
+    return i == 0 ? TC(4.0 / 9.0) : (i < 5 ? TC(1.0 / 9.0) : TC(1.0 / 36.0));
+}
+
+// Ghost value k = 1 or 2 spacings beyond a wall from the node next to it
+// (a) and the one after it (b): the quadratic through the wall displacement
+// uw of a momentum wall, the value a at a traction wall.
+template <class TU>
+__device__ __forceinline__ TU gen_ghost(int kind, TU uw, TU a, TU b, int k)
+{
+    if (kind == BC_NEUMANN) return a;
+    return k == 1 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
+}
+
+// wall displacement of edge e at step t (lattice units)
+template <class TU>
+__device__ __forceinline__ TU gen_uw(const GenParams &p, int e, int a, double t)
+{
+    return TU(p.val[e][a] * t);
+}
+
+// u of column x (0 <= x < nx) at row y (-2 <= y <= ny + 1): ghost rows of
+// the y walls, or the periodic image
+template <class TU>
+__device__ __forceinline__ TU gen_u_row(const TU *u, const GenParams &p, int a, int x, int y, double t)
+{
+    const size_t pl = (size_t)p.plane;
+    if (y >= 0 && y < p.ny) return u[a * pl + (size_t)y * p.nx + x];
+    if (p.bc[EDGE_YMIN] == BC_PERIODIC) {
+        y = (y % p.ny + p.ny) % p.ny;
+        return u[a * pl + (size_t)y * p.nx + x];
+    }
+    const bool lo = y < 0;
+    const int e = lo ? EDGE_YMIN : EDGE_YMAX;
+    const int k = lo ? -y : y - (p.ny - 1);
+    const TU u0 = u[a * pl + (size_t)(lo ? 0 : p.ny - 1) * p.nx + x];
+    const TU u1 = u[a * pl + (size_t)(lo ? 1 : p.ny - 2) * p.nx + x];
+    return gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, a, t), u0, u1, k);
+}
+
+// u at (x, y) within two spacings of the lattice: ghost columns of the x
+// walls are extrapolated across the wall from the rows' values (ghost rows
+// included), so corner ghosts come from the ghost rows
+template <class TU>
+__device__ __forceinline__ TU gen_u(const TU *u, const GenParams &p, int a, int x, int y, double t)
+{
+    if (x >= 0 && x < p.nx) return gen_u_row(u, p, a, x, y, t);
+    if (p.bc[EDGE_XMIN] == BC_PERIODIC) return gen_u_row(u, p, a, (x % p.nx + p.nx) % p.nx, y, t);
+    const bool lo = x < 0;
+    const int e = lo ? EDGE_XMIN : EDGE_XMAX;
+    const int k = lo ? -x : x - (p.nx - 1);
+    const TU u0 = gen_u_row(u, p, a, lo ? 0 : p.nx - 1, y, t);
+    const TU u1 = gen_u_row(u, p, a, lo ? 1 : p.nx - 2, y, t);
+    return gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, a, t), u0, u1, k);
+}
+
+__device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
+{
+    return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * (p.nx + 2) + (size_t)(x + 1);
+}
+
+// Pass 1 / 4a: K = P + Pbar from central differences of u (eqs. (10), (15),
+// (27)) on the lattice and its ring of ghost nodes. `which`: 0 = u_n at step
+// n, 1 = the predictor u^p at step n + 1. Sets the flag where J <= 0.
+template <class PR>
+__global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int which)
+{
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    const int w = p.nx + 2;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= w * (p.ny + 2)) return;
+    const int y = s / w - 1, x = s % w - 1;
+    const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
+    const double t = (double)(p.step + which);
+    TC H[4], K[4];
+    for (int a = 0; a < 2; ++a) {
+        H[2 * a + 0] = TC((gen_u(u, p, a, x + 1, y, t) - gen_u(u, p, a, x - 1, y, t)) * TU(0.5));
+        H[2 * a + 1] = TC((gen_u(u, p, a, x, y + 1, t) - gen_u(u, p, a, x, y - 1, t)) * TU(0.5));
+    }
+    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
+    TC *Kp = static_cast<TC *>(p.K);
+    for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
+    if (which == 0 && x >= 0 && x < p.nx && y >= 0 && y < p.ny && !(J > TC(0))) p.flag[0] = 1u;
+}
+
+// central divergence of K at node (x, y) plus the body force (eq. (23))
+template <class TC>
+__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, TC S[2])
+{
+    const TC *K = static_cast<const TC *>(p.K);
+    S[0] = TC(p.bx) + TC(0.5) * (K[k_index(p, 0, x + 1, y)] - K[k_index(p, 0, x - 1, y)]) +
+           TC(0.5) * (K[k_index(p, 1, x, y + 1)] - K[k_index(p, 1, x, y - 1)]);
+    S[1] = TC(p.by) + TC(0.5) * (K[k_index(p, 2, x + 1, y)] - K[k_index(p, 2, x - 1, y)]) +
+           TC(0.5) * (K[k_index(p, 3, x, y + 1)] - K[k_index(p, 3, x, y - 1)]);
+}
+
+// Pass 2: source, moments, equilibrium (20), forcing (22) and BGK collision (4)
+template <class PR>
+__global__ void __launch_bounds__(256) collide_pass(const GenParams p)
+{
+    using TF = typename PR::TF;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const int n = p.nx * p.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / p.nx, x = s - y * p.nx;
+    const size_t pl = (size_t)p.plane;
+    const TF *fin = static_cast<const TF *>(p.f_in);
+    const TJ *jin = static_cast<const TJ *>(p.j_in);
+    TC S[2], f[9], fc[9], r, pxx;
+    gen_source(p, x, y, S);
+    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+    collide(f, TC(jin[s]), TC(jin[pl + s]), S[0], S[1], TC(p.omega), fc, r, pxx);
+    TC *fcol = static_cast<TC *>(p.fcol);
+    for (int i = 0; i < 9; ++i) fcol[i * pl + s] = fc[i];
+    TC *Sp = static_cast<TC *>(p.S);
+    Sp[s] = S[0];
+    Sp[pl + s] = S[1];
+}
+
+// Value the wall returns into direction opp(o) at node (x, y) for the link o
+// that leaves through the wall(s): sx, sy are the outward signs of the x
+// and y walls it crosses (0 = none). Bounce-back with the wall momentum
+// (eq. (25)) if a crossed wall is a momentum wall (the mean j* if both are);
+// otherwise anti-bounce-back (eq. (26)) with r_bd and Pbar* at the node:
+// each traction wall's transform gives its normal column, -s T* + K N; a
+// tangential entry keeps the populations' second moment; at a corner the
+// off-diagonal entry is the mean of both walls' values.
+template <class PR>
+__device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, int y, int o, int sx, int sy,
+                                                    typename PR::TC fco)
+{
+    using TF = typename PR::TF;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const int ex = sx < 0 ? EDGE_XMIN : EDGE_XMAX, ey = sy < 0 ? EDGE_YMIN : EDGE_YMAX;
+    const bool dx = sx != 0 && p.bc[ex] == BC_DIRICHLET, dy = sy != 0 && p.bc[ey] == BC_DIRICHLET;
+    const TC w = gweight<TC>(o);
+    const TC cx = TC(kGx[o]), cy = TC(kGy[o]);
+    if (dx || dy) {
+        TC jx, jy;
+        if (dx && dy) {
+            jx = TC(0.5 * (p.val[ex][0] + p.val[ey][0]));
+            jy = TC(0.5 * (p.val[ex][1] + p.val[ey][1]));
+        } else {
+            const int e = dx ? ex : ey;
+            jx = TC(p.val[e][0]);
+            jy = TC(p.val[e][1]);
+        }
+        return fco - TC(6) * w * (cx * jx + cy * jy);
+    }
+    // populations' moments r and Pi at the node (state n)
+    const size_t pl = (size_t)p.plane, s = (size_t)y * p.nx + x;
+    const TF *fin = static_cast<const TF *>(p.f_in);
+    TC f[9];
+    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+    const TC r = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const TC dsum = (f[5] + f[6]) + (f[7] + f[8]);
+    TC Pxx = (f[1] + f[3]) + dsum, Pyy = (f[2] + f[4]) + dsum, Pxy = (f[5] - f[6]) + (f[7] - f[8]);
+    const TC *K = static_cast<const TC *>(p.K);
+    TC qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
+    if (sx) {  // x wall: column x of Pbar*, q_a = -s T_a + K_ax
+        const TC sg = TC(sx);
+        qx0 = -sg * TC(p.val[ex][0]) + K[k_index(p, 0, x, y)];
+        qx1 = -sg * TC(p.val[ex][1]) + K[k_index(p, 2, x, y)];
+    }
+    if (sy) {  // y wall: column y, q_a = -s T_a + K_ay
+        const TC sg = TC(sy);
+        qy0 = -sg * TC(p.val[ey][0]) + K[k_index(p, 1, x, y)];
+        qy1 = -sg * TC(p.val[ey][1]) + K[k_index(p, 3, x, y)];
+    }
+    if (sx && sy) {
+        Pxx = qx0;
+        Pyy = qy1;
+        Pxy = TC(0.5) * (qx1 + qy0);
+    } else if (sy) {
+        Pxy = qy0;
+        Pyy = qy1;
+    } else {
+        Pxx = qx0;
+        Pxy = qx1;
+    }
+    // A = Pbar* - r/3 I; A : (e e - I/3)
+    const TC third = TC(1) / TC(3);
+    const TC axx = Pxx - r * third, ayy = Pyy - r * third;
+    const TC q = axx * cx * cx + TC(2) * Pxy * cx * cy + ayy * cy * cy - (axx + ayy) * third;
+    return -fco + TC(2) * w * (r + TC(4.5) * q);
+}
+
+// Pass 3: pull streaming (5) with the wall rules (Sec. 6), storage of the
+// new populations, their first moment jf and the predictor u^p (PC), or the
+// new j and u directly (explicit).
+template <class PR>
+__global__ void __launch_bounds__(256) stream_pass(const GenParams p)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const int n = p.nx * p.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / p.nx, x = s - y * p.nx;
+    const size_t pl = (size_t)p.plane;
+    const TC *fcol = static_cast<const TC *>(p.fcol);
+    const bool perx = p.bc[EDGE_XMIN] == BC_PERIODIC, pery = p.bc[EDGE_YMIN] == BC_PERIODIC;
+    TC fn[9];
+    for (int i = 0; i < 9; ++i) {
+        int sxp = x - kGx[i], syp = y - kGy[i];
+        bool cx = sxp < 0 || sxp >= p.nx, cy = syp < 0 || syp >= p.ny;
+        if (cx && perx) {
+            sxp = (sxp + p.nx) % p.nx;
+            cx = false;
+        }
+        if (cy && pery) {
+            syp = (syp + p.ny) % p.ny;
+            cy = false;
+        }
+        if (!cx && !cy) {
+            fn[i] = fcol[i * pl + (size_t)syp * p.nx + sxp];
+        } else {
+            const int o = kGopp[i];  // the link that left through the wall
+            fn[i] = gen_wall<PR>(p, x, y, o, cx ? kGx[o] : 0, cy ? kGy[o] : 0, fcol[o * pl + s]);
+        }
+    }
+    const bool sr = FS::kStochastic && p.sr;
+    const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
+    store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, fn, TC(p.f_scale), sr, key);
+    const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
+    const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
+    const TC *S = static_cast<const TC *>(p.S);
+    const TU *u = static_cast<const TU *>(p.u_in);
+    const TJ *jin = static_cast<const TJ *>(p.j_in);
+    const TC jn0 = TC(jin[s]), jn1 = TC(jin[pl + s]);
+    if (p.pc) {
+        TC *jf = static_cast<TC *>(p.jf);
+        jf[s] = jfx;
+        jf[pl + s] = jfy;
+        const TC jpx = jfx + TC(0.5) * S[s], jpy = jfy + TC(0.5) * S[pl + s];
+        TU *up = static_cast<TU *>(p.up);
+        up[s] = u[s] + TU(TC(0.5) * (jpx + jn0));
+        up[pl + s] = u[pl + s] + TU(TC(0.5) * (jpy + jn1));
+    } else {
+        const TC j0 = jfx + TC(0.5) * S[s], j1 = jfy + TC(0.5) * S[pl + s];
+        const TU u0 = u[s] + TU(TC(0.5) * (j0 + jn0)), u1 = u[pl + s] + TU(TC(0.5) * (j1 + jn1));
+        static_cast<TU *>(p.u_out)[s] = u0;
+        static_cast<TU *>(p.u_out)[pl + s] = u1;
+        static_cast<TJ *>(p.j_out)[s] = TJ(j0);
+        static_cast<TJ *>(p.j_out)[pl + s] = TJ(j1);
+        if (!isfinite((double)u0) || !isfinite((double)u1) || !isfinite((double)j0) || !isfinite((double)j1))
+            p.flag[0] = 1u;
+    }
+}
+
+// Pass 4b (PC): S^p from K(u^p), j_{n+1} = jf + S^p / 2 and the trapezoidal
+// displacement update (eq. (24)).
+template <class PR>
+__global__ void __launch_bounds__(256) update_pass(const GenParams p)
+{
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    const int n = p.nx * p.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / p.nx, x = s - y * p.nx;
+    const size_t pl = (size_t)p.plane;
+    TC Sp[2];
+    gen_source(p, x, y, Sp);
+    const TC *jf = static_cast<const TC *>(p.jf);
+    const TU *u = static_cast<const TU *>(p.u_in);
+    const TJ *jin = static_cast<const TJ *>(p.j_in);
+    const TC j0 = jf[s] + TC(0.5) * Sp[0], j1 = jf[pl + s] + TC(0.5) * Sp[1];
+    const TU u0 = u[s] + TU(TC(0.5) * (j0 + TC(jin[s]))), u1 = u[pl + s] + TU(TC(0.5) * (j1 + TC(jin[pl + s])));
+    static_cast<TU *>(p.u_out)[s] = u0;
+    static_cast<TU *>(p.u_out)[pl + s] = u1;
+    static_cast<TJ *>(p.j_out)[s] = TJ(j0);
+    static_cast<TJ *>(p.j_out)[pl + s] = TJ(j1);
+    if (!isfinite((double)u0) || !isfinite((double)u1) || !isfinite((double)j0) || !isfinite((double)j1))
+        p.flag[0] = 1u;
+}
+
+// Scratch bytes of the passes for an nx x ny plate.
+template <class PR>
+inline size_t general_scratch_bytes(int nx, int ny)
+{
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    const size_t n = (size_t)nx * ny, ne = (size_t)(nx + 2) * (ny + 2);
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    return al(4 * ne * sizeof(TC)) + al(9 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) +
+           al(2 * n * sizeof(TU));
+}
+
+// Enqueue one time step of the passes on the stream; scratch is
+// general_scratch_bytes<PR>(nx, ny) bytes, 256-byte aligned.
+template <class PR>
+inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
+{
+    using TC = typename PR::TC;
+    const size_t n = (size_t)p.nx * p.ny, ne = (size_t)(p.nx + 2) * (p.ny + 2);
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    size_t off = 0;
+    p.K = scratch + off;
+    off += al(4 * ne * sizeof(TC));
+    p.fcol = scratch + off;
+    off += al(9 * n * sizeof(TC));
+    p.S = scratch + off;
+    off += al(2 * n * sizeof(TC));
+    p.jf = scratch + off;
+    off += al(2 * n * sizeof(TC));
+    p.up = scratch + off;
+    const int nb = (int)((n + 255) / 256), nbe = (int)((ne + 255) / 256);
+    hipLaunchKernelGGL((stress_pass<PR>), dim3(nbe), dim3(256), 0, st, p, 0);
+    hipLaunchKernelGGL((collide_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((stream_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    if (p.pc) {
+        hipLaunchKernelGGL((stress_pass<PR>), dim3(nbe), dim3(256), 0, st, p, 1);
+        hipLaunchKernelGGL((update_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -119,24 +119,6 @@ inline void fill_physics(StepParams &sp, const Units &U, double tau_over_dt, con
     }
 }
 
-// Geometry/material view used by the start-up, read-out and diagnostics kernels.
-inline FieldParams field_params(int nx, int ny, const Units &U, int bc_lo, const double val_lo[2], int bc_hi,
-                                const double val_hi[2], double t_steps)
-{
-    FieldParams fp{};
-    fp.nx = nx;
-    fp.ny = ny;
-    fp.plane = (long long)nx * ny;
-    fp.bc_lo = bc_lo;
-    fp.bc_hi = bc_hi;
-    for (int a = 0; a < 2; ++a) {
-        fp.uw_lo[a] = bc_lo == LBM_BC_DIRICHLET_J ? val_lo[a] / U.momentum() * t_steps : 0.0;
-        fp.uw_hi[a] = bc_hi == LBM_BC_DIRICHLET_J ? val_hi[a] / U.momentum() * t_steps : 0.0;
-    }
-    fp.lam = U.lam / U.stress();
-    fp.mu = U.mu / U.stress();
-    return fp;
-}
 
 // ---------------------------------------------------------------- launches
 
@@ -258,8 +240,10 @@ struct PlateIO {
     int nx, ny;
     lbm_precision prec;
     Units U;
-    int bc_lo, bc_hi;
+    int bc_lo, bc_hi;           // y edges
     double val_lo[2], val_hi[2];
+    int bc_left, bc_right;      // x edges (periodic unless set)
+    double val_left[2], val_right[2];
     void *f, *u, *j;            // current state copy
     void *f_other;              // the other copy (staging for start-up)
     double f_scale;
@@ -269,6 +253,31 @@ struct PlateIO {
     double *diag_out;           // 8 doubles
     hipStream_t stream;
 };
+
+// Geometry/material view used by the start-up, read-out and diagnostics
+// kernels at step t_steps (momentum walls have moved by j* t).
+inline FieldParams field_params(const PlateIO &io, double t_steps)
+{
+    const Units &U = io.U;
+    FieldParams fp{};
+    fp.nx = io.nx;
+    fp.ny = io.ny;
+    fp.plane = (long long)io.nx * io.ny;
+    fp.bc_lo = io.bc_lo;
+    fp.bc_hi = io.bc_hi;
+    fp.bc_left = io.bc_left;
+    fp.bc_right = io.bc_right;
+    auto uw = [&](int bc, double v) { return bc == LBM_BC_DIRICHLET_J ? v / U.momentum() * t_steps : 0.0; };
+    for (int a = 0; a < 2; ++a) {
+        fp.uw_lo[a] = uw(io.bc_lo, io.val_lo[a]);
+        fp.uw_hi[a] = uw(io.bc_hi, io.val_hi[a]);
+        fp.uw_left[a] = uw(io.bc_left, io.val_left[a]);
+        fp.uw_right[a] = uw(io.bc_right, io.val_right[a]);
+    }
+    fp.lam = U.lam / U.stress();
+    fp.mu = U.mu / U.stress();
+    return fp;
+}
 
 // f = f^eq of the start fields (u0, v0 host arrays). For 16-bit storage the
 // population scale is chosen here (returned in *scale); *nonfinite is set if
@@ -283,8 +292,7 @@ inline hipError_t plate_start(const PlateIO &io, const double *u0, const double 
     if ((e = hipMemcpyAsync(su, u0, 2 * n * sizeof(double), hipMemcpyHostToDevice, io.stream))) return e;
     if ((e = hipMemcpyAsync(sv, v0, 2 * n * sizeof(double), hipMemcpyHostToDevice, io.stream))) return e;
     InitParams ip{};
-    const double zero[2] = {0.0, 0.0};
-    ip.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, zero, io.bc_hi, zero, 0.0);
+    ip.fp = field_params(io, 0.0);
     ip.u0 = su;
     ip.v0 = sv;
     ip.f = io.f;
@@ -328,7 +336,7 @@ inline hipError_t plate_rows(const PlateIO &io, double t_steps, int what, double
 {
     const int nx = io.nx, ny = io.ny;
     ReadParams rp{};
-    rp.fp = field_params(nx, ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+    rp.fp = field_params(io, t_steps);
     rp.u = io.u;
     rp.j = io.j;
     rp.out = io.staging;
@@ -375,7 +383,7 @@ inline hipError_t plate_sample(const PlateIO &io, double t_steps, int n, const i
     hipError_t e;
     if ((e = hipMemcpyAsync(d_idx, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, io.stream))) return e;
     ReadParams rp{};
-    rp.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+    rp.fp = field_params(io, t_steps);
     rp.u = io.u;
     rp.j = io.j;
     rp.out = vals;
@@ -406,7 +414,7 @@ inline hipError_t plate_read(const PlateIO &io, double t_steps, double *u, doubl
     }
     if (out7) {
         DiagParams dp{};
-        dp.fp = field_params(io.nx, io.ny, io.U, io.bc_lo, io.val_lo, io.bc_hi, io.val_hi, t_steps);
+        dp.fp = field_params(io, t_steps);
         dp.f = io.f;
         dp.u = io.u;
         dp.j = io.j;

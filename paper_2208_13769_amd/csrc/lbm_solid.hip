@@ -11,6 +11,7 @@
 #include <new>
 #include <string>
 
+#include "general_kernels.hpp"
 #include "host_common.hpp"
 
 using namespace lbm;
@@ -21,7 +22,19 @@ struct Layout {
     StateLayout state;
     size_t staging, staging_bytes;
     size_t partials, small, total;
+    size_t scratch, total_walled;  // scratch of the general passes (walls on the x edges)
 };
+
+size_t general_scratch(int nx, int ny, lbm_precision p)
+{
+    switch (p) {
+    case LBM_FP64: return general_scratch_bytes<PrecF64>(nx, ny);
+    case LBM_FP32: return general_scratch_bytes<PrecF32>(nx, ny);
+    case LBM_FP16_STORE: return general_scratch_bytes<PrecF16>(nx, ny);
+    case LBM_FP32_U64: return general_scratch_bytes<PrecF32U64>(nx, ny);
+    default: return general_scratch_bytes<PrecBF16>(nx, ny);
+    }
+}
 
 Layout make_layout(int nx, int ny, lbm_precision p)
 {
@@ -36,6 +49,8 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.small = off;  // flag word + final diagnostics
     off = align_up(off + 64 * sizeof(double));
     L.total = off;
+    L.scratch = off;
+    L.total_walled = align_up(off + general_scratch(nx, ny, p));
     return L;
 }
 
@@ -62,6 +77,9 @@ struct lbm_solver {
     int spl = 1;  // time steps per launch (1, or 2 with the predictor-corrector)
     int sr = 0;   // stochastic rounding of 16-bit populations
     unsigned long long seed = 0;
+    bool force_general = false;  // run the general passes even without x walls
+
+    bool general() const { return force_general || bc[LBM_EDGE_XMIN] != LBM_BC_PERIODIC; }
     std::string err;
 
     void *fptr(int c) const { return ws + L.state.f[c]; }
@@ -79,9 +97,13 @@ struct lbm_solver {
         p.U = units();
         p.bc_lo = bc[LBM_EDGE_YMIN];
         p.bc_hi = bc[LBM_EDGE_YMAX];
+        p.bc_left = bc[LBM_EDGE_XMIN];
+        p.bc_right = bc[LBM_EDGE_XMAX];
         for (int a = 0; a < 2; ++a) {
             p.val_lo[a] = bcval[LBM_EDGE_YMIN][a];
             p.val_hi[a] = bcval[LBM_EDGE_YMAX][a];
+            p.val_left[a] = bcval[LBM_EDGE_XMIN][a];
+            p.val_right[a] = bcval[LBM_EDGE_XMAX][a];
         }
         p.f = fptr(cur);
         p.u = uptr(cur);
@@ -167,6 +189,12 @@ size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p)
     return make_layout(nx, ny, p).total;
 }
 
+size_t lbm_workspace_bytes_walled(int nx, int ny, lbm_precision p)
+{
+    if (nx < 5 || ny < 5 || !valid_precision(p)) return 0;
+    return make_layout(nx, ny, p).total_walled;
+}
+
 lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s, void *dev_workspace,
                       size_t ws_bytes, void *hip_stream, lbm_solver **out)
 {
@@ -229,12 +257,14 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
     if (!h) return LBM_ERR_ARG;
     if (e < LBM_EDGE_XMIN || e > LBM_EDGE_YMAX) return fail(h, LBM_ERR_ARG, "unknown edge");
     if (bc < LBM_BC_PERIODIC || bc > LBM_BC_NEUMANN_T) return fail(h, LBM_ERR_ARG, "unknown boundary rule");
-    if ((e == LBM_EDGE_XMIN || e == LBM_EDGE_XMAX) && bc != LBM_BC_PERIODIC)
-        return fail(h, LBM_ERR_UNSUPPORTED, "x edges are periodic in this build");
+    if ((e == LBM_EDGE_XMIN || e == LBM_EDGE_XMAX) && bc != LBM_BC_PERIODIC && h->ws_bytes < h->L.total_walled)
+        return fail(h, LBM_ERR_NOMEM, "walls on the x edges need a workspace of lbm_workspace_bytes_walled() bytes");
     if (bc != LBM_BC_PERIODIC && (!value || !std::isfinite(value[0]) || !std::isfinite(value[1])))
         return fail(h, LBM_ERR_ARG, "boundary value missing or not finite");
-    if (e == LBM_EDGE_XMIN || e == LBM_EDGE_XMAX) return LBM_OK;
-    const int other = e == LBM_EDGE_YMIN ? LBM_EDGE_YMAX : LBM_EDGE_YMIN;
+    const int other = e == LBM_EDGE_YMIN ? LBM_EDGE_YMAX
+                      : e == LBM_EDGE_YMAX ? LBM_EDGE_YMIN
+                      : e == LBM_EDGE_XMIN ? LBM_EDGE_XMAX
+                                           : LBM_EDGE_XMIN;
     if (bc == LBM_BC_PERIODIC && h->bc[other] != LBM_BC_PERIODIC) {
         // periodic edges come in pairs
         h->bc[other] = LBM_BC_PERIODIC;
@@ -283,6 +313,15 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
     if (steps_per_launch != 1 && steps_per_launch != 2) return LBM_OK;
     if (steps_per_launch == 2 && (h->scheme != LBM_SCHEME_PC || block > 256)) return LBM_OK;
     *blocks = resident_blocks(h, block, steps_per_launch);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_general_path(lbm_solver *h, int on)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (on && h->ws_bytes < h->L.total_walled)
+        return fail(h, LBM_ERR_NOMEM, "the general passes need a workspace of lbm_workspace_bytes_walled() bytes");
+    h->force_general = on != 0;
     return LBM_OK;
 }
 
@@ -361,6 +400,43 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
     sp.seed = h->seed;
     const int nblocks = h->shape.n_strips * h->shape.n_segs;
     const bool pc = h->scheme == LBM_SCHEME_PC;
+    if (h->general()) {
+        GenParams gp{};
+        gp.nx = h->nx;
+        gp.ny = h->ny;
+        gp.plane = sp.plane;
+        gp.omega = sp.omega;
+        gp.lam = sp.lam;
+        gp.mu = sp.mu;
+        gp.bx = sp.bx;
+        gp.by = sp.by;
+        const Units U = h->units();
+        for (int e = 0; e < 4; ++e) {
+            gp.bc[e] = h->bc[e];
+            for (int a = 0; a < 2; ++a)  // j* -> lattice momentum, T* -> lattice stress
+                gp.val[e][a] = h->bc[e] == LBM_BC_DIRICHLET_J ? h->bcval[e][a] / U.momentum()
+                                                              : h->bcval[e][a] / U.stress();
+        }
+        gp.f_scale = sp.f_scale;
+        gp.f_inv_scale = sp.f_inv_scale;
+        gp.sr = sp.sr;
+        gp.seed = sp.seed;
+        gp.pc = pc ? 1 : 0;
+        gp.flag = sp.flag;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            gp.f_in = h->fptr(h->cur);
+            gp.u_in = h->uptr(h->cur);
+            gp.j_in = h->jptr(h->cur);
+            gp.f_out = h->fptr(h->cur ^ 1);
+            gp.u_out = h->uptr(h->cur ^ 1);
+            gp.j_out = h->jptr(h->cur ^ 1);
+            gp.step = h->steps;
+            HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gp, h->ws + h->L.scratch, h->stream)));
+            h->cur ^= 1;
+            h->steps += 1;
+        }
+        return LBM_OK;
+    }
     int64_t k = 0;
     if (h->spl == 2) {
         for (; k + 2 <= nsteps; k += 2) {

@@ -37,7 +37,7 @@ EXPORTED = [
     "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
     "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
     "lbm_resident_blocks", "lbm_set_rounding", "lbm_read_derived", "lbm_sample", "lbm_batch_read_derived",
-    "lbm_batch_sample",
+    "lbm_batch_sample", "lbm_workspace_bytes_walled", "lbm_set_general_path",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
     "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_set_steps_per_launch",
@@ -79,6 +79,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp, dp, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t
     lib.lbm_workspace_bytes.restype = sz
     lib.lbm_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.lbm_workspace_bytes_walled.restype = sz
+    lib.lbm_workspace_bytes_walled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.lbm_set_general_path.restype = ctypes.c_int
+    lib.lbm_set_general_path.argtypes = [vp, ctypes.c_int]
     lib.lbm_create.restype = ctypes.c_int
     lib.lbm_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                vp, sz, vp, ctypes.POINTER(vp)]
@@ -138,6 +142,14 @@ def _check(status: int, handle) -> None:
 
 def lbm_workspace_bytes(nx: int, ny: int, precision: int) -> int:
     return int(load_library().lbm_workspace_bytes(nx, ny, precision))
+
+
+def lbm_workspace_bytes_walled(nx: int, ny: int, precision: int) -> int:
+    return int(load_library().lbm_workspace_bytes_walled(nx, ny, precision))
+
+
+def lbm_set_general_path(h, on: bool):
+    _check(load_library().lbm_set_general_path(h, int(bool(on))), h)
 
 
 def lbm_create(nx, ny, dx, precision, scheme, workspace_ptr, ws_bytes, stream_ptr):
@@ -263,13 +275,14 @@ class Solver:
     """One plate on one GPU; the workspace is a torch uint8 tensor."""
 
     def __init__(self, nx: int, ny: int, dx: float = 1.0, precision: str = "fp64", scheme: str = "pc",
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, walled: bool = False):
+        """walled: size the workspace for walls on the x edges (the general passes)."""
         import torch
 
         self.nx, self.ny, self.dx = nx, ny, dx
         self.precision = precision
         prec = PRECISIONS[precision]
-        nbytes = lbm_workspace_bytes(nx, ny, prec)
+        nbytes = (lbm_workspace_bytes_walled if walled else lbm_workspace_bytes)(nx, ny, prec)
         if nbytes == 0:
             raise LbmError(LBM_ERR_ARG, "invalid size or precision")
         self.device = torch.device(device)
@@ -297,6 +310,9 @@ class Solver:
 
     def set_boundary(self, edge: int, bc: int, value=None):
         lbm_set_boundary(self.h, edge, bc, value)
+
+    def set_general_path(self, on: bool):
+        lbm_set_general_path(self.h, on)
 
     def set_fields(self, u0, v0):
         lbm_set_fields(self.h, u0, v0)

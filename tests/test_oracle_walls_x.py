@@ -13,9 +13,16 @@ Q11 and Q20), against properties that do not use the new code's formulas:
 - A block pulled symmetrically at its top and bottom edges, free at its
   sides, stays mirror-symmetric about both centre lines.
 - A block at rest between walls with zero loads stays at rest.
+- Loaded blocks settle to the homogeneous states of the continuum problem:
+  slow uniaxial tension to the neo-Hooke uniaxial-stress stretch (one scalar
+  equation, solved here with a root finder), pure shear to F = cI + g(e1e2 +
+  e2e1) with J = 1 and g = tau / (2 mu) (closed form). The nonlinear parts of
+  both answers are larger than the tolerances, so a linear or wrong material
+  response at the walls fails them.
 """
 import numpy as np
 import pytest
+from scipy.optimize import brentq
 
 from oracle import oracle as O
 
@@ -110,3 +117,72 @@ def test_unpaired_periodic_edges_are_rejected():
     p = O.Params(nx=12, ny=10, bc_xmin=N_, bc_xmax=O.PERIODIC)
     with pytest.raises(ValueError):
         O.Solver(p, np.zeros((2, 10, 12)), np.zeros((2, 10, 12)))
+
+
+def _edge_stretch(u, n):
+    """mean stretches (x, y) between the outermost node columns / rows"""
+    L = 1.0 - 1.0 / n
+    return (1.0 + (u[0][:, -1].mean() - u[0][:, 0].mean()) / L,
+            1.0 + (u[1][-1, :].mean() - u[1][0, :].mean()) / L)
+
+
+def test_slow_tension_settles_to_uniaxial_stress():
+    """Top and bottom pulled with T = 0.2 mu, ramped over t = 10, sides free;
+    the stretch averaged over t in [10, 16] against the homogeneous solution
+    F = diag(a, b) with P11 = 0, P22 = T of the Sec. 7 energy. At 40 x 40 the
+    traction walls of reading Q11 overshoot the axial strain by about a
+    quarter of its nonlinear part (1.3 % of the strain), hence the bounds."""
+    n, T, lam, mu, t_ramp, t_end = 40, 0.2, 1.0, 1.0, 10.0, 16.0
+    # P11 = 0 gives a^2 = (mu + lam/2) / (mu + lam b^2 / 2); then P22(b) = T
+    a_of = lambda b: np.sqrt((mu + lam / 2) / (mu + lam * b * b / 2))
+    P22 = lambda b: mu * (b - 1 / b) + lam / 2 * ((a_of(b) * b) ** 2 - 1) / b - T
+    b = brentq(P22, 1.0, 1.5, xtol=1e-15)
+    a = a_of(b)
+    # linear elasticity (plane strain): eps_yy = T (lam + 2mu) / (4 mu (lam + mu)), eps_xx = -T lam / (4 mu (lam + mu))
+    b_lin, a_lin = 1 + T * (lam + 2 * mu) / (4 * mu * (lam + mu)), 1 - T * lam / (4 * mu * (lam + mu))
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=lam, mu=mu, tau_over_dt=0.8,
+                 bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_)
+    s = O.Solver(p, np.zeros((2, n, n)), np.zeros((2, n, n)))
+    dt = O.dt(p)
+    hist = []
+    for k in range(int(round(t_end / dt))):
+        f = T * min(k * dt / t_ramp, 1.0)
+        s.set_boundary_value("ymax", (0.0, f))
+        s.set_boundary_value("ymin", (0.0, -f))
+        s.step(1)
+        if k * dt > t_ramp and k % 3 == 0:
+            hist.append(_edge_stretch(s.u, n))
+    ax, by = np.mean(hist, axis=0)
+    assert abs(by - b) < 0.3 * abs(b - b_lin)
+    assert abs(ax - a) < 0.1 * abs(a - a_lin)
+
+
+def test_pure_shear_settles_to_the_homogeneous_state():
+    """The shear workload of Sec. 7.1 read as pure shear (tangential traction
+    tau = 0.05 mu on all four edges, ramped over t = 1), run to t = 16: the
+    shear H12 = H21 averaged over t in [12, 16] against g = tau / (2 mu), and
+    the normal strains against the second-order c - 1 = sqrt(1 + g^2) - 1."""
+    n, tau, t_end = 40, 0.05, 16.0
+    g = tau / 2.0
+    c1 = np.sqrt(1.0 + g * g) - 1.0
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.8,
+                 bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_)
+    s = O.Solver(p, np.zeros((2, n, n)), np.zeros((2, n, n)))
+    dt = O.dt(p)
+    L = 1.0 - 1.0 / n
+    hist = []
+    for k in range(int(round(t_end / dt))):
+        f = tau * min(k * dt, 1.0)
+        s.set_boundary_value("ymax", (f, 0.0))
+        s.set_boundary_value("ymin", (-f, 0.0))
+        s.set_boundary_value("xmax", (0.0, f))
+        s.set_boundary_value("xmin", (0.0, -f))
+        s.step(1)
+        if k * dt > t_end - 4.0 and k % 3 == 0:
+            u = s.u
+            hist.append(((u[0][-1, :].mean() - u[0][0, :].mean()) / L, (u[1][:, -1].mean() - u[1][:, 0].mean()) / L,
+                         _edge_stretch(u, n)[0] - 1.0, _edge_stretch(u, n)[1] - 1.0))
+    H12, H21, H11, H22 = np.mean(hist, axis=0)
+    assert abs(H12 - g) < 0.03 * g and abs(H21 - g) < 0.03 * g
+    # J = 1: no volume change to first order; the normal strains are the nonlinear c - 1
+    assert abs(H11 - c1) < 0.4 * c1 and abs(H22 - c1) < 0.4 * c1
