@@ -14,7 +14,9 @@
  * The second moment that enters the equilibrium is the populations' own
  * second moment; the source of the moment step is taken at t + dt by a
  * predictor-corrector (the footnote on stability in Sec. 5), or at t as
- * printed in Algorithm 1 (LBM_SCHEME_EXPLICIT).
+ * printed in Algorithm 1 (LBM_SCHEME_EXPLICIT), or at t + dt from a
+ * predictor displacement whose j is extrapolated linearly from t - dt and t
+ * (LBM_SCHEME_EXTRAP, the variant closing Sec. 5).
  *
  * Units: every value that crosses this ABI is in physical units (lengths in
  * the unit of dx, rho0, lambda, mu, velocities, stresses). The time step is
@@ -75,8 +77,12 @@ typedef enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_STORE = 2, LBM_BF16_STORE = 
  * and batching. 32- and 64-bit storage always rounds to nearest. */
 typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
 
-/* Time level of the source in the moment step (Sec. 5). */
-typedef enum { LBM_SCHEME_PC = 0, LBM_SCHEME_EXPLICIT = 1 } lbm_scheme;
+/* Time level of the source in the moment step (Sec. 5). EXTRAP takes the
+ * predictor displacement from the trapezoidal rule with j(t + dt) replaced
+ * by 2 j(t) - j(t - dt) (j(t - dt) = j(0) at the first step). It grows for
+ * lambda > mu (about 9 % per step at lambda = 2 mu) and always runs the
+ * general per-site passes, so it needs lbm_workspace_bytes_walled(). */
+typedef enum { LBM_SCHEME_PC = 0, LBM_SCHEME_EXPLICIT = 1, LBM_SCHEME_EXTRAP = 2 } lbm_scheme;
 
 typedef enum { LBM_EDGE_XMIN = 0, LBM_EDGE_XMAX = 1, LBM_EDGE_YMIN = 2, LBM_EDGE_YMAX = 3 } lbm_edge;
 
@@ -108,7 +114,8 @@ size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p);
 size_t lbm_workspace_bytes_walled(int nx, int ny, lbm_precision p);
 
 /* Create a handle. nx, ny >= 5; dx > 0. dev_workspace: device memory of
- * ws_bytes >= lbm_workspace_bytes(nx, ny, p) bytes, 256-byte aligned.
+ * ws_bytes >= lbm_workspace_bytes(nx, ny, p) bytes (lbm_workspace_bytes_walled
+ * for LBM_SCHEME_EXTRAP; LBM_ERR_NOMEM otherwise), 256-byte aligned.
  * hip_stream: a hipStream_t (NULL = the default stream). */
 lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s,
                       void *dev_workspace, size_t ws_bytes, void *hip_stream, lbm_solver **out);

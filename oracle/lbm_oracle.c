@@ -39,6 +39,10 @@
  *      to the wall (zeroth-order extrapolation). Higher-order extrapolation
  *      of any of them makes the scheme grow without bound near the wall.
  *  Q12 The anti-bounce-back rule uses r_bd in both places (eq. (26)).
+ *  Q22 The extrapolation variant (scheme 2, end of Sec. 5): the predictor
+ *      displacement for the source at t + dt comes from the trapezoidal
+ *      rule with j at t + dt extrapolated linearly from t - dt and t,
+ *      2 j(t) - j(t - dt). At the first step j(t - dt) is taken as j(0).
  *
  * Layout: every field is structure-of-arrays, component-major, row-major
  * inside a component: f[i][y][x] with i in the oracle's own D2Q9 order
@@ -69,7 +73,8 @@ typedef struct {
     double lam, mu;     /* Lame parameters of the neo-Hooke law (27) */
     double tau_over_dt; /* relaxation time tau / dt */
     double body[2];     /* body force per unit mass b */
-    int scheme;         /* 0: predictor-corrector (R2), 1: explicit (Alg. 1) */
+    int scheme;         /* 0: predictor-corrector (R2), 1: explicit (Alg. 1),
+                           2: j extrapolated to t + dt for the predictor (Q22) */
     int bc_ymin, bc_ymax;        /* ORACLE_* kind of the bottom / top edge */
     double val_ymin[2], val_ymax[2]; /* j* (Dirichlet) or T* (Neumann) */
     int bc_xmin, bc_xmax;        /* ORACLE_* kind of the left / right edge */
@@ -449,7 +454,7 @@ int oracle_init(const oracle_params *p, const double *u0, const double *v0,
 
 /* One time step of Algorithm 1 with readings R1/R2. step is the index n of
  * the state on entry (time t = n dt). */
-static void one_step(const oracle_params *p, double *f, double *u, double *j, long step)
+static void one_step(const oracle_params *p, double *f, double *u, double *j, double *jprev, long step)
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
@@ -546,12 +551,14 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
         jf[N + s] = a1;
     }
 
-    /* 6. source at the new time level: predictor-corrector (R2) or explicit */
-    if (p->scheme == 0) {
+    /* 6. source at the new time level: predictor-corrector (R2), j
+     * extrapolated from t - dt and t (Q22), or explicit */
+    if (p->scheme == 0 || p->scheme == 2) {
         double *up = malloc(sizeof(double) * 2 * N);
         for (int a = 0; a < 2; ++a)
             for (size_t s = 0; s < N; ++s) {
-                double jp = jf[a * N + s] + 0.5 * dt * S[a * N + s];
+                double jp = p->scheme == 0 ? jf[a * N + s] + 0.5 * dt * S[a * N + s]
+                                           : 2.0 * j[a * N + s] - jprev[a * N + s];
                 up[a * N + s] = u[a * N + s] + dt / (2.0 * p->rho0) * (jp + j[a * N + s]);
             }
         source_of_u(p, up, t + dt, Sp);
@@ -565,6 +572,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
         for (size_t s = 0; s < N; ++s) {
             double jnew = jf[a * N + s] + 0.5 * dt * Sp[a * N + s];
             u[a * N + s] += dt / (2.0 * p->rho0) * (jnew + j[a * N + s]);
+            if (jprev) jprev[a * N + s] = j[a * N + s];
             j[a * N + s] = jnew;
         }
     memcpy(f, fnew, sizeof(double) * 9 * N);
@@ -580,8 +588,20 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, lo
 
 int oracle_step(const oracle_params *p, double *f, double *u, double *j, long step0, int nsteps)
 {
-    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p)) return -1;
-    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, step0 + n);
+    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p) || p->scheme < 0 || p->scheme > 1)
+        return -1;
+    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, NULL, step0 + n);
+    return 0;
+}
+
+/* any scheme; jprev holds j one step before the state (j itself before the
+ * first step) and is advanced with it */
+int oracle_step_prev(const oracle_params *p, double *f, double *u, double *j, double *jprev, long step0,
+                     int nsteps)
+{
+    if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p) || p->scheme < 0 || p->scheme > 2)
+        return -1;
+    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, jprev, step0 + n);
     return 0;
 }
 

@@ -25,7 +25,7 @@ _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 PERIODIC, DIRICHLET_J, NEUMANN_T = 0, 1, 2
-PC, EXPLICIT = 0, 1
+PC, EXPLICIT, EXTRAP = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -66,6 +66,7 @@ def lib():
         _lib.oracle_dt.argtypes = [pp]
         _lib.oracle_init.argtypes = [pp, dp, dp, dp, dp, dp]
         _lib.oracle_step.argtypes = [pp, dp, dp, dp, ctypes.c_long, ctypes.c_int]
+        _lib.oracle_step_prev.argtypes = [pp, dp, dp, dp, dp, ctypes.c_long, ctypes.c_int]
         _lib.oracle_fields.argtypes = [pp, dp, dp, ctypes.c_double, dp, dp]
         _lib.oracle_diagnostics.argtypes = [pp, dp, dp, dp, ctypes.c_double, dp]
         _lib.oracle_piola.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
@@ -138,6 +139,7 @@ class Solver:
         self.f = np.zeros((9, ny, nx))
         self.u = np.zeros((2, ny, nx))
         self.j = np.zeros((2, ny, nx))
+        self.jprev = np.zeros((2, ny, nx))  # j one step back (the extrapolation variant)
         self.step_index = 0
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
@@ -147,14 +149,15 @@ class Solver:
                                _ptr(self.f), _ptr(self.u), _ptr(self.j))
         if rc != 0:
             raise ValueError("oracle_init rejected the parameters")
+        self.jprev[...] = self.j
 
     @property
     def t(self) -> float:
         return self.step_index * dt(self.p)
 
     def step(self, n: int) -> None:
-        rc = lib().oracle_step(ctypes.byref(self._pc), _ptr(self.f), _ptr(self.u), _ptr(self.j),
-                               self.step_index, int(n))
+        rc = lib().oracle_step_prev(ctypes.byref(self._pc), _ptr(self.f), _ptr(self.u), _ptr(self.j),
+                                    _ptr(self.jprev), self.step_index, int(n))
         if rc != 0:
             raise ValueError("oracle_step rejected the parameters")
         self.step_index += int(n)

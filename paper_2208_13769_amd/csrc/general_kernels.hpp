@@ -15,6 +15,9 @@
 //      predictor u^p (stream_pass);
 //   4. K of u^p at t + dt (stress_pass again), then S^p, j_{n+1} and
 //      u_{n+1} (update_pass). The explicit scheme stops after pass 3.
+// In the extrapolation variant (end of Sec. 5) u^p takes 2 j_n - j_{n-1}
+// for j at t + dt; j_{n-1} is still in the output buffer of j, which pass 3
+// reads at its own site before pass 4b overwrites it.
 // Same lattice units, arithmetic and storage rounding as the fused kernel.
 #pragma once
 
@@ -36,7 +39,7 @@ struct GenParams {
     long long step;                 // index n of the input state
     int sr;
     unsigned long long seed;
-    int pc;                         // predictor-corrector (1) or explicit (0)
+    int pc;  // explicit (0), predictor-corrector (1), j extrapolated for the predictor (2)
     void *K;     // scratch [4][ny + 2][nx + 2] TC: stress sum with one ghost ring
     void *fcol;  // scratch [9][ny][nx] TC: post-collision populations
     void *S;     // scratch [2][ny][nx] TC: source S_n
@@ -294,7 +297,12 @@ __global__ void __launch_bounds__(256) stream_pass(const GenParams p)
         TC *jf = static_cast<TC *>(p.jf);
         jf[s] = jfx;
         jf[pl + s] = jfy;
-        const TC jpx = jfx + TC(0.5) * S[s], jpy = jfy + TC(0.5) * S[pl + s];
+        TC jpx = jfx + TC(0.5) * S[s], jpy = jfy + TC(0.5) * S[pl + s];
+        if (p.pc == 2) {
+            const TJ *jold = static_cast<const TJ *>(p.j_out);
+            jpx = TC(2) * jn0 - TC(jold[s]);
+            jpy = TC(2) * jn1 - TC(jold[pl + s]);
+        }
         TU *up = static_cast<TU *>(p.up);
         up[s] = u[s] + TU(TC(0.5) * (jpx + jn0));
         up[pl + s] = u[pl + s] + TU(TC(0.5) * (jpy + jn1));

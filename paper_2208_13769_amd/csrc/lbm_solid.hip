@@ -79,7 +79,10 @@ struct lbm_solver {
     unsigned long long seed = 0;
     bool force_general = false;  // run the general passes even without x walls
 
-    bool general() const { return force_general || bc[LBM_EDGE_XMIN] != LBM_BC_PERIODIC; }
+    bool general() const
+    {
+        return force_general || bc[LBM_EDGE_XMIN] != LBM_BC_PERIODIC || scheme == LBM_SCHEME_EXTRAP;
+    }
     std::string err;
 
     void *fptr(int c) const { return ws + L.state.f[c]; }
@@ -203,13 +206,16 @@ lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s, 
     if (nx < 5 || ny < 5) return fail(nullptr, LBM_ERR_ARG, "nx and ny must be >= 5");
     if (!(dx > 0.0) || !std::isfinite(dx)) return fail(nullptr, LBM_ERR_ARG, "dx must be positive");
     if (!valid_precision(p)) return fail(nullptr, LBM_ERR_ARG, "unknown precision");
-    if (s != LBM_SCHEME_PC && s != LBM_SCHEME_EXPLICIT) return fail(nullptr, LBM_ERR_ARG, "unknown scheme");
+    if (s != LBM_SCHEME_PC && s != LBM_SCHEME_EXPLICIT && s != LBM_SCHEME_EXTRAP)
+        return fail(nullptr, LBM_ERR_ARG, "unknown scheme");
     if (!dev_workspace) return fail(nullptr, LBM_ERR_ARG, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return fail(nullptr, LBM_ERR_ARG, "workspace not 256-byte aligned");
     if ((long long)nx * ny > (1LL << 29)) return fail(nullptr, LBM_ERR_UNSUPPORTED, "more than 2^29 sites");
     const Layout L = make_layout(nx, ny, p);
     if (ws_bytes < L.total) return fail(nullptr, LBM_ERR_NOMEM, "workspace smaller than lbm_workspace_bytes()");
+    if (s == LBM_SCHEME_EXTRAP && ws_bytes < L.total_walled)
+        return fail(nullptr, LBM_ERR_NOMEM, "the extrapolation scheme needs lbm_workspace_bytes_walled() bytes");
     lbm_solver *h = new (std::nothrow) lbm_solver();
     if (!h) return fail(nullptr, LBM_ERR_NOMEM, "host allocation failed");
     h->nx = nx;
@@ -371,6 +377,9 @@ lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0)
     if (e != hipSuccess) return hip_fail(h, e, "start-up");
     if (nonfinite) return fail(h, LBM_ERR_ARG, "initial fields not finite");
     h->f_scale = scale;
+    if (h->scheme == LBM_SCHEME_EXTRAP)  // j one step back: j(0) before the first step
+        HIP_TRY(h, hipMemcpyAsync(h->jptr(1), h->jptr(0), 2 * (size_t)h->nx * h->ny * elem_sizes(h->prec).j,
+                                  hipMemcpyDeviceToDevice, h->stream));
     HIP_TRY(h, hipMemsetAsync(h->flag(), 0, sizeof(unsigned), h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->steps = 0;
@@ -421,7 +430,7 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.f_inv_scale = sp.f_inv_scale;
         gp.sr = sp.sr;
         gp.seed = sp.seed;
-        gp.pc = pc ? 1 : 0;
+        gp.pc = h->scheme == LBM_SCHEME_EXTRAP ? 2 : (pc ? 1 : 0);
         gp.flag = sp.flag;
         for (int64_t k = 0; k < nsteps; ++k) {
             gp.f_in = h->fptr(h->cur);

@@ -21,14 +21,14 @@ LIB_PATH = os.path.join(_HERE, "liblbm_solid.so")
 LBM_OK, LBM_ERR_ARG, LBM_ERR_NOMEM, LBM_ERR_HIP, LBM_ERR_STATE, LBM_ERR_UNSTABLE, LBM_ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6
 LBM_FP64, LBM_FP32, LBM_FP16_STORE, LBM_BF16_STORE, LBM_FP32_U64 = 0, 1, 2, 3, 4
-LBM_SCHEME_PC, LBM_SCHEME_EXPLICIT = 0, 1
+LBM_SCHEME_PC, LBM_SCHEME_EXPLICIT, LBM_SCHEME_EXTRAP = 0, 1, 2
 LBM_EDGE_XMIN, LBM_EDGE_XMAX, LBM_EDGE_YMIN, LBM_EDGE_YMAX = 0, 1, 2, 3
 LBM_BC_PERIODIC, LBM_BC_DIRICHLET_J, LBM_BC_NEUMANN_T = 0, 1, 2
 LBM_ROUND_NEAREST, LBM_ROUND_STOCHASTIC = 0, 1
 
 PRECISIONS = {"fp64": LBM_FP64, "fp32": LBM_FP32, "fp16": LBM_FP16_STORE, "bf16": LBM_BF16_STORE,
               "fp32u64": LBM_FP32_U64}
-SCHEMES = {"pc": LBM_SCHEME_PC, "explicit": LBM_SCHEME_EXPLICIT}
+SCHEMES = {"pc": LBM_SCHEME_PC, "explicit": LBM_SCHEME_EXPLICIT, "extrap": LBM_SCHEME_EXTRAP}
 ROUNDINGS = {"nearest": LBM_ROUND_NEAREST, "stochastic": LBM_ROUND_STOCHASTIC}
 
 EXPORTED_EXTRA: list = []
@@ -276,12 +276,14 @@ class Solver:
 
     def __init__(self, nx: int, ny: int, dx: float = 1.0, precision: str = "fp64", scheme: str = "pc",
                  device: str = "cuda:0", stream=None, walled: bool = False):
-        """walled: size the workspace for walls on the x edges (the general passes)."""
+        """walled: size the workspace for walls on the x edges (the general
+        passes); always so for the "extrap" scheme."""
         import torch
 
         self.nx, self.ny, self.dx = nx, ny, dx
         self.precision = precision
         prec = PRECISIONS[precision]
+        walled = walled or scheme == "extrap"
         nbytes = (lbm_workspace_bytes_walled if walled else lbm_workspace_bytes)(nx, ny, prec)
         if nbytes == 0:
             raise LbmError(LBM_ERR_ARG, "invalid size or precision")
