@@ -108,9 +108,10 @@ typedef struct {
  * (two copies of the state plus staging and reduction scratch). */
 size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p);
 
-/* Device bytes a plate needs when it may have walls on its x edges (or run
- * the general passes): lbm_workspace_bytes plus the scratch fields of the
- * passes (about 19 values per site). */
+/* Device bytes a plate needs when it may have walls on its x edges, holes
+ * or the extrapolation scheme (the general per-site passes):
+ * lbm_workspace_bytes plus the scratch fields of the passes (about 19
+ * values per site) and one mask byte per site. */
 size_t lbm_workspace_bytes_walled(int nx, int ny, lbm_precision p);
 
 /* Create a handle. nx, ny >= 5; dx > 0. dev_workspace: device memory of
@@ -199,6 +200,22 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
  * results up to rounding; they exist for walls on the x edges and are
  * slower. Needs a workspace of lbm_workspace_bytes_walled() bytes. */
 lbm_status lbm_set_general_path(lbm_solver *h, int on);
+
+/* Holes in the plate (the plate with a hole of Sec. 7.2). solid: host array
+ * [ny][nx], nonzero for a material node, 0 for a node in a hole; NULL
+ * removes the mask. A link from a material node into a hole crosses a
+ * traction-free wall half-way between the nodes. The wall is the one the
+ * link's axis step enters; the diagonal that meets a hole corner crosses
+ * both and takes the two-wall rule. In the central differences a hole
+ * neighbour takes the node's own displacement. Hole nodes hold no
+ * material: their fields read as zero and they add nothing to the
+ * diagnostics. Holes must keep off the rows and columns next to a wall
+ * edge (they may cross periodic edges), and no material node may have
+ * hole nodes on both sides along one axis (LBM_ERR_ARG otherwise). Set
+ * the boundaries first, then the mask, then the fields (LBM_ERR_STATE
+ * after lbm_set_fields). Needs lbm_workspace_bytes_walled() (LBM_ERR_NOMEM
+ * otherwise); runs the general passes. Copies the array; synchronises. */
+lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid);
 
 /* Rounding of the populations written by later steps (the start state of
  * lbm_set_fields always rounds to nearest). STOCHASTIC needs FP16_STORE or

@@ -57,6 +57,19 @@
  *      and whose off-diagonal entry is the mean of the two walls' values.
  *      Ghost displacements beyond a corner are extrapolated across the x
  *      wall from the ghost rows.
+ *  Q23 Holes (Sec. 7.2): a mask marks lattice nodes outside the material.
+ *      Links from a material node to a hole node cross a traction-free wall
+ *      half-way between them (the rules of Q11 with T* = 0). The wall of a
+ *      hole edge is the one the link's axis step enters: a link whose x
+ *      step (y step) lands in the hole crosses the x (y) wall, one whose
+ *      axis steps both stay in the material -- the diagonal that meets a
+ *      hole corner, at a re-entrant corner of the material -- crosses both
+ *      and takes the two-wall rule of Q20. In the central differences at a
+ *      material node a hole neighbour's displacement is replaced by the
+ *      node's own (zeroth-order ghost, as Q11); the stress sum K at such a
+ *      neighbour, needed by the divergence, is K of the node's gradient
+ *      with the derivatives along that axis set to zero (what the constant
+ *      ghost gives at a straight edge). Hole nodes carry no state.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -79,6 +92,7 @@ typedef struct {
     double val_ymin[2], val_ymax[2]; /* j* (Dirichlet) or T* (Neumann) */
     int bc_xmin, bc_xmax;        /* ORACLE_* kind of the left / right edge */
     double val_xmin[2], val_xmax[2];
+    const unsigned char *solid;  /* [ny][nx]: 1 material, 0 hole (Q23); NULL: all material */
 } oracle_params;
 
 /* ---- D2Q9 lattice (Sec. 3): 9 velocities incl. the rest velocity ---- */
@@ -213,6 +227,21 @@ void oracle_source_pop(const oracle_params *p, const double S[2], double psi[9])
 static size_t at(const oracle_params *p, int y, int x) { return (size_t)y * p->nx + x; }
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
 static size_t plane(const oracle_params *p) { return (size_t)p->nx * p->ny; }
+/* node (y, x) of the lattice lies in a hole (Q23); coordinates beyond a
+ * periodic edge wrap, beyond a wall they are outside every hole */
+static int in_hole(const oracle_params *p, int y, int x)
+{
+    if (!p->solid) return 0;
+    if (y < 0 || y >= p->ny) {
+        if (p->bc_ymin != ORACLE_PERIODIC) return 0;
+        y = ((y % p->ny) + p->ny) % p->ny;
+    }
+    if (x < 0 || x >= p->nx) {
+        if (p->bc_xmin != ORACLE_PERIODIC) return 0;
+        x = ((x % p->nx) + p->nx) % p->nx;
+    }
+    return !p->solid[(size_t)y * p->nx + x];
+}
 
 /* Extended grids: the displacement with two ghost rows and columns on every
  * side, (ny + 4) rows of (nx + 4) values, lattice node (y, x) at (y + 2,
@@ -285,8 +314,14 @@ static void extend_u(const oracle_params *p, const double *u, double t, double *
 static void grad_u(const oracle_params *p, const double *ue, int y, int x, double H[4])
 {
     for (int a = 0; a < 2; ++a) {
-        double dudx = (ue[ue_at(p, a, y, x + 1)] - ue[ue_at(p, a, y, x - 1)]) / (2.0 * p->dx);
-        double dudy = (ue[ue_at(p, a, y + 1, x)] - ue[ue_at(p, a, y - 1, x)]) / (2.0 * p->dx);
+        /* a hole neighbour takes the node's own value (Q23) */
+        double c = ue[ue_at(p, a, y, x)];
+        double xp = in_hole(p, y, x + 1) ? c : ue[ue_at(p, a, y, x + 1)];
+        double xm = in_hole(p, y, x - 1) ? c : ue[ue_at(p, a, y, x - 1)];
+        double yp = in_hole(p, y + 1, x) ? c : ue[ue_at(p, a, y + 1, x)];
+        double ym = in_hole(p, y - 1, x) ? c : ue[ue_at(p, a, y - 1, x)];
+        double dudx = (xp - xm) / (2.0 * p->dx);
+        double dudy = (yp - ym) / (2.0 * p->dx);
         H[2 * a + 0] = dudx;
         H[2 * a + 1] = dudy;
     }
@@ -300,6 +335,10 @@ static void stress_sum(const oracle_params *p, const double *ue, double *K)
     for (int y = -1; y <= ny; ++y)
         for (int x = -1; x <= nx; ++x) {
             double H[4], P[4], Pb[4];
+            if (in_hole(p, y, x)) {
+                for (int c = 0; c < 4; ++c) K[k_at(p, c, y, x)] = 0.0;
+                continue;
+            }
             grad_u(p, ue, y, x, H);
             oracle_piola(p->lam, p->mu, H, P);
             oracle_poisson(p->mu, H, Pb);
@@ -307,19 +346,49 @@ static void stress_sum(const oracle_params *p, const double *ue, double *K)
         }
 }
 
-/* 1S_a = rho0 b_a + d_b (P_ab + Pbar_ab), eq. (23), central divergence. */
-static void source_field(const oracle_params *p, const double *K, double *S)
+/* K at the hole neighbour of node (y, x) across axis n (Q23): K of the
+ * node's gradient with the derivatives along n set to zero */
+static void k_hole(const oracle_params *p, const double *ue, int y, int x, int n, double K[4])
+{
+    double H[4], P[4], Pb[4];
+    grad_u(p, ue, y, x, H);
+    H[n] = 0.0;
+    H[2 + n] = 0.0;
+    oracle_piola(p->lam, p->mu, H, P);
+    oracle_poisson(p->mu, H, Pb);
+    for (int c = 0; c < 4; ++c) K[c] = P[c] + Pb[c];
+}
+
+/* 1S_a = rho0 b_a + d_b (P_ab + Pbar_ab), eq. (23), central divergence.
+ * Hole nodes get zero. */
+static void source_field(const oracle_params *p, const double *ue, const double *K, double *S)
 {
     int nx = p->nx, ny = p->ny;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x)
+        for (int x = 0; x < nx; ++x) {
+            if (in_hole(p, y, x)) {
+                S[at(p, y, x)] = S[plane(p) + at(p, y, x)] = 0.0;
+                continue;
+            }
+            double kxp[4], kxm[4], kyp[4], kym[4];
+            for (int c = 0; c < 4; ++c) {
+                kxp[c] = K[k_at(p, c, y, x + 1)];
+                kxm[c] = K[k_at(p, c, y, x - 1)];
+                kyp[c] = K[k_at(p, c, y + 1, x)];
+                kym[c] = K[k_at(p, c, y - 1, x)];
+            }
+            if (in_hole(p, y, x + 1)) k_hole(p, ue, y, x, 0, kxp);
+            if (in_hole(p, y, x - 1)) k_hole(p, ue, y, x, 0, kxm);
+            if (in_hole(p, y + 1, x)) k_hole(p, ue, y, x, 1, kyp);
+            if (in_hole(p, y - 1, x)) k_hole(p, ue, y, x, 1, kym);
             for (int a = 0; a < 2; ++a) {
                 /* K_a1 at the x neighbours, K_a2 at the y neighbours */
-                double div = (K[k_at(p, 2 * a + 0, y, x + 1)] - K[k_at(p, 2 * a + 0, y, x - 1)]) / (2.0 * p->dx)
-                           + (K[k_at(p, 2 * a + 1, y + 1, x)] - K[k_at(p, 2 * a + 1, y - 1, x)]) / (2.0 * p->dx);
+                double div = (kxp[2 * a + 0] - kxm[2 * a + 0]) / (2.0 * p->dx)
+                           + (kyp[2 * a + 1] - kym[2 * a + 1]) / (2.0 * p->dx);
                 S[a * plane(p) + at(p, y, x)] = p->rho0 * p->body[a] + div;
             }
+        }
 }
 
 /* source 1S(u) at time t for the whole lattice */
@@ -329,7 +398,7 @@ static void source_of_u(const oracle_params *p, const double *u, double t, doubl
     double *K = malloc(sizeof(double) * 4 * k_plane(p));
     extend_u(p, u, t, ue);
     stress_sum(p, ue, K);
-    source_field(p, K, S);
+    source_field(p, ue, K, S);
     free(ue);
     free(K);
 }
@@ -416,11 +485,26 @@ static double bb_term(const oracle_params *p, int i, const double jstar[2])
     return -2.0 / cs2(p) * weight(i) * (C[0] * jstar[0] + C[1] * jstar[1]);
 }
 
-/* Periodic edges come in pairs. */
+/* Periodic edges come in pairs. Hole nodes (Q23) keep off rows and columns
+ * next to a wall, and no material node has hole nodes on both sides along
+ * one axis. */
 static int edges_valid(const oracle_params *p)
 {
-    return (p->bc_xmin == ORACLE_PERIODIC) == (p->bc_xmax == ORACLE_PERIODIC) &&
-           (p->bc_ymin == ORACLE_PERIODIC) == (p->bc_ymax == ORACLE_PERIODIC);
+    if ((p->bc_xmin == ORACLE_PERIODIC) != (p->bc_xmax == ORACLE_PERIODIC) ||
+        (p->bc_ymin == ORACLE_PERIODIC) != (p->bc_ymax == ORACLE_PERIODIC))
+        return 0;
+    if (!p->solid) return 1;
+    for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+            int hole = in_hole(p, y, x);
+            if (hole && (((y == 0 || y == p->ny - 1) && p->bc_ymin != ORACLE_PERIODIC) ||
+                         ((x == 0 || x == p->nx - 1) && p->bc_xmin != ORACLE_PERIODIC)))
+                return 0;
+            if (!hole && ((in_hole(p, y, x - 1) && in_hole(p, y, x + 1)) ||
+                          (in_hole(p, y - 1, x) && in_hole(p, y + 1, x))))
+                return 0;
+        }
+    return 1;
 }
 
 /* Initialisation (Algorithm 1): r0 = -rho0 div u0 (eq. (18)), j0 = rho0 v0,
@@ -436,6 +520,11 @@ int oracle_init(const oracle_params *p, const double *u0, const double *v0,
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
             double H[4], Pb[4], jj[2], feq[9];
+            if (in_hole(p, y, x)) {
+                for (int i = 0; i < 9; ++i) f[i * plane(p) + s] = 0.0;
+                u[s] = u[plane(p) + s] = j[s] = j[plane(p) + s] = 0.0;
+                continue;
+            }
             grad_u(p, ue, y, x, H);
             oracle_poisson(p->mu, H, Pb);
             double r = -p->rho0 * (H[0] + H[3]);
@@ -471,13 +560,17 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
     /* 1. stress sum K(u_n) and source 1S_n (eq. (23)) */
     extend_u(p, u, t, ue);
     stress_sum(p, ue, K);
-    source_field(p, K, S);
+    source_field(p, ue, K, S);
 
     /* 2. moments of f_n, equilibrium (20), source populations (22), collision (4) */
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
+            if (in_hole(p, y, x)) {
+                for (int i = 0; i < 9; ++i) fcol[i * N + s] = 0.0;
+                continue;
+            }
             double r, Pi[4], jj[2] = {j[s], j[N + s]}, SS[2] = {S[s], S[N + s]}, feq[9], psi[9];
             moments_r_pi(p, f, s, &r, Pi);
             oracle_equilibrium(p, r, jj, Pi, feq);
@@ -504,6 +597,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
                     if (p->bc_xmin != ORACLE_PERIODIC) continue;
                     xt = wrap(xt, nx);
                 }
+                if (in_hole(p, y, x) || in_hole(p, yt, xt)) continue;
                 fnew[i * N + at(p, yt, xt)] = fcol[i * N + at(p, y, x)];
             }
         }
@@ -516,6 +610,17 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
             for (int i = 0; i < 9; ++i) {
                 int ex = ex_of(i), ey = ey_of(i);
                 int sx = 0, sy = 0; /* walls the link crosses (outward sign) */
+                if (in_hole(p, y, x)) continue;
+                if ((ex || ey) && in_hole(p, y + ey, x + ex)) {
+                    /* a traction-free hole wall (Q23) */
+                    static const double zero[2] = {0.0, 0.0};
+                    int hx = ex && in_hole(p, y, x + ex), hy = ey && in_hole(p, y + ey, x);
+                    if (!hx && !hy) hx = hy = 1; /* the diagonal through a hole corner */
+                    double rbd, Pstar[4];
+                    traction_wall_moments(p, f, K, y, x, hx ? ex : 0, zero, hy ? ey : 0, zero, &rbd, Pstar);
+                    fnew[opposite(i) * N + at(p, y, x)] = -fcol[i * N + at(p, y, x)] + abb_term(p, i, rbd, Pstar);
+                    continue;
+                }
                 if ((x + ex < 0 || x + ex >= nx) && p->bc_xmin != ORACLE_PERIODIC) sx = ex;
                 if ((y + ey < 0 || y + ey >= ny) && p->bc_ymin != ORACLE_PERIODIC) sy = ey;
                 if (!sx && !sy) continue;
@@ -536,6 +641,12 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
                 }
                 fnew[opposite(i) * N + at(p, y, x)] = v;
             }
+
+    /* hole nodes carry no populations */
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (in_hole(p, y, x))
+                for (int i = 0; i < 9; ++i) fnew[i * N + at(p, y, x)] = 0.0;
 
     /* 5. first moment of the streamed populations, jf = sum_i C_i f_i */
 #pragma omp parallel for schedule(static)
@@ -617,6 +728,11 @@ int oracle_fields(const oracle_params *p, const double *u, const double *j, doub
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
             double H[4], PP[4];
+            if (in_hole(p, y, x)) {
+                for (int c = 0; c < 4; ++c) P[c * N + s] = 0.0;
+                v[s] = v[N + s] = 0.0;
+                continue;
+            }
             grad_u(p, ue, y, x, H);
             oracle_piola(p->lam, p->mu, H, PP);
             for (int c = 0; c < 4; ++c) P[c * N + s] = PP[c];
@@ -641,6 +757,14 @@ int oracle_derived(const oracle_params *p, const double *u, double t, double *si
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
             double H[4], T[4];
+            if (in_hole(p, y, x)) {
+                for (int c = 0; c < 4; ++c) {
+                    if (sig) sig[c * N + s] = 0.0;
+                    if (E) E[c * N + s] = 0.0;
+                }
+                if (W) W[s] = 0.0;
+                continue;
+            }
             grad_u(p, ue, y, x, H);
             if (sig) {
                 oracle_cauchy(p->lam, p->mu, H, T);
@@ -673,6 +797,7 @@ int oracle_diagnostics(const oracle_params *p, const double *f, const double *u,
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
             double H[4], r = 0.0;
+            if (in_hole(p, y, x)) continue;
             grad_u(p, ue, y, x, H);
             for (int i = 0; i < 9; ++i) r += f[i * N + s];
             double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];

@@ -50,6 +50,7 @@ class _Params(ctypes.Structure):
         ("val_ymin", ctypes.c_double * 2), ("val_ymax", ctypes.c_double * 2),
         ("bc_xmin", ctypes.c_int), ("bc_xmax", ctypes.c_int),
         ("val_xmin", ctypes.c_double * 2), ("val_xmax", ctypes.c_double * 2),
+        ("solid", ctypes.c_void_p),
     ]
 
 
@@ -108,6 +109,7 @@ class Params:
     bc_xmax: int = PERIODIC
     val_xmin: tuple = (0.0, 0.0)
     val_xmax: tuple = (0.0, 0.0)
+    solid: object = None  # [ny][nx] 1 material / 0 hole (reading Q23), or None
 
     def c(self) -> _Params:
         p = _Params()
@@ -122,6 +124,11 @@ class Params:
         p.bc_xmin, p.bc_xmax = self.bc_xmin, self.bc_xmax
         p.val_xmin[0], p.val_xmin[1] = self.val_xmin
         p.val_xmax[0], p.val_xmax[1] = self.val_xmax
+        if self.solid is not None:
+            m = np.ascontiguousarray(self.solid, dtype=np.uint8)
+            assert m.shape == (self.ny, self.nx)
+            p._solid = m  # keeps the array alive with the structure
+            p.solid = m.ctypes.data
         return p
 
 

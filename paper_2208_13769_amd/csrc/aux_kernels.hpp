@@ -16,7 +16,24 @@ struct FieldParams {
     int bc_left, bc_right;      // x edges
     double uw_left[2], uw_right[2];
     double lam, mu;             // lattice units
+    const unsigned char *mask;  // [ny][nx] 1 material, 0 hole (Sec. 7.2); nullptr: no holes
 };
+
+// Node (x, y) lies in a hole; coordinates beyond a periodic edge wrap,
+// beyond a wall they are in no hole.
+__device__ inline bool in_hole(const FieldParams &p, int x, int y)
+{
+    if (!p.mask) return false;
+    if (y < 0 || y >= p.ny) {
+        if (p.bc_lo != BC_PERIODIC) return false;
+        y = (y % p.ny + p.ny) % p.ny;
+    }
+    if (x < 0 || x >= p.nx) {
+        if (p.bc_left != BC_PERIODIC) return false;
+        x = (x % p.nx + p.nx) % p.nx;
+    }
+    return p.mask[(size_t)y * p.nx + x] == 0;
+}
 
 // Displacement of node (x, y), 0 <= x < nx, in lattice units, with the
 // ghost-row rules of the y walls for y = -1 and y = ny.
@@ -56,12 +73,19 @@ __device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, i
     return 8.0 / 3.0 * (left ? p.uw_left[a] : p.uw_right[a]) - 2.0 * u0 + u1 / 3.0;
 }
 
+// Central-difference gradient at (x, y); a hole neighbour takes the node's
+// own displacement (the constant ghost of a traction-free wall).
 template <class TU>
 __device__ inline void grad_at(const TU *u, const FieldParams &p, int x, int y, double H[4])
 {
+    const bool hxp = in_hole(p, x + 1, y), hxm = in_hole(p, x - 1, y);
+    const bool hyp = in_hole(p, x, y + 1), hym = in_hole(p, x, y - 1);
     for (int a = 0; a < 2; ++a) {
-        H[2 * a + 0] = 0.5 * (u_at(u, p, a, x + 1, y) - u_at(u, p, a, x - 1, y));
-        H[2 * a + 1] = 0.5 * (u_at(u, p, a, x, y + 1) - u_at(u, p, a, x, y - 1));
+        const double c = (hxp || hxm || hyp || hym) ? u_at(u, p, a, x, y) : 0.0;
+        const double xp = hxp ? c : u_at(u, p, a, x + 1, y), xm = hxm ? c : u_at(u, p, a, x - 1, y);
+        const double yp = hyp ? c : u_at(u, p, a, x, y + 1), ym = hym ? c : u_at(u, p, a, x, y - 1);
+        H[2 * a + 0] = 0.5 * (xp - xm);
+        H[2 * a + 1] = 0.5 * (yp - ym);
     }
 }
 
@@ -95,25 +119,21 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
     double m = 0.0;
     if (s < n) {
         const int y = (int)(s / fp.nx), x = (int)(s - (long long)y * fp.nx);
-        // u0 in lattice units; the staged array has the same layout as u
+        const bool hole = in_hole(fp, x, y);
+        // u0 in lattice units; the staged array has the same layout as u.
+        // The ghost rules apply with the walls at rest (t = 0).
+        FieldParams rest = fp;
+        rest.uw_lo[0] = rest.uw_lo[1] = rest.uw_hi[0] = rest.uw_hi[1] = 0.0;
+        rest.uw_left[0] = rest.uw_left[1] = rest.uw_right[0] = rest.uw_right[1] = 0.0;
         double H[4];
-        for (int a = 0; a < 2; ++a) {
-            auto U = [&](int xx, int yy) {
-                // reuse the ghost rules on the staged double array (walls at rest at t = 0)
-                FieldParams q = fp;
-                q.uw_lo[0] = q.uw_lo[1] = q.uw_hi[0] = q.uw_hi[1] = 0.0;
-                q.uw_left[0] = q.uw_left[1] = q.uw_right[0] = q.uw_right[1] = 0.0;
-                return u_at(p.u0, q, a, xx, yy) * p.inv_dx;
-            };
-            H[2 * a + 0] = 0.5 * (U(x + 1, y) - U(x - 1, y));
-            H[2 * a + 1] = 0.5 * (U(x, y + 1) - U(x, y - 1));
-        }
+        grad_at(p.u0, rest, x, y, H);
+        for (int c = 0; c < 4; ++c) H[c] *= p.inv_dx;
         const double mu = fp.mu;
         const double tr = H[0] + H[3];
         const double r = -tr;
         const double Pxx = -mu * (2.0 * H[0] + tr), Pyy = -mu * (2.0 * H[3] + tr);
         const double Pxy = -mu * (H[1] + H[2]);
-        const double jx = p.v0[s] * p.v_to_j, jy = p.v0[pl + s] * p.v_to_j;
+        const double jx = hole ? 0.0 : p.v0[s] * p.v_to_j, jy = hole ? 0.0 : p.v0[pl + s] * p.v_to_j;
         const double axx = Pxx - r / 3.0, ayy = Pyy - r / 3.0, trA = axx + ayy;
         const double q[9] = {-trA / 3.0,
                              axx - trA / 3.0,
@@ -128,7 +148,7 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
         const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
         const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
         for (int i = 0; i < 9; ++i) {
-            const double fi = w[i] * (r + 3.0 * (ex[i] * jx + ey[i] * jy) + 4.5 * q[i]);
+            const double fi = hole ? 0.0 : w[i] * (r + 3.0 * (ex[i] * jx + ey[i] * jy) + 4.5 * q[i]);
             m = fmax(m, fabs(fi));
             if (p.mode == 1) FStore<TF>::store(static_cast<TF *>(p.f), i * pl + s, (typename PR::TC)fi,
                                                (typename PR::TC)p.f_scale);
@@ -136,8 +156,8 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
         if (p.mode == 1) {
             TU *u = static_cast<TU *>(p.u);
             TJ *j = static_cast<TJ *>(p.j);
-            u[s] = TU(p.u0[s] * p.inv_dx);
-            u[pl + s] = TU(p.u0[pl + s] * p.inv_dx);
+            u[s] = hole ? TU(0) : TU(p.u0[s] * p.inv_dx);
+            u[pl + s] = hole ? TU(0) : TU(p.u0[pl + s] * p.inv_dx);
             j[s] = TJ(jx);
             j[pl + s] = TJ(jy);
         }
@@ -197,9 +217,14 @@ __global__ void __launch_bounds__(256) readout_kernel(const ReadParams p)
     const TU *u = static_cast<const TU *>(p.u);
     const TJ *j = static_cast<const TJ *>(p.j);
     const size_t g = (size_t)y * fp.nx + x;
+    const size_t cp = (size_t)p.count;
+    if (in_hole(fp, x, y)) {  // no material: every value reads as zero
+        const int nv = ((p.what & 1) ? 8 : 0) + ((p.what & 2) ? 9 : 0);
+        for (int k = 0; k < nv; ++k) p.out[k * cp + s] = 0.0;
+        return;
+    }
     double H[4];
     grad_at(u, fp, x, y, H);
-    const size_t cp = (size_t)p.count;
     int k = 0;
     if (p.what & 1) {
         double P[4];
@@ -257,6 +282,7 @@ __global__ void __launch_bounds__(256) diag_kernel(const DiagParams p)
     const TJ *j = static_cast<const TJ *>(p.j);
     for (long long s = (long long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long long)gridDim.x * 256) {
         const int y = (int)(s / fp.nx), x = (int)(s - (long long)y * fp.nx);
+        if (in_hole(fp, x, y)) continue;
         double H[4];
         grad_at(u, fp, x, y, H);
         double r = 0.0;

@@ -18,6 +18,12 @@
 // In the extrapolation variant (end of Sec. 5) u^p takes 2 j_n - j_{n-1}
 // for j at t + dt; j_{n-1} is still in the output buffer of j, which pass 3
 // reads at its own site before pass 4b overwrites it.
+// Holes (Sec. 7.2): a mask marks nodes outside the material. A link from a
+// material node into a hole crosses a traction-free wall half-way; the wall
+// is the one its axis step enters, both for the diagonal that meets a hole
+// corner. In the differences a hole neighbour takes the node's own
+// displacement, and K there is K of the node's gradient with the
+// derivatives along that axis set to zero. Hole nodes hold zeros.
 // Same lattice units, arithmetic and storage rounding as the fused kernel.
 #pragma once
 
@@ -46,6 +52,7 @@ struct GenParams {
     void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
     void *up;    // scratch [2][ny][nx] TU: predictor displacement
     unsigned *flag;
+    const unsigned char *mask;  // [ny][nx] 1 material, 0 hole; nullptr: no holes
 };
 
 // D2Q9 of this implementation (see lattice.hpp)
@@ -111,6 +118,41 @@ __device__ __forceinline__ TU gen_u(const TU *u, const GenParams &p, int a, int 
     return gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, a, t), u0, u1, k);
 }
 
+// node (x, y) lies in a hole; coordinates beyond a periodic edge wrap,
+// beyond a wall they are in no hole
+__device__ __forceinline__ bool g_hole(const GenParams &p, int x, int y)
+{
+    if (!p.mask) return false;
+    if (y < 0 || y >= p.ny) {
+        if (p.bc[EDGE_YMIN] != BC_PERIODIC) return false;
+        y = (y % p.ny + p.ny) % p.ny;
+    }
+    if (x < 0 || x >= p.nx) {
+        if (p.bc[EDGE_XMIN] != BC_PERIODIC) return false;
+        x = (x % p.nx + p.nx) % p.nx;
+    }
+    return p.mask[(size_t)y * p.nx + x] == 0;
+}
+
+// central-difference gradient of u at (x, y) (lattice or ghost ring); a hole
+// neighbour takes the node's own value
+template <class PR>
+__device__ __forceinline__ void gen_grad(const GenParams &p, const typename PR::TU *u, int x, int y, double t,
+                                         typename PR::TC H[4])
+{
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    const bool hxp = g_hole(p, x + 1, y), hxm = g_hole(p, x - 1, y);
+    const bool hyp = g_hole(p, x, y + 1), hym = g_hole(p, x, y - 1);
+    for (int a = 0; a < 2; ++a) {
+        const TU c = (hxp || hxm || hyp || hym) ? gen_u(u, p, a, x, y, t) : TU(0);
+        const TU xp = hxp ? c : gen_u(u, p, a, x + 1, y, t), xm = hxm ? c : gen_u(u, p, a, x - 1, y, t);
+        const TU yp = hyp ? c : gen_u(u, p, a, x, y + 1, t), ym = hym ? c : gen_u(u, p, a, x, y - 1, t);
+        H[2 * a + 0] = TC((xp - xm) * TU(0.5));
+        H[2 * a + 1] = TC((yp - ym) * TU(0.5));
+    }
+}
+
 __device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
 {
     return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * (p.nx + 2) + (size_t)(x + 1);
@@ -130,26 +172,55 @@ __global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int 
     const int y = s / w - 1, x = s % w - 1;
     const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
     const double t = (double)(p.step + which);
-    TC H[4], K[4];
-    for (int a = 0; a < 2; ++a) {
-        H[2 * a + 0] = TC((gen_u(u, p, a, x + 1, y, t) - gen_u(u, p, a, x - 1, y, t)) * TU(0.5));
-        H[2 * a + 1] = TC((gen_u(u, p, a, x, y + 1, t) - gen_u(u, p, a, x, y - 1, t)) * TU(0.5));
-    }
-    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
     TC *Kp = static_cast<TC *>(p.K);
+    if (g_hole(p, x, y)) {
+        for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = TC(0);
+        return;
+    }
+    TC H[4], K[4];
+    gen_grad<PR>(p, u, x, y, t, H);
+    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
     for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
     if (which == 0 && x >= 0 && x < p.nx && y >= 0 && y < p.ny && !(J > TC(0))) p.flag[0] = 1u;
 }
 
-// central divergence of K at node (x, y) plus the body force (eq. (23))
-template <class TC>
-__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, TC S[2])
+// K at the hole neighbour of (x, y) across axis n: K of the node's gradient
+// with the derivatives along n set to zero
+template <class PR>
+__device__ __noinline__ void gen_k_hole(const GenParams &p, int x, int y, int which, int n,
+                                        typename PR::TC K[4])
 {
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    TC H[4];
+    gen_grad<PR>(p, static_cast<const TU *>(which ? p.up : p.u_in), x, y, (double)(p.step + which), H);
+    H[n] = TC(0);
+    H[2 + n] = TC(0);
+    stress_sum(H, TC(p.lam), TC(p.mu), K);
+}
+
+// central divergence of K at node (x, y) plus the body force (eq. (23));
+// which: K of u_n (0) or of u^p (1), for hole neighbours
+template <class PR>
+__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, int which, typename PR::TC S[2])
+{
+    using TC = typename PR::TC;
     const TC *K = static_cast<const TC *>(p.K);
-    S[0] = TC(p.bx) + TC(0.5) * (K[k_index(p, 0, x + 1, y)] - K[k_index(p, 0, x - 1, y)]) +
-           TC(0.5) * (K[k_index(p, 1, x, y + 1)] - K[k_index(p, 1, x, y - 1)]);
-    S[1] = TC(p.by) + TC(0.5) * (K[k_index(p, 2, x + 1, y)] - K[k_index(p, 2, x - 1, y)]) +
-           TC(0.5) * (K[k_index(p, 3, x, y + 1)] - K[k_index(p, 3, x, y - 1)]);
+    TC kxp[4], kxm[4], kyp[4], kym[4];
+    for (int c = 0; c < 4; ++c) {
+        kxp[c] = K[k_index(p, c, x + 1, y)];
+        kxm[c] = K[k_index(p, c, x - 1, y)];
+        kyp[c] = K[k_index(p, c, x, y + 1)];
+        kym[c] = K[k_index(p, c, x, y - 1)];
+    }
+    if (p.mask) {
+        if (g_hole(p, x + 1, y)) gen_k_hole<PR>(p, x, y, which, 0, kxp);
+        if (g_hole(p, x - 1, y)) gen_k_hole<PR>(p, x, y, which, 0, kxm);
+        if (g_hole(p, x, y + 1)) gen_k_hole<PR>(p, x, y, which, 1, kyp);
+        if (g_hole(p, x, y - 1)) gen_k_hole<PR>(p, x, y, which, 1, kym);
+    }
+    S[0] = TC(p.bx) + TC(0.5) * (kxp[0] - kxm[0]) + TC(0.5) * (kyp[1] - kym[1]);
+    S[1] = TC(p.by) + TC(0.5) * (kxp[2] - kxm[2]) + TC(0.5) * (kyp[3] - kym[3]);
 }
 
 // Pass 2: source, moments, equilibrium (20), forcing (22) and BGK collision (4)
@@ -164,11 +235,12 @@ __global__ void __launch_bounds__(256) collide_pass(const GenParams p)
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const int y = s / p.nx, x = s - y * p.nx;
+    if (g_hole(p, x, y)) return;
     const size_t pl = (size_t)p.plane;
     const TF *fin = static_cast<const TF *>(p.f_in);
     const TJ *jin = static_cast<const TJ *>(p.j_in);
     TC S[2], f[9], fc[9], r, pxx;
-    gen_source(p, x, y, S);
+    gen_source<PR>(p, x, y, 0, S);
     for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
     collide(f, TC(jin[s]), TC(jin[pl + s]), S[0], S[1], TC(p.omega), fc, r, pxx);
     TC *fcol = static_cast<TC *>(p.fcol);
@@ -186,15 +258,19 @@ __global__ void __launch_bounds__(256) collide_pass(const GenParams p)
 // each traction wall's transform gives its normal column, -s T* + K N; a
 // tangential entry keeps the populations' second moment; at a corner the
 // off-diagonal entry is the mean of both walls' values.
+// hole: the walls are those of a hole (traction-free), not of the edges.
 template <class PR>
 __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, int y, int o, int sx, int sy,
-                                                    typename PR::TC fco)
+                                                    typename PR::TC fco, bool hole)
 {
     using TF = typename PR::TF;
     using TC = typename PR::TC;
     using FS = FStore<TF>;
     const int ex = sx < 0 ? EDGE_XMIN : EDGE_XMAX, ey = sy < 0 ? EDGE_YMIN : EDGE_YMAX;
-    const bool dx = sx != 0 && p.bc[ex] == BC_DIRICHLET, dy = sy != 0 && p.bc[ey] == BC_DIRICHLET;
+    const bool dx = !hole && sx != 0 && p.bc[ex] == BC_DIRICHLET;
+    const bool dy = !hole && sy != 0 && p.bc[ey] == BC_DIRICHLET;
+    const double tx0 = hole ? 0.0 : p.val[ex][0], tx1 = hole ? 0.0 : p.val[ex][1];
+    const double ty0 = hole ? 0.0 : p.val[ey][0], ty1 = hole ? 0.0 : p.val[ey][1];
     const TC w = gweight<TC>(o);
     const TC cx = TC(kGx[o]), cy = TC(kGy[o]);
     if (dx || dy) {
@@ -221,13 +297,13 @@ __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, i
     TC qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
     if (sx) {  // x wall: column x of Pbar*, q_a = -s T_a + K_ax
         const TC sg = TC(sx);
-        qx0 = -sg * TC(p.val[ex][0]) + K[k_index(p, 0, x, y)];
-        qx1 = -sg * TC(p.val[ex][1]) + K[k_index(p, 2, x, y)];
+        qx0 = -sg * TC(tx0) + K[k_index(p, 0, x, y)];
+        qx1 = -sg * TC(tx1) + K[k_index(p, 2, x, y)];
     }
     if (sy) {  // y wall: column y, q_a = -s T_a + K_ay
         const TC sg = TC(sy);
-        qy0 = -sg * TC(p.val[ey][0]) + K[k_index(p, 1, x, y)];
-        qy1 = -sg * TC(p.val[ey][1]) + K[k_index(p, 3, x, y)];
+        qy0 = -sg * TC(ty0) + K[k_index(p, 1, x, y)];
+        qy1 = -sg * TC(ty1) + K[k_index(p, 3, x, y)];
     }
     if (sx && sy) {
         Pxx = qx0;
@@ -263,11 +339,32 @@ __global__ void __launch_bounds__(256) stream_pass(const GenParams p)
     if (s >= n) return;
     const int y = s / p.nx, x = s - y * p.nx;
     const size_t pl = (size_t)p.plane;
+    if (g_hole(p, x, y)) {  // no material: zero state
+        for (int i = 0; i < 9; ++i) FS::store(static_cast<TF *>(p.f_out), i * pl + s, TC(0), TC(p.f_scale));
+        if (p.pc) {
+            static_cast<TC *>(p.jf)[s] = static_cast<TC *>(p.jf)[pl + s] = TC(0);
+            static_cast<TU *>(p.up)[s] = static_cast<TU *>(p.up)[pl + s] = TU(0);
+        } else {
+            static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
+            static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
+        }
+        return;
+    }
     const TC *fcol = static_cast<const TC *>(p.fcol);
     const bool perx = p.bc[EDGE_XMIN] == BC_PERIODIC, pery = p.bc[EDGE_YMIN] == BC_PERIODIC;
     TC fn[9];
     for (int i = 0; i < 9; ++i) {
         int sxp = x - kGx[i], syp = y - kGy[i];
+        if (i && g_hole(p, sxp, syp)) {
+            // the link o = opp(i) enters a hole: the wall its axis step
+            // enters, or both for the diagonal through a hole corner
+            const int o = kGopp[i];
+            const bool hx = kGx[o] && g_hole(p, x + kGx[o], y), hy = kGy[o] && g_hole(p, x, y + kGy[o]);
+            const bool both = !hx && !hy;
+            fn[i] = gen_wall<PR>(p, x, y, o, (hx || both) ? kGx[o] : 0, (hy || both) ? kGy[o] : 0,
+                                 fcol[o * pl + s], true);
+            continue;
+        }
         bool cx = sxp < 0 || sxp >= p.nx, cy = syp < 0 || syp >= p.ny;
         if (cx && perx) {
             sxp = (sxp + p.nx) % p.nx;
@@ -281,7 +378,7 @@ __global__ void __launch_bounds__(256) stream_pass(const GenParams p)
             fn[i] = fcol[i * pl + (size_t)syp * p.nx + sxp];
         } else {
             const int o = kGopp[i];  // the link that left through the wall
-            fn[i] = gen_wall<PR>(p, x, y, o, cx ? kGx[o] : 0, cy ? kGy[o] : 0, fcol[o * pl + s]);
+            fn[i] = gen_wall<PR>(p, x, y, o, cx ? kGx[o] : 0, cy ? kGy[o] : 0, fcol[o * pl + s], false);
         }
     }
     const bool sr = FS::kStochastic && p.sr;
@@ -331,8 +428,13 @@ __global__ void __launch_bounds__(256) update_pass(const GenParams p)
     if (s >= n) return;
     const int y = s / p.nx, x = s - y * p.nx;
     const size_t pl = (size_t)p.plane;
+    if (g_hole(p, x, y)) {
+        static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
+        static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
+        return;
+    }
     TC Sp[2];
-    gen_source(p, x, y, Sp);
+    gen_source<PR>(p, x, y, 1, Sp);
     const TC *jf = static_cast<const TC *>(p.jf);
     const TU *u = static_cast<const TU *>(p.u_in);
     const TJ *jin = static_cast<const TJ *>(p.j_in);

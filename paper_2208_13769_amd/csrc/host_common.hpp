@@ -244,6 +244,7 @@ struct PlateIO {
     double val_lo[2], val_hi[2];
     int bc_left, bc_right;      // x edges (periodic unless set)
     double val_left[2], val_right[2];
+    const unsigned char *mask;  // device [ny][nx] material mask, or nullptr
     void *f, *u, *j;            // current state copy
     void *f_other;              // the other copy (staging for start-up)
     double f_scale;
@@ -276,6 +277,7 @@ inline FieldParams field_params(const PlateIO &io, double t_steps)
     }
     fp.lam = U.lam / U.stress();
     fp.mu = U.mu / U.stress();
+    fp.mask = io.mask;
     return fp;
 }
 

@@ -23,6 +23,7 @@ struct Layout {
     size_t staging, staging_bytes;
     size_t partials, small, total;
     size_t scratch, total_walled;  // scratch of the general passes (walls on the x edges)
+    size_t mask;                   // material mask [ny][nx] bytes, after the scratch
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -50,7 +51,8 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     off = align_up(off + 64 * sizeof(double));
     L.total = off;
     L.scratch = off;
-    L.total_walled = align_up(off + general_scratch(nx, ny, p));
+    L.mask = align_up(off + general_scratch(nx, ny, p));
+    L.total_walled = align_up(L.mask + (size_t)nx * ny);
     return L;
 }
 
@@ -78,10 +80,15 @@ struct lbm_solver {
     int sr = 0;   // stochastic rounding of 16-bit populations
     unsigned long long seed = 0;
     bool force_general = false;  // run the general passes even without x walls
+    bool has_mask = false;       // holes (lbm_set_mask)
 
     bool general() const
     {
-        return force_general || bc[LBM_EDGE_XMIN] != LBM_BC_PERIODIC || scheme == LBM_SCHEME_EXTRAP;
+        return force_general || has_mask || bc[LBM_EDGE_XMIN] != LBM_BC_PERIODIC || scheme == LBM_SCHEME_EXTRAP;
+    }
+    const unsigned char *mask_ptr() const
+    {
+        return has_mask ? reinterpret_cast<const unsigned char *>(ws + L.mask) : nullptr;
     }
     std::string err;
 
@@ -117,6 +124,7 @@ struct lbm_solver {
         p.staging_bytes = L.staging_bytes;
         p.partials = reinterpret_cast<double *>(ws + L.partials);
         p.diag_out = reinterpret_cast<double *>(ws + L.small + 64);
+        p.mask = mask_ptr();
         p.stream = stream;
         return p;
     }
@@ -322,6 +330,48 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
     return LBM_OK;
 }
 
+lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (h->fields) return fail(h, LBM_ERR_STATE, "set the mask before the fields");
+    if (!solid) {
+        h->has_mask = false;
+        return LBM_OK;
+    }
+    if (h->ws_bytes < h->L.total_walled)
+        return fail(h, LBM_ERR_NOMEM, "holes need a workspace of lbm_workspace_bytes_walled() bytes");
+    const int nx = h->nx, ny = h->ny;
+    const bool perx = h->bc[LBM_EDGE_XMIN] == LBM_BC_PERIODIC, pery = h->bc[LBM_EDGE_YMIN] == LBM_BC_PERIODIC;
+    auto hole = [&](int x, int y) {
+        if (y < 0 || y >= ny) {
+            if (!pery) return false;
+            y = (y % ny + ny) % ny;
+        }
+        if (x < 0 || x >= nx) {
+            if (!perx) return false;
+            x = (x % nx + nx) % nx;
+        }
+        return solid[(size_t)y * nx + x] == 0;
+    };
+    bool any_material = false;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            if (hole(x, y)) {
+                if (((y == 0 || y == ny - 1) && !pery) || ((x == 0 || x == nx - 1) && !perx))
+                    return fail(h, LBM_ERR_ARG, "a hole touches a wall edge");
+                continue;
+            }
+            any_material = true;
+            if ((hole(x - 1, y) && hole(x + 1, y)) || (hole(x, y - 1) && hole(x, y + 1)))
+                return fail(h, LBM_ERR_ARG, "material one node thick between holes");
+        }
+    if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
+    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, solid, (size_t)nx * ny, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->has_mask = true;
+    return LBM_OK;
+}
+
 lbm_status lbm_set_general_path(lbm_solver *h, int on)
 {
     if (!h) return LBM_ERR_ARG;
@@ -432,6 +482,7 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.seed = sp.seed;
         gp.pc = h->scheme == LBM_SCHEME_EXTRAP ? 2 : (pc ? 1 : 0);
         gp.flag = sp.flag;
+        gp.mask = h->mask_ptr();
         for (int64_t k = 0; k < nsteps; ++k) {
             gp.f_in = h->fptr(h->cur);
             gp.u_in = h->uptr(h->cur);

@@ -37,7 +37,7 @@ EXPORTED = [
     "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
     "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
     "lbm_resident_blocks", "lbm_set_rounding", "lbm_read_derived", "lbm_sample", "lbm_batch_read_derived",
-    "lbm_batch_sample", "lbm_workspace_bytes_walled", "lbm_set_general_path",
+    "lbm_batch_sample", "lbm_workspace_bytes_walled", "lbm_set_general_path", "lbm_set_mask",
     "lbm_batch_plate_bytes", "lbm_batch_plate_tiles", "lbm_batch_workspace_bytes", "lbm_batch_create",
     "lbm_batch_add", "lbm_batch_step", "lbm_batch_query", "lbm_batch_read", "lbm_batch_retire", "lbm_batch_info",
     "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_set_steps_per_launch",
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_workspace_bytes_walled.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.lbm_set_general_path.restype = ctypes.c_int
     lib.lbm_set_general_path.argtypes = [vp, ctypes.c_int]
+    lib.lbm_set_mask.restype = ctypes.c_int
+    lib.lbm_set_mask.argtypes = [vp, vp]
     lib.lbm_create.restype = ctypes.c_int
     lib.lbm_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                vp, sz, vp, ctypes.POINTER(vp)]
@@ -150,6 +152,14 @@ def lbm_workspace_bytes_walled(nx: int, ny: int, precision: int) -> int:
 
 def lbm_set_general_path(h, on: bool):
     _check(load_library().lbm_set_general_path(h, int(bool(on))), h)
+
+
+def lbm_set_mask(h, solid):
+    if solid is None:
+        _check(load_library().lbm_set_mask(h, None), h)
+        return
+    m = np.ascontiguousarray(solid, dtype=np.uint8)
+    _check(load_library().lbm_set_mask(h, m.ctypes.data_as(ctypes.c_void_p)), h)
 
 
 def lbm_create(nx, ny, dx, precision, scheme, workspace_ptr, ws_bytes, stream_ptr):
@@ -315,6 +325,10 @@ class Solver:
 
     def set_general_path(self, on: bool):
         lbm_set_general_path(self.h, on)
+
+    def set_mask(self, solid):
+        """solid: [ny][nx] array, nonzero for material, 0 for holes; None removes it."""
+        lbm_set_mask(self.h, solid)
 
     def set_fields(self, u0, v0):
         lbm_set_fields(self.h, u0, v0)

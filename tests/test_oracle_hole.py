@@ -1,0 +1,156 @@
+"""Pins of the oracle's holes (Sec. 7.2; reading Q23), against results that do
+not use the hole code:
+
+- A hole that is a band of whole rows (columns) in a plate periodic in y (x)
+  leaves a strip bounded by two traction-free walls: the result must equal
+  the strip run with traction walls on its edges (Q11), which the resonance
+  pins already tie down. Bands of rows and columns together leave a block
+  with four walls and four corners (Q20).
+- Uniform translation of a plate with a hole between free walls is exact.
+- A centred hole under symmetric tension keeps both mirror symmetries.
+- An off-centre hole and its loads, transposed, give the transposed result
+  (the x and y hole walls are written separately).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+N_, D_ = O.NEUMANN_T, O.DIRICHLET_J
+
+
+def _run(p, u0, v0, n, loads=None):
+    s = O.Solver(p, u0, v0)
+    for k in range(n):
+        if loads:
+            for e, v in loads(k).items():
+                s.set_boundary_value(e, v)
+        s.step(1)
+    u, v, P = s.fields()
+    return u, v, P, s
+
+
+def _pad(a, shape):
+    out = np.zeros(a.shape[:-2] + shape)
+    out[..., : a.shape[-2], : a.shape[-1]] = a
+    return out
+
+
+@pytest.mark.parametrize("scheme", [O.PC, O.EXPLICIT])
+def test_row_band_equals_traction_walls(scheme):
+    nx, ny, k, n = 12, 15, 3, 80
+    rng = np.random.Generator(np.random.PCG64(21))
+    u0 = 0.01 * rng.standard_normal((2, ny - k, nx))
+    v0 = 0.01 * rng.standard_normal((2, ny - k, nx))
+    common = dict(lam=0.07, mu=0.05, tau_over_dt=0.9, scheme=scheme, body=(0.001, -0.002))
+    uw, vw, Pw, _ = _run(O.Params(nx=nx, ny=ny - k, bc_ymin=N_, bc_ymax=N_, **common), u0, v0, n)
+    m = np.ones((ny, nx), np.uint8)
+    m[ny - k:] = 0
+    uh, vh, Ph, _ = _run(O.Params(nx=nx, ny=ny, solid=m, **common), _pad(u0, (ny, nx)), _pad(v0, (ny, nx)), n)
+    for a, b in ((uh[:, : ny - k], uw), (vh[:, : ny - k], vw), (Ph[:, :, : ny - k], Pw)):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    assert np.abs(uh[:, ny - k:]).max() == 0.0 and np.abs(Ph[:, :, ny - k:]).max() == 0.0
+
+
+def test_column_band_equals_traction_walls():
+    nx, ny, k, n = 15, 12, 2, 80
+    rng = np.random.Generator(np.random.PCG64(22))
+    u0 = 0.01 * rng.standard_normal((2, ny, nx - k))
+    v0 = 0.01 * rng.standard_normal((2, ny, nx - k))
+    common = dict(lam=0.12, mu=0.05, tau_over_dt=0.8, body=(-0.001, 0.0005))
+    uw, vw, Pw, _ = _run(O.Params(nx=nx - k, ny=ny, bc_xmin=N_, bc_xmax=N_, **common), u0, v0, n)
+    m = np.ones((ny, nx), np.uint8)
+    m[:, nx - k:] = 0
+    uh, vh, Ph, _ = _run(O.Params(nx=nx, ny=ny, solid=m, **common), _pad(u0, (ny, nx)), _pad(v0, (ny, nx)), n)
+    for a, b in ((uh[:, :, : nx - k], uw), (Ph[:, :, :, : nx - k], Pw)):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_row_and_column_bands_equal_a_four_wall_block():
+    nx, ny, n = 11, 10, 80
+    rng = np.random.Generator(np.random.PCG64(23))
+    u0 = 0.01 * rng.standard_normal((2, ny, nx))
+    v0 = 0.01 * rng.standard_normal((2, ny, nx))
+    common = dict(lam=0.07, mu=0.05, tau_over_dt=0.8, body=(0.001, -0.002))
+    ub, vb, Pb, _ = _run(O.Params(nx=nx, ny=ny, bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_, **common), u0, v0, n)
+    m = np.zeros((ny + 3, nx + 2), np.uint8)
+    m[:ny, :nx] = 1
+    uh, vh, Ph, _ = _run(O.Params(nx=nx + 2, ny=ny + 3, solid=m, **common), _pad(u0, m.shape), _pad(v0, m.shape), n)
+    for a, b in ((uh[:, :ny, :nx], ub), (vh[:, :ny, :nx], vb), (Ph[:, :, :ny, :nx], Pb)):
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_translation_with_a_hole_is_exact():
+    n, steps = 24, 50
+    m = np.ones((n, n), np.uint8)
+    m[8:15, 6:17] = 0
+    p = O.Params(nx=n, ny=n, lam=0.1, mu=0.05, bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_, solid=m)
+    vel = np.array([0.013, -0.007])
+    v0 = vel[:, None, None] * m[None].astype(float)
+    u, v, P, s = _run(p, np.zeros((2, n, n)), v0, steps)
+    t = steps * O.dt(p)
+    assert np.abs(v - v0).max() <= 1e-14
+    assert np.abs(u - v0 * t).max() <= 1e-13 * np.abs(vel).max() * t
+    assert np.abs(P).max() <= 1e-14
+
+
+def test_centred_hole_keeps_both_mirror_symmetries():
+    n, h, steps, T = 40, 16, 150, 0.02
+    a = (n - h) // 2
+    m = np.ones((n, n), np.uint8)
+    m[a:a + h, a:a + h] = 0
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.8,
+                 bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_, solid=m)
+    dt = O.dt(p)
+    loads = lambda k: {"ymax": (0.0, T * min(k * dt, 1.0)), "ymin": (0.0, -T * min(k * dt, 1.0))}
+    z = np.zeros((2, n, n))
+    u, v, P, s = _run(p, z, z.copy(), steps, loads)
+    scale = np.abs(u).max()
+    assert scale > 1e-4
+    assert np.abs(u[0] + u[0][:, ::-1]).max() <= 1e-12 * scale
+    assert np.abs(u[1] - u[1][:, ::-1]).max() <= 1e-12 * scale
+    assert np.abs(u[0] - u[0][::-1, :]).max() <= 1e-12 * scale
+    assert np.abs(u[1] + u[1][::-1, :]).max() <= 1e-12 * scale
+    # the hole opens along the load: its top edge moves up, the sides move in
+    assert u[1][a + h, n // 2] > u[1][a - 1, n // 2]
+    assert u[0][n // 2, a - 1] > 0 > u[0][n // 2, a + h]
+
+
+def _T(a):
+    return np.ascontiguousarray(a[::-1].transpose(0, 2, 1))
+
+
+def test_transposed_hole_problem_gives_the_transposed_result():
+    nx, ny, steps = 26, 20, 100
+    m = np.ones((ny, nx), np.uint8)
+    m[5:12, 8:19] = 0
+    m[14:17, 3:6] = 0
+    rng = np.random.Generator(np.random.PCG64(24))
+    u0 = 0.005 * rng.standard_normal((2, ny, nx)) * m[None]
+    v0 = 0.005 * rng.standard_normal((2, ny, nx)) * m[None]
+    common = dict(lam=0.09, mu=0.05, tau_over_dt=0.85)
+    py = O.Params(nx=nx, ny=ny, bc_ymin=D_, bc_ymax=N_, val_ymin=(0.00002, 0.0), val_ymax=(0.0001, 0.0002),
+                  body=(0.00004, -0.00001), solid=m, **common)
+    px = O.Params(nx=ny, ny=nx, bc_xmin=D_, bc_xmax=N_, val_xmin=(0.0, 0.00002), val_xmax=(0.0002, 0.0001),
+                  body=(-0.00001, 0.00004), solid=np.ascontiguousarray(m.T), **common)
+    uy, vy, Py, _ = _run(py, u0, v0, steps)
+    ux, vx, Px, _ = _run(px, _T(u0), _T(v0), steps)
+    assert np.isfinite(uy).all() and np.abs(uy).max() > 0.1
+    for a, b in ((ux, _T(uy)), (vx, _T(vy))):
+        assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    assert np.abs(Px - np.ascontiguousarray(Py[::-1, ::-1].transpose(0, 1, 3, 2))).max() <= 1e-12 * np.abs(Py).max()
+
+
+@pytest.mark.parametrize("case", ["edge", "thin"])
+def test_invalid_masks_are_rejected(case):
+    n = 12
+    m = np.ones((n, n), np.uint8)
+    if case == "edge":
+        m[0, 4:7] = 0  # touches the bottom wall
+        kw = dict(bc_ymin=N_, bc_ymax=N_)
+    else:
+        m[3:9, 3] = 0
+        m[3:9, 5] = 0  # column 4 is one node thick
+        kw = {}
+    with pytest.raises(ValueError):
+        O.Solver(O.Params(nx=n, ny=n, solid=m, **kw), np.zeros((2, n, n)), np.zeros((2, n, n)))
