@@ -111,6 +111,150 @@ def cpu_baseline(wl, steps: int):
                        f"FP64, {el:.1f} s"), (u, v, P)
 
 
+# Element sizes (f, u, j, compute) of each storage form.
+ELEM = {"fp64": (8, 8, 8, 8), "fp32": (4, 4, 4, 4), "fp32u64": (4, 8, 4, 4), "fp16": (2, 8, 4, 4),
+        "bf16": (2, 8, 4, 4)}
+
+
+def general_bytes_per_site(precision: str) -> dict:
+    """Algorithmic bytes per site and step of each general pass: the fields it
+    must read and write once (neighbour values come from cache)."""
+    F, U, J, C = ELEM[precision]
+    return {
+        "stress_pass (u_n)": 2 * U + 4 * C,                              # u -> K on the ring
+        "collide_pass": 4 * C + 9 * F + 2 * J + 9 * C + 2 * C,            # K, f, j -> f_col, S
+        "stream_pass": 9 * C + 2 * C + 2 * U + 2 * J + 9 * F + 2 * C + 2 * U,  # f_col, S, u, j -> f, jf, u^p
+        "stress_pass (u^p)": 2 * U + 4 * C,                              # u^p -> K
+        "update_pass": 4 * C + 2 * C + 2 * U + 2 * J + 2 * U + 2 * J,     # K, jf, u, j -> u, j
+    }
+
+
+def copy_probe(mib: int, device):
+    """A plain elementwise copy of `mib` MiB (float32 read + write), three
+    times: its HBM counter readings calibrate the kernels' (profiling runs)."""
+    import torch
+
+    if mib <= 0:
+        return
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=device)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def general_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ["general_kernels.hpp", "step_kernel.hpp", "lattice.hpp"]:
+        with open(os.path.join(ROOT, "paper_2208_13769_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def general_traffic_for(precision: str, n: int):
+    """HBM bytes per step of the hole workload from the committed rocprofv3
+    counter record, if it was taken on the current source at this size."""
+    path = os.path.join(ROOT, "profiles", f"general_{precision}_{n}_hole_counters.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != general_source_hash() or rec.get("n") != n:
+        return None
+    return rec.get("hbm_bytes_per_step")
+
+
+def bench_hole(args):
+    """The plate with a square hole of Sec. 7.2 at a size that fills the GPU:
+    side l = 1 on n x n nodes (default 4096), a centred hole of 0.4 l, all four
+    edges and the hole traction-free except for a normal traction of 0.02 mu
+    on the top and bottom edges, lam = mu = rho0 = 1, tau/dt = 0.8, starting
+    at rest. It runs on the general per-site passes (five launches per step)."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2208_13769_amd import lbm
+
+    n = args.hole_n
+    prec = args.precision or "fp32u64"
+    h = int(round(0.4 * n))
+    a = (n - h) // 2
+    solid = np.ones((n, n), np.uint8)
+    solid[a:a + h, a:a + h] = 0
+    material = int(solid.sum())
+    T = 0.02
+    z = np.zeros((2, n, n))
+    s = lbm.Solver(n, n, 1.0 / n, prec, "pc", walled=True)
+    s.set_material(1.0, 1.0, 1.0, 0.8)
+    s.set_boundary(lbm.LBM_EDGE_XMIN, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
+    s.set_boundary(lbm.LBM_EDGE_XMAX, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
+    s.set_boundary(lbm.LBM_EDGE_YMIN, lbm.LBM_BC_NEUMANN_T, (0.0, -T))
+    s.set_boundary(lbm.LBM_EDGE_YMAX, lbm.LBM_BC_NEUMANN_T, (0.0, T))
+    s.set_mask(solid)
+    s.set_fields(z, z)
+    copy_probe(args.copy_probe_mib, s.device)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.step(args.steps)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    u, v, P, d, st = s.read()
+    s.close()
+    per_pass = general_bytes_per_site(prec)
+    # hole nodes move no state: the bytes count material nodes, as MLUPS does
+    step_bytes = sum(per_pass.values()) * material
+    achieved = step_bytes / (ms_step / 1e3) / 1e9
+    traffic = general_traffic_for(prec, n)
+    out = {
+        "metric": METRIC, "value": round(material / (ms_step / 1e3) / 1e6, 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": f"plate with a centred square hole (Sec. 7.2 geometry) on {n}x{n} nodes, hole "
+                               f"{h}x{h}, all edges and the hole traction-free except 0.02 mu normal traction on "
+                               "top and bottom, lam = mu = 1, tau/dt = 0.8, predictor-corrector; general per-site "
+                               "passes; MLUPS counts material nodes",
+                   "grid": [n, n], "material_sites": material, "precision": prec, "scheme": "pc"},
+        # whole-step roofline: the passes of one step as one unit (bytes each pass must move)
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "general passes, 8 launches per step (traffic: HBM bytes per step)",
+                     "bytes_per_site_per_step": per_pass},
+        "run": {"status": int(st), "min_J": d.min_J, "max_strain": d.max_strain},
+    }
+    if not args.no_cpu_baseline:
+        steps = args.cpu_steps
+        p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.8, bc_xmin=O.NEUMANN_T,
+                     bc_xmax=O.NEUMANN_T, bc_ymin=O.NEUMANN_T, bc_ymax=O.NEUMANN_T, val_ymin=(0.0, -T),
+                     val_ymax=(0.0, T), solid=solid)
+        ref = O.Solver(p, z, z)
+        t0 = time.perf_counter()
+        ref.step(steps)
+        el = time.perf_counter() - t0
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": material * steps / el / 1e6, "unit": "MLUPS", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{steps} time steps of the full grid from rest, FP64, {el:.1f} s"}
+        g = lbm.Solver(n, n, 1.0 / n, prec, "pc", walled=True)
+        g.set_material(1.0, 1.0, 1.0, 0.8)
+        for e, val in ((lbm.LBM_EDGE_XMIN, (0.0, 0.0)), (lbm.LBM_EDGE_XMAX, (0.0, 0.0)),
+                       (lbm.LBM_EDGE_YMIN, (0.0, -T)), (lbm.LBM_EDGE_YMAX, (0.0, T))):
+            g.set_boundary(e, lbm.LBM_BC_NEUMANN_T, val)
+        g.set_mask(solid)
+        g.set_fields(z, z)
+        g.step(steps)
+        ug, _, Pg, _, _ = g.read()
+        g.close()
+        uo, _, Po = ref.fields()
+        out["error_vs_oracle"] = {"steps": steps, "rel_l2_u": float(np.linalg.norm(ug - uo) / np.linalg.norm(uo)),
+                                  "rel_l2_P": float(np.linalg.norm(Pg - Po) / np.linalg.norm(Po))}
+    print(json.dumps(out), flush=True)
+
+
 def bench_config4(args):
     """256 plates of uneven sizes in one batch (one persistent launch per one
     or two steps, graph-captured chunks), FP16 populations, 2000 steps each."""
@@ -225,6 +369,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=200, help="config4: steps per graph-captured chunk")
     ap.add_argument("--batch-spl", type=int, default=0,
                     help="config4: time steps per batch launch (1 or 2; 0 = the batch's default)")
+    ap.add_argument("--hole-n", type=int, default=4096, help="hole: nodes per side")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -236,6 +381,9 @@ def main():
     from paper_2208_13769_amd import lbm
     from paper_2208_13769_amd.autotune import best_tiling
 
+    if args.workload == "hole":
+        bench_hole(args)
+        return
     if args.workload == "config4":
         bench_config4(args)
         return
@@ -263,14 +411,7 @@ def main():
     spl = s.steps_per_launch()
 
     stream = s.stream
-    if args.copy_probe_mib > 0:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=s.device)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_probe(args.copy_probe_mib, s.device)
     s.step(args.warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)

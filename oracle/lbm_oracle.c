@@ -486,8 +486,8 @@ static double bb_term(const oracle_params *p, int i, const double jstar[2])
 }
 
 /* Periodic edges come in pairs. Hole nodes (Q23) keep off rows and columns
- * next to a wall, and no material node has hole nodes on both sides along
- * one axis. */
+ * next to a wall, and neither a material node nor a hole node has nodes of
+ * the other kind on both sides along one axis. */
 static int edges_valid(const oracle_params *p)
 {
     if ((p->bc_xmin == ORACLE_PERIODIC) != (p->bc_xmax == ORACLE_PERIODIC) ||
@@ -499,6 +499,9 @@ static int edges_valid(const oracle_params *p)
             int hole = in_hole(p, y, x);
             if (hole && (((y == 0 || y == p->ny - 1) && p->bc_ymin != ORACLE_PERIODIC) ||
                          ((x == 0 || x == p->nx - 1) && p->bc_xmin != ORACLE_PERIODIC)))
+                return 0;
+            if (hole && ((!in_hole(p, y, x - 1) && !in_hole(p, y, x + 1)) ||
+                         (!in_hole(p, y - 1, x) && !in_hole(p, y + 1, x))))
                 return 0;
             if (!hole && ((in_hole(p, y, x - 1) && in_hole(p, y, x + 1)) ||
                           (in_hole(p, y - 1, x) && in_hole(p, y + 1, x))))

@@ -4,8 +4,9 @@
 // The fused step kernel marches rows with a register/LDS pipeline whose x
 // halo is periodic; walls on the x edges need ghost columns and wall rules
 // in every stage, which that pipeline cannot hold without extra barriers.
-// These kernels do one time step in four or five launches over full fields
-// instead (one thread per site):
+// These kernels do one time step as per-site passes over full fields
+// instead (one thread per site; the stress and streaming passes in two
+// launches each, interior nodes and a list of edge nodes):
 //   1. K = P + Pbar on the lattice and one ring of ghost nodes, from u_n and
 //      its ghost values (stress_pass);
 //   2. source S_n (central divergence of K), moments, equilibrium and BGK
@@ -23,7 +24,12 @@
 // is the one its axis step enters, both for the diagonal that meets a hole
 // corner. In the differences a hole neighbour takes the node's own
 // displacement, and K there is K of the node's gradient with the
-// derivatives along that axis set to zero. Hole nodes hold zeros.
+// derivatives along that axis set to zero. Holes are at least two nodes
+// wide, so a hole node has at most one material neighbour per axis: the
+// stress pass stores that K in the hole node's own slot (columns of the x
+// neighbour's K in entries 0 and 2, of the y neighbour's in 1 and 3, the
+// entries the divergence reads), and the source needs no special case.
+// Hole nodes hold zero state.
 // Same lattice units, arithmetic and storage rounding as the fused kernel.
 #pragma once
 
@@ -53,6 +59,9 @@ struct GenParams {
     void *up;    // scratch [2][ny][nx] TU: predictor displacement
     unsigned *flag;
     const unsigned char *mask;  // [ny][nx] 1 material, 0 hole; nullptr: no holes
+    const int *edge_k;          // ring indices (y + 1)(nx + 2) + x + 1 of the stress pass's edge nodes
+    const int *edge_f;          // lattice indices of the stream pass's edge nodes
+    int n_edge_k, n_edge_f;
 };
 
 // D2Q9 of this implementation (see lattice.hpp)
@@ -153,41 +162,26 @@ __device__ __forceinline__ void gen_grad(const GenParams &p, const typename PR::
     }
 }
 
+// (x, y) and its eight neighbours are lattice nodes of the material (no
+// ghost value, no wall, no hole): the common case, taken without branches
+__device__ __forceinline__ bool g_inner(const GenParams &p, int x, int y)
+{
+    if (x < 1 || x > p.nx - 2 || y < 1 || y > p.ny - 2) return false;
+    if (!p.mask) return true;
+    const unsigned char *m = p.mask + (size_t)(y - 1) * p.nx + (x - 1);
+    const size_t r = (size_t)p.nx;
+    return (m[0] & m[1] & m[2] & m[r] & m[r + 1] & m[r + 2] & m[2 * r] & m[2 * r + 1] & m[2 * r + 2]) != 0;
+}
+
 __device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
 {
     return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * (p.nx + 2) + (size_t)(x + 1);
 }
 
-// Pass 1 / 4a: K = P + Pbar from central differences of u (eqs. (10), (15),
-// (27)) on the lattice and its ring of ghost nodes. `which`: 0 = u_n at step
-// n, 1 = the predictor u^p at step n + 1. Sets the flag where J <= 0.
-template <class PR>
-__global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int which)
-{
-    using TU = typename PR::TU;
-    using TC = typename PR::TC;
-    const int w = p.nx + 2;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= w * (p.ny + 2)) return;
-    const int y = s / w - 1, x = s % w - 1;
-    const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
-    const double t = (double)(p.step + which);
-    TC *Kp = static_cast<TC *>(p.K);
-    if (g_hole(p, x, y)) {
-        for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = TC(0);
-        return;
-    }
-    TC H[4], K[4];
-    gen_grad<PR>(p, u, x, y, t, H);
-    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
-    for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
-    if (which == 0 && x >= 0 && x < p.nx && y >= 0 && y < p.ny && !(J > TC(0))) p.flag[0] = 1u;
-}
-
 // K at the hole neighbour of (x, y) across axis n: K of the node's gradient
 // with the derivatives along n set to zero
 template <class PR>
-__device__ __noinline__ void gen_k_hole(const GenParams &p, int x, int y, int which, int n,
+__device__ __forceinline__ void gen_k_hole(const GenParams &p, int x, int y, int which, int n,
                                         typename PR::TC K[4])
 {
     using TU = typename PR::TU;
@@ -199,10 +193,62 @@ __device__ __noinline__ void gen_k_hole(const GenParams &p, int x, int y, int wh
     stress_sum(H, TC(p.lam), TC(p.mu), K);
 }
 
-// central divergence of K at node (x, y) plus the body force (eq. (23));
-// which: K of u_n (0) or of u^p (1), for hole neighbours
+// Pass 1 / 4a: K = P + Pbar from central differences of u (eqs. (10), (15),
+// (27)) on the lattice and its ring of ghost nodes. `which`: 0 = u_n at step
+// n, 1 = the predictor u^p at step n + 1. Sets the flag where J <= 0.
+// EDGE: the launch over the listed nodes with a ghost, wall or hole in
+// their stencil; the other launch takes the interior nodes (no branches), so
+// neither carries the registers of the other's path.
+template <class PR, bool EDGE>
+__global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int which)
+{
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    const int w = p.nx + 2;
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    if (tid >= (EDGE ? p.n_edge_k : w * (p.ny + 2))) return;
+    const int s = EDGE ? p.edge_k[tid] : tid;
+    const int y = s / w - 1, x = s % w - 1;
+    const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
+    const double t = (double)(p.step + which);
+    TC *Kp = static_cast<TC *>(p.K);
+    if (!EDGE) {
+        if (!g_inner(p, x, y)) return;
+        const size_t pl = (size_t)p.plane, o = (size_t)y * p.nx + x;
+        TC H[4], K[4];
+        for (int a = 0; a < 2; ++a) {
+            const TU *ua = u + a * pl + o;
+            H[2 * a + 0] = TC((ua[1] - ua[-1]) * TU(0.5));
+            H[2 * a + 1] = TC((ua[p.nx] - ua[-(ptrdiff_t)p.nx]) * TU(0.5));
+        }
+        const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
+        for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
+        if (which == 0 && !(J > TC(0))) p.flag[0] = 1u;
+        return;
+    }
+    if (g_hole(p, x, y)) {
+        // K seen from the material neighbour across each axis (zero if none)
+        TC kx[4] = {TC(0), TC(0), TC(0), TC(0)}, ky[4] = {TC(0), TC(0), TC(0), TC(0)};
+        const int sx = !g_hole(p, x - 1, y) ? -1 : (!g_hole(p, x + 1, y) ? 1 : 0);
+        const int sy = !g_hole(p, x, y - 1) ? -1 : (!g_hole(p, x, y + 1) ? 1 : 0);
+        if (sx) gen_k_hole<PR>(p, x + sx, y, which, 0, kx);
+        if (sy) gen_k_hole<PR>(p, x, y + sy, which, 1, ky);
+        Kp[k_index(p, 0, x, y)] = kx[0];
+        Kp[k_index(p, 2, x, y)] = kx[2];
+        Kp[k_index(p, 1, x, y)] = ky[1];
+        Kp[k_index(p, 3, x, y)] = ky[3];
+        return;
+    }
+    TC H[4], K[4];
+    gen_grad<PR>(p, u, x, y, t, H);
+    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
+    for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
+    if (which == 0 && x >= 0 && x < p.nx && y >= 0 && y < p.ny && !(J > TC(0))) p.flag[0] = 1u;
+}
+
+// central divergence of K at node (x, y) plus the body force (eq. (23))
 template <class PR>
-__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, int which, typename PR::TC S[2])
+__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, typename PR::TC S[2])
 {
     using TC = typename PR::TC;
     const TC *K = static_cast<const TC *>(p.K);
@@ -212,12 +258,6 @@ __device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, int
         kxm[c] = K[k_index(p, c, x - 1, y)];
         kyp[c] = K[k_index(p, c, x, y + 1)];
         kym[c] = K[k_index(p, c, x, y - 1)];
-    }
-    if (p.mask) {
-        if (g_hole(p, x + 1, y)) gen_k_hole<PR>(p, x, y, which, 0, kxp);
-        if (g_hole(p, x - 1, y)) gen_k_hole<PR>(p, x, y, which, 0, kxm);
-        if (g_hole(p, x, y + 1)) gen_k_hole<PR>(p, x, y, which, 1, kyp);
-        if (g_hole(p, x, y - 1)) gen_k_hole<PR>(p, x, y, which, 1, kym);
     }
     S[0] = TC(p.bx) + TC(0.5) * (kxp[0] - kxm[0]) + TC(0.5) * (kyp[1] - kym[1]);
     S[1] = TC(p.by) + TC(0.5) * (kxp[2] - kxm[2]) + TC(0.5) * (kyp[3] - kym[3]);
@@ -240,7 +280,7 @@ __global__ void __launch_bounds__(256) collide_pass(const GenParams p)
     const TF *fin = static_cast<const TF *>(p.f_in);
     const TJ *jin = static_cast<const TJ *>(p.j_in);
     TC S[2], f[9], fc[9], r, pxx;
-    gen_source<PR>(p, x, y, 0, S);
+    gen_source<PR>(p, x, y, S);
     for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
     collide(f, TC(jin[s]), TC(jin[pl + s]), S[0], S[1], TC(p.omega), fc, r, pxx);
     TC *fcol = static_cast<TC *>(p.fcol);
@@ -323,36 +363,15 @@ __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, i
     return -fco + TC(2) * w * (r + TC(4.5) * q);
 }
 
-// Pass 3: pull streaming (5) with the wall rules (Sec. 6), storage of the
-// new populations, their first moment jf and the predictor u^p (PC), or the
-// new j and u directly (explicit).
+// Pull of the nine populations of a node next to an edge or a hole: a link
+// whose source lies beyond a wall, or in a hole, takes the wall's rule.
 template <class PR>
-__global__ void __launch_bounds__(256) stream_pass(const GenParams p)
+__device__ __forceinline__ void stream_edge(const GenParams &p, int x, int y, int s, bool perx, bool pery,
+                                         typename PR::TC fn[9])
 {
-    using TF = typename PR::TF;
-    using TU = typename PR::TU;
-    using TJ = typename PR::TJ;
     using TC = typename PR::TC;
-    using FS = FStore<TF>;
-    const int n = p.nx * p.ny;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int y = s / p.nx, x = s - y * p.nx;
     const size_t pl = (size_t)p.plane;
-    if (g_hole(p, x, y)) {  // no material: zero state
-        for (int i = 0; i < 9; ++i) FS::store(static_cast<TF *>(p.f_out), i * pl + s, TC(0), TC(p.f_scale));
-        if (p.pc) {
-            static_cast<TC *>(p.jf)[s] = static_cast<TC *>(p.jf)[pl + s] = TC(0);
-            static_cast<TU *>(p.up)[s] = static_cast<TU *>(p.up)[pl + s] = TU(0);
-        } else {
-            static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
-            static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
-        }
-        return;
-    }
     const TC *fcol = static_cast<const TC *>(p.fcol);
-    const bool perx = p.bc[EDGE_XMIN] == BC_PERIODIC, pery = p.bc[EDGE_YMIN] == BC_PERIODIC;
-    TC fn[9];
     for (int i = 0; i < 9; ++i) {
         int sxp = x - kGx[i], syp = y - kGy[i];
         if (i && g_hole(p, sxp, syp)) {
@@ -380,6 +399,33 @@ __global__ void __launch_bounds__(256) stream_pass(const GenParams p)
             const int o = kGopp[i];  // the link that left through the wall
             fn[i] = gen_wall<PR>(p, x, y, o, cx ? kGx[o] : 0, cy ? kGy[o] : 0, fcol[o * pl + s], false);
         }
+    }
+}
+
+// Pass 3: pull streaming (5) with the wall rules (Sec. 6), storage of the
+// new populations, their first moment jf and the predictor u^p (PC), or the
+// new j and u directly (explicit).
+template <class PR, bool EDGE>
+__global__ void __launch_bounds__(256) stream_pass(const GenParams p)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    if (tid >= (EDGE ? p.n_edge_f : p.nx * p.ny)) return;
+    const int s = EDGE ? p.edge_f[tid] : tid;
+    const int y = s / p.nx, x = s - y * p.nx;
+    const size_t pl = (size_t)p.plane;
+    if (!EDGE && !g_inner(p, x, y)) return;  // (hole nodes are in no launch: their state is never read)
+    const TC *fcol = static_cast<const TC *>(p.fcol);
+    const bool perx = p.bc[EDGE_XMIN] == BC_PERIODIC, pery = p.bc[EDGE_YMIN] == BC_PERIODIC;
+    TC fn[9];
+    if (!EDGE) {
+        for (int i = 0; i < 9; ++i) fn[i] = fcol[i * pl + (size_t)(s - kGy[i] * p.nx - kGx[i])];
+    } else {
+        stream_edge<PR>(p, x, y, s, perx, pery, fn);
     }
     const bool sr = FS::kStochastic && p.sr;
     const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
@@ -434,7 +480,7 @@ __global__ void __launch_bounds__(256) update_pass(const GenParams p)
         return;
     }
     TC Sp[2];
-    gen_source<PR>(p, x, y, 1, Sp);
+    gen_source<PR>(p, x, y, Sp);
     const TC *jf = static_cast<const TC *>(p.jf);
     const TU *u = static_cast<const TU *>(p.u_in);
     const TJ *jin = static_cast<const TJ *>(p.j_in);
@@ -479,11 +525,15 @@ inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
     off += al(2 * n * sizeof(TC));
     p.up = scratch + off;
     const int nb = (int)((n + 255) / 256), nbe = (int)((ne + 255) / 256);
-    hipLaunchKernelGGL((stress_pass<PR>), dim3(nbe), dim3(256), 0, st, p, 0);
+    const int nbk = (p.n_edge_k + 255) / 256, nbf = (p.n_edge_f + 255) / 256;
+    hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbe), dim3(256), 0, st, p, 0);
+    if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 0);
     hipLaunchKernelGGL((collide_pass<PR>), dim3(nb), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((stream_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((stream_pass<PR, false>), dim3(nb), dim3(256), 0, st, p);
+    if (nbf) hipLaunchKernelGGL((stream_pass<PR, true>), dim3(nbf), dim3(256), 0, st, p);
     if (p.pc) {
-        hipLaunchKernelGGL((stress_pass<PR>), dim3(nbe), dim3(256), 0, st, p, 1);
+        hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbe), dim3(256), 0, st, p, 1);
+        if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 1);
         hipLaunchKernelGGL((update_pass<PR>), dim3(nb), dim3(256), 0, st, p);
     }
     return hipGetLastError();

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "general_kernels.hpp"
 #include "host_common.hpp"
@@ -24,6 +25,7 @@ struct Layout {
     size_t partials, small, total;
     size_t scratch, total_walled;  // scratch of the general passes (walls on the x edges)
     size_t mask;                   // material mask [ny][nx] bytes, after the scratch
+    size_t edge_k, edge_f;         // node lists of the edge launches (int32), after the mask
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -52,7 +54,9 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.total = off;
     L.scratch = off;
     L.mask = align_up(off + general_scratch(nx, ny, p));
-    L.total_walled = align_up(L.mask + (size_t)nx * ny);
+    L.edge_k = align_up(L.mask + (size_t)nx * ny);
+    L.edge_f = align_up(L.edge_k + sizeof(int) * (size_t)(nx + 2) * (ny + 2));
+    L.total_walled = align_up(L.edge_f + sizeof(int) * (size_t)nx * ny);
     return L;
 }
 
@@ -81,6 +85,9 @@ struct lbm_solver {
     unsigned long long seed = 0;
     bool force_general = false;  // run the general passes even without x walls
     bool has_mask = false;       // holes (lbm_set_mask)
+    std::vector<unsigned char> mask_host;  // copy of the mask, for the edge lists
+    bool edges_dirty = true;     // the edge lists need rebuilding (edges or mask changed)
+    int n_edge_k = 0, n_edge_f = 0;
 
     bool general() const
     {
@@ -290,6 +297,7 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
         h->bcval[other][0] = h->bcval[other][1] = 0.0;
     }
     h->bc[e] = bc;
+    h->edges_dirty = true;
     h->bcval[e][0] = bc == LBM_BC_PERIODIC ? 0.0 : value[0];
     h->bcval[e][1] = bc == LBM_BC_PERIODIC ? 0.0 : value[1];
     return LBM_OK;
@@ -336,6 +344,8 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
     if (h->fields) return fail(h, LBM_ERR_STATE, "set the mask before the fields");
     if (!solid) {
         h->has_mask = false;
+        h->mask_host.clear();
+        h->edges_dirty = true;
         return LBM_OK;
     }
     if (h->ws_bytes < h->L.total_walled)
@@ -359,6 +369,8 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
             if (hole(x, y)) {
                 if (((y == 0 || y == ny - 1) && !pery) || ((x == 0 || x == nx - 1) && !perx))
                     return fail(h, LBM_ERR_ARG, "a hole touches a wall edge");
+                if ((!hole(x - 1, y) && !hole(x + 1, y)) || (!hole(x, y - 1) && !hole(x, y + 1)))
+                    return fail(h, LBM_ERR_ARG, "hole one node wide");
                 continue;
             }
             any_material = true;
@@ -366,9 +378,13 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
                 return fail(h, LBM_ERR_ARG, "material one node thick between holes");
         }
     if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
-    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, solid, (size_t)nx * ny, hipMemcpyHostToDevice, h->stream));
+    h->mask_host.assign(solid, solid + (size_t)nx * ny);
+    for (auto &m : h->mask_host) m = m ? 1 : 0;
+    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, h->mask_host.data(), (size_t)nx * ny, hipMemcpyHostToDevice,
+                              h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->has_mask = true;
+    h->edges_dirty = true;
     return LBM_OK;
 }
 
@@ -437,6 +453,63 @@ lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0)
     return LBM_OK;
 }
 
+namespace {
+
+// Node lists of the edge launches of the general passes: the stress pass's
+// ring nodes and lattice nodes whose stencil meets a ghost, wall or hole
+// (hole nodes only where a material node borders them), and the stream
+// pass's material nodes not in the interior. Built on the host when the
+// edges or the mask change; hole nodes off the borders are never read, so
+// no launch visits them.
+hipError_t build_edge_lists(lbm_solver *h)
+{
+    const int nx = h->nx, ny = h->ny;
+    const bool perx = h->bc[LBM_EDGE_XMIN] == LBM_BC_PERIODIC, pery = h->bc[LBM_EDGE_YMIN] == LBM_BC_PERIODIC;
+    const unsigned char *m = h->has_mask ? h->mask_host.data() : nullptr;
+    auto hole = [&](int x, int y) {
+        if (!m) return false;
+        if (y < 0 || y >= ny) {
+            if (!pery) return false;
+            y = (y % ny + ny) % ny;
+        }
+        if (x < 0 || x >= nx) {
+            if (!perx) return false;
+            x = (x % nx + nx) % nx;
+        }
+        return m[(size_t)y * nx + x] == 0;
+    };
+    auto inner = [&](int x, int y) {
+        if (x < 1 || x > nx - 2 || y < 1 || y > ny - 2) return false;
+        if (!m) return true;
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                if (!m[(size_t)(y + dy) * nx + (x + dx)]) return false;
+        return true;
+    };
+    std::vector<int> ek, ef;
+    for (int y = -1; y <= ny; ++y)
+        for (int x = -1; x <= nx; ++x) {
+            if (inner(x, y)) continue;
+            if (hole(x, y) && hole(x - 1, y) && hole(x + 1, y) && hole(x, y - 1) && hole(x, y + 1)) continue;
+            ek.push_back((y + 1) * (nx + 2) + (x + 1));
+            if (x >= 0 && x < nx && y >= 0 && y < ny && !hole(x, y)) ef.push_back(y * nx + x);
+        }
+    h->n_edge_k = (int)ek.size();
+    h->n_edge_f = (int)ef.size();
+    hipError_t e = hipSuccess;
+    if (!ek.empty())
+        e = hipMemcpyAsync(h->ws + h->L.edge_k, ek.data(), sizeof(int) * ek.size(), hipMemcpyHostToDevice,
+                           h->stream);
+    if (!e && !ef.empty())
+        e = hipMemcpyAsync(h->ws + h->L.edge_f, ef.data(), sizeof(int) * ef.size(), hipMemcpyHostToDevice,
+                           h->stream);
+    if (!e) e = hipStreamSynchronize(h->stream);
+    if (!e) h->edges_dirty = false;
+    return e;
+}
+
+}  // namespace
+
 lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
 {
     if (!h) return LBM_ERR_ARG;
@@ -483,6 +556,11 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.pc = h->scheme == LBM_SCHEME_EXTRAP ? 2 : (pc ? 1 : 0);
         gp.flag = sp.flag;
         gp.mask = h->mask_ptr();
+        if (h->edges_dirty) HIP_TRY(h, build_edge_lists(h));
+        gp.edge_k = reinterpret_cast<const int *>(h->ws + h->L.edge_k);
+        gp.edge_f = reinterpret_cast<const int *>(h->ws + h->L.edge_f);
+        gp.n_edge_k = h->n_edge_k;
+        gp.n_edge_f = h->n_edge_f;
         for (int64_t k = 0; k < nsteps; ++k) {
             gp.f_in = h->fptr(h->cur);
             gp.u_in = h->uptr(h->cur);
