@@ -13,7 +13,7 @@ EDGES = ("xmin", "xmax", "ymin", "ymax")
 
 
 def _gpu(nx, ny, u0, v0, n, kinds, vals, mask, precision="fp64", lam=0.1, mu=0.05, tau=0.8, scheme="pc", dx=1.0,
-         body=(0.0, 0.0), loads=None, samples=None):
+         body=(0.0, 0.0), loads=None, samples=None, sample_every=52):
     from paper_2208_13769_amd import lbm
 
     s = lbm.Solver(nx, ny, dx, precision, scheme, walled=True)
@@ -32,7 +32,7 @@ def _gpu(nx, ny, u0, v0, n, kinds, vals, mask, precision="fp64", lam=0.1, mu=0.0
             for e, v in loads(k, s.dt).items():
                 s.set_boundary(EDGES.index(e), kinds[EDGES.index(e)], v)
             s.step(1)
-            if samples is not None and (k + 1) % 52 == 0:
+            if samples is not None and (k + 1) % sample_every == 0:
                 series.append(s.sample(samples[0], samples[1]))
     else:
         s.step(n)
@@ -90,14 +90,14 @@ def test_holes_match_oracle(gpu, kinds, scheme):
 
 
 def test_plate_with_hole_80x80_matches_oracle(gpu):
-    """The geometry and timing of Sec. 7.2: side l = 1 on 80 x 80 nodes
-    (dX = 0.0125), a centred square hole of 0.4 l (32 x 32 nodes), lam = mu
-    = 1, tau/dt = 0.8, traction on the top and bottom edges applied at t = 0
-    and removed at t = 1, run to t = 3 (416 steps), sides and hole free. The
-    load is 0.02 mu: at the paper's 0.1 mu the re-entrant corners of this
-    boundary scheme fail near t = 0.9 (design notes). Probes Q1 (beside the
-    hole on the centre line) and Q2 (top centre) every 52 steps."""
-    n, h, T = 80, 32, 0.02
+    """The plate with a hole of Sec. 7.2 as the paper runs it: side l = 1 on
+    80 x 80 nodes (dX = 0.0125), a centred square hole of 0.4 l (32 x 32
+    nodes), lam = mu = 1, a traction of 0.1 mu on the top and bottom edges
+    applied at t = 0 and removed at t = 1, run to t = 3 (416 steps), sides
+    and hole free; tau/dt = 0.55 (reading Q24). Also the paper's one
+    number: the plate lengthens by about 18 % (here on the centre line, the
+    top edge node against the bottom one, sampled every step)."""
+    n, h, T = 80, 32, 0.1
     a = (n - h) // 2
     m = np.ones((n, n), np.uint8)
     m[a:a + h, a:a + h] = 0
@@ -109,19 +109,20 @@ def test_plate_with_hole_80x80_matches_oracle(gpu):
         return {"ymax": (0.0, f), "ymin": (0.0, -f)}
 
     z = np.zeros((2, n, n))
-    q = (np.array([a + h, n // 2]), np.array([n // 2, n - 1]))
-    uo, vo, Po, so, _ = _oracle(n, n, z, z.copy(), 416, kinds, vals, m, lam=1.0, mu=1.0, dx=1.0 / n, loads=loads)
-    ug, vg, Pg, sg, dg, st, series = _gpu(n, n, z, z.copy(), 416, kinds, vals, m, lam=1.0, mu=1.0, dx=1.0 / n,
-                                          loads=loads, samples=q)
+    q = (np.array([n // 2, n // 2, a + h]), np.array([n - 1, 0, n // 2]))
+    kw = dict(lam=1.0, mu=1.0, tau=0.55, dx=1.0 / n, loads=loads)
+    uo, vo, Po, so, _ = _oracle(n, n, z, z.copy(), 416, kinds, vals, m, **kw)
+    ug, vg, Pg, sg, dg, st, series = _gpu(n, n, z, z.copy(), 416, kinds, vals, m, samples=q, sample_every=1, **kw)
     assert st == 0
     e = [rel_l2(ug, uo), rel_l2(Pg, Po), rel_l2(sg, so)]
-    stretch = (ug[1][-1].mean() - ug[1][0].mean()) / (1 - 1 / n)
-    print(f"hole 80x80: rel-L2 u {e[0]:.3e} P {e[1]:.3e} sigma {e[2]:.3e}; stretch {stretch:.4f}; "
-          f"u1(Q1), u2(Q2) at t = 3: {ug[0][n // 2, a + h]:.5f} {ug[1][n - 1, n // 2]:.5f}", flush=True)
+    series = np.array(series)  # [step][node][17]
+    length = series[:, 0, 1] - series[:, 1, 1]
+    peak = length.max()
+    t_peak = (np.argmax(length) + 1) * 3.0 / 416
+    print(f"hole 80x80: rel-L2 u {e[0]:.3e} P {e[1]:.3e} sigma {e[2]:.3e}; peak lengthening {peak:.4f} at "
+          f"t = {t_peak:.2f}; u1(Q1) min {series[:, 2, 0].min():.4f}", flush=True)
     assert max(e) < 1e-11
-    assert len(series) == 8 and np.allclose(series[-1][:, 0:2], np.array([[ug[0][n // 2, a + h], ug[1][n // 2, a + h]],
-                                                                          [ug[0][n - 1, n // 2], ug[1][n - 1, n // 2]]]),
-                                            rtol=1e-12, atol=1e-15)
+    assert 0.16 < peak < 0.20 and 0.9 < t_peak < 1.1
 
 
 def test_fp32_hole(gpu):

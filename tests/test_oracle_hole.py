@@ -154,3 +154,32 @@ def test_invalid_masks_are_rejected(case):
         kw = {}
     with pytest.raises(ValueError):
         O.Solver(O.Params(nx=n, ny=n, solid=m, **kw), np.zeros((2, n, n)), np.zeros((2, n, n)))
+
+
+def test_plate_with_hole_lengthens_by_about_18_percent():
+    """Sec. 7.2 states the only number of the hole example: under the sudden
+    0.1 mu traction the plate lengthens by about 18 % along the load. Here
+    the geometry, load and timing of Sec. 7.2 (80 x 80 nodes, centred
+    32 x 32 hole, lam = mu = 1, load held for t < 1) with tau/dt = 0.55
+    (reading Q24: the paper gives no tau): the distance between the top and
+    bottom edge nodes on the centre line grows by 18.2 % at its peak, at
+    t = 1 when the load is removed. The band is the paper's 'about'."""
+    n, h = 80, 32
+    a = (n - h) // 2
+    m = np.ones((n, n), np.uint8)
+    m[a:a + h, a:a + h] = 0
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.55,
+                 bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_, solid=m)
+    s = O.Solver(p, np.zeros((2, n, n)), np.zeros((2, n, n)))
+    dt = O.dt(p)
+    peak, t_peak = 0.0, 0.0
+    for k in range(int(round(1.2 / dt))):
+        f = 0.1 if k * dt < 1.0 else 0.0
+        s.set_boundary_value("ymax", (0.0, f))
+        s.set_boundary_value("ymin", (0.0, -f))
+        s.step(1)
+        d = s.u[1][-1, n // 2] - s.u[1][0, n // 2]
+        if d > peak:
+            peak, t_peak = d, (k + 1) * dt
+    assert 0.16 < peak < 0.20, peak
+    assert 0.9 < t_peak < 1.1, t_peak
