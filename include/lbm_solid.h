@@ -212,7 +212,9 @@ lbm_status lbm_set_general_path(lbm_solver *h, int on);
  * diagnostics. Holes must keep off the rows and columns next to a wall
  * edge (they may cross periodic edges), and neither a material node nor a
  * hole node may have nodes of the other kind on both sides along one axis
- * (material and holes at least two nodes thick; LBM_ERR_ARG otherwise). Set
+ * (material and holes at least two nodes thick; LBM_ERR_ARG otherwise). Once a mask
+ * is set, lbm_set_boundary may change boundary values and kinds but may not
+ * make an edge periodic or not (LBM_ERR_STATE). Set
  * the boundaries first, then the mask, then the fields (LBM_ERR_STATE
  * after lbm_set_fields). Needs lbm_workspace_bytes_walled() (LBM_ERR_NOMEM
  * otherwise); runs the general passes. Copies the array; synchronises. */

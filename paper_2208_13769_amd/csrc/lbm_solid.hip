@@ -286,6 +286,8 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
                       : e == LBM_EDGE_YMAX ? LBM_EDGE_YMIN
                       : e == LBM_EDGE_XMIN ? LBM_EDGE_XMAX
                                            : LBM_EDGE_XMIN;
+    if (h->has_mask && (h->bc[e] == LBM_BC_PERIODIC) != (bc == LBM_BC_PERIODIC))
+        return fail(h, LBM_ERR_STATE, "a mask was checked against the edges: make edges periodic or not before it");
     if (bc == LBM_BC_PERIODIC && h->bc[other] != LBM_BC_PERIODIC) {
         // periodic edges come in pairs
         h->bc[other] = LBM_BC_PERIODIC;
@@ -296,8 +298,10 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
         h->bc[other] = LBM_BC_DIRICHLET_J;
         h->bcval[other][0] = h->bcval[other][1] = 0.0;
     }
+    const bool was_periodic = h->bc[e] == LBM_BC_PERIODIC;
     h->bc[e] = bc;
-    h->edges_dirty = true;
+    // the edge lists depend only on which edges are periodic (and the mask)
+    if (was_periodic != (bc == LBM_BC_PERIODIC)) h->edges_dirty = true;
     h->bcval[e][0] = bc == LBM_BC_PERIODIC ? 0.0 : value[0];
     h->bcval[e][1] = bc == LBM_BC_PERIODIC ? 0.0 : value[1];
     return LBM_OK;

@@ -187,6 +187,10 @@ def test_mask_errors(gpu):
         s.set_mask(thin)
     assert e.value.status == lbm.LBM_ERR_ARG
     s.set_mask(m)
+    with pytest.raises(lbm.LbmError) as e:  # periodicity is fixed once a mask is set
+        s.set_boundary(lbm.LBM_EDGE_XMIN, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
+    assert e.value.status == lbm.LBM_ERR_STATE
+    s.set_boundary(lbm.LBM_EDGE_YMAX, lbm.LBM_BC_NEUMANN_T, (0.0, 0.01))  # values may change
     s.set_fields(np.zeros((2, n, n)), np.zeros((2, n, n)))
     with pytest.raises(lbm.LbmError) as e:
         s.set_mask(m)
