@@ -7,7 +7,7 @@ corrector source, FP32 storage and arithmetic with the displacement stored
 and accumulated in FP64 (plain FP32 misses the 1e-5 bound on P after 500
 steps; --precision fp32 runs it); u0 = 0 and a seeded
 Gaussian-filtered velocity field (sigma = 32 cells, seed 2) scaled to the
-calibrated peak velocity (tests/golden/config2_amplitude.json). A "step" is
+calibrated peak velocity (tests/golden/large_strain_amplitude.json). A "step" is
 one time step of the whole grid; the fused step kernel advances one or two
 steps per launch (the autotuner picks).
 
@@ -55,8 +55,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def config2_amplitude() -> float:
-    path = os.path.join(ROOT, "tests", "golden", "config2_amplitude.json")
+def large_strain_amplitude() -> float:
+    path = os.path.join(ROOT, "tests", "golden", "large_strain_amplitude.json")
     with open(path) as fh:
         return float(json.load(fh)["peak_velocity"])
 
@@ -64,9 +64,9 @@ def config2_amplitude() -> float:
 def workload(name: str):
     from paper_2208_13769_amd import inputs
 
-    if name == "config2":
+    if name == "large-strain-4096":
         n = 4096
-        u0, v0 = inputs.filtered_random_velocity(n, n, 32.0, 2, config2_amplitude())
+        u0, v0 = inputs.filtered_random_velocity(n, n, 32.0, 2, large_strain_amplitude())
         return dict(nx=n, ny=n, precision="fp32u64", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
                     desc="periodic 4096x4096 D2Q9, neo-Hooke lam=0.1 mu=0.05, tau/dt=0.8, "
                          "predictor-corrector, FP32 arithmetic and storage with the displacement "
@@ -255,7 +255,7 @@ def bench_hole(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_config4(args):
+def bench_plates(args):
     """256 plates of uneven sizes in one batch (one persistent launch per one
     or two steps, graph-captured chunks), FP16 populations, 2000 steps each."""
     import torch
@@ -356,7 +356,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="large-strain-4096",
+                    help="large-strain-4096 (default) | fp16-4096 | plates-256 | hole")
     ap.add_argument("--precision", default=None,
                     help="override the workload's precision (fp64, fp32, fp32u64, fp16, bf16)")
     ap.add_argument("--cpu-steps", type=int, default=16)
@@ -365,10 +366,10 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB (float32 read + "
                          "write) three times: its HBM counter readings calibrate the step kernel's")
-    ap.add_argument("--plate-steps", type=int, default=2000, help="config4: steps per plate")
-    ap.add_argument("--chunk", type=int, default=200, help="config4: steps per graph-captured chunk")
+    ap.add_argument("--plate-steps", type=int, default=2000, help="plates-256: steps per plate")
+    ap.add_argument("--chunk", type=int, default=200, help="plates-256: steps per graph-captured chunk")
     ap.add_argument("--batch-spl", type=int, default=0,
-                    help="config4: time steps per batch launch (1 or 2; 0 = the batch's default)")
+                    help="plates-256: time steps per batch launch (1 or 2; 0 = the batch's default)")
     ap.add_argument("--hole-n", type=int, default=4096, help="hole: nodes per side")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -384,8 +385,8 @@ def main():
     if args.workload == "hole":
         bench_hole(args)
         return
-    if args.workload == "config4":
-        bench_config4(args)
+    if args.workload == "plates-256":
+        bench_plates(args)
         return
     wl = workload(args.workload)
     if args.precision:

@@ -6,7 +6,7 @@ cells, seed 2) scaled so that the peak Green-Lagrange strain reaches about
 linear-regime peak velocity (1e-3), records the largest spectral norm of
 E = (F^T F - I)/2 over all sites at every 10th step up to step 200, and
 scales the amplitude linearly to a target strain of 0.2. The result is
-written to config2_amplitude.json next to this file.
+written to large_strain_amplitude.json next to this file.
 
 Runs only the oracle (about 10-15 minutes on 8 cores).
 """
@@ -40,7 +40,7 @@ def main():
     out = {"grid": N, "sigma": SIGMA, "seed": SEED, "pilot_peak_velocity": PILOT,
            "pilot_peak_strain": peak, "target_strain": TARGET, "peak_velocity": amp,
            "history": history}
-    with open(os.path.join(HERE, "config2_amplitude.json"), "w") as fh:
+    with open(os.path.join(HERE, "large_strain_amplitude.json"), "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps({k: v for k, v in out.items() if k != "history"}))
 

@@ -89,7 +89,7 @@ def _large_strain_case():
     import json
     import os
 
-    path = os.path.join(os.path.dirname(__file__), "golden", "config2_amplitude.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", "large_strain_amplitude.json")
     with open(path) as fh:
         peak = float(json.load(fh)["peak_velocity"])
     return inputs.filtered_random_velocity(1024, 1024, 8.0, 2, peak)

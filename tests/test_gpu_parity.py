@@ -26,7 +26,7 @@ def _compare(case, nsteps, tol_u, tol_P, tol_v=None, precision="fp64", **kw):
     return (uo, vo, Po, do), (ug, vg, Pg, dg)
 
 
-def config1_case():
+def shear_wave_64_case():
     u0, v0 = inputs.shear_wave(64, 64, 1e-4, 64)
     return u0, v0, 64, 64
 
@@ -37,9 +37,9 @@ def random_case(nx, ny, seed, peak, sigma=3.0):
     return u0, v0, nx, ny
 
 
-def test_config1_fp64(gpu):
+def test_shear_wave_64_fp64(gpu):
     """64 x 64 periodic shear wave, FP64, 1000 steps: u, v, P and momentum."""
-    o, g = _compare(config1_case(), 1000, 1e-12, 1e-12, 1e-12)
+    o, g = _compare(shear_wave_64_case(), 1000, 1e-12, 1e-12, 1e-12)
     assert np.allclose(g[3].momentum, o[3]["momentum"], rtol=0, atol=1e-14)
 
 
@@ -149,8 +149,8 @@ def test_unstable_flag(gpu):
 @pytest.mark.parametrize("precision,tol", [("fp16", 2e-2), ("bf16", 1e-1)])
 def test_16bit_storage_short_run(gpu, precision, tol):
     """16-bit population storage against the FP64 oracle, 200 steps of the
-    config-1 wave (errors per dtype are reported by the benchmark suite)."""
-    _compare(config1_case(), 200, tol, tol, precision=precision)
+    64 x 64 shear wave (errors per dtype are reported by the benchmark suite)."""
+    _compare(shear_wave_64_case(), 200, tol, tol, precision=precision)
 
 
 @pytest.mark.parametrize("precision,walled", [("fp32", False), ("fp32", True), ("fp16", False), ("fp16", True),
