@@ -33,11 +33,14 @@
  *      Ghost displacement rows for the finite differences: at a wall with a
  *      momentum (Dirichlet) rule, the quadratic through the wall value and
  *      the two nearest rows; at a traction (Neumann) wall, constant
- *      extrapolation of the nearest row. The boundary moments of the
- *      anti-bounce-back rule (26) -- r_bd, the tangential entry of Pbar* and
- *      P + Pbar in the traction transform -- are taken at the node row next
- *      to the wall (zeroth-order extrapolation). Higher-order extrapolation
- *      of any of them makes the scheme grow without bound near the wall.
+ *      extrapolation of the nearest row. Of the boundary moments of the
+ *      anti-bounce-back rule (26), r_bd and the tangential entry of Pbar*
+ *      are taken at the node row next to the wall (zeroth-order
+ *      extrapolation; higher orders make the scheme grow without bound near
+ *      the wall), and P + Pbar in the traction transform is its value at
+ *      the wall, the mean of the node row and the ghost row (the wall lies
+ *      midway) -- the same wall value the central divergence at the node
+ *      row implies, so the wall passes exactly T*.
  *  Q12 The anti-bounce-back rule uses r_bd in both places (eq. (26)).
  *  Q22 The extrapolation variant (scheme 2, end of Sec. 5): the predictor
  *      displacement for the source at t + dt comes from the trapezoidal
@@ -423,11 +426,21 @@ static void moments_r_pi(const oracle_params *p, const double *f, size_t s, doub
  * wall normal is axis n (0: x, 1: y) with outward sign s, T the traction.
  * Pbar N = -T* + (P + Pbar) N gives the wall's normal column of the boundary
  * Poisson tensor, q_a = Pbar*_an = (-T_a + K_an s) / s, with K = P + Pbar
- * taken at the node (zeroth-order extrapolation, reading Q11). */
-static void traction_column(const oracle_params *p, const double *K, int y, int x, int n, double s,
-                            const double T[2], double q[2])
+ * at the wall: the mean of K at the node and at the neighbour beyond the
+ * wall (a ghost node, or a hole node whose K is that of Q23) (reading Q11). */
+static void traction_column(const oracle_params *p, const double *K, const double *ue, int y, int x, int n,
+                            double s, const double T[2], double q[2])
 {
-    for (int a = 0; a < 2; ++a) q[a] = (-T[a] + K[k_at(p, 2 * a + n, y, x)] * s) / s;
+    const int gy = y + (n == 1 ? (int)s : 0), gx = x + (n == 0 ? (int)s : 0);
+    double kg[4];
+    if (in_hole(p, gy, gx))
+        k_hole(p, ue, y, x, n, kg);
+    else
+        for (int c = 0; c < 4; ++c) kg[c] = K[k_at(p, c, gy, gx)];
+    for (int a = 0; a < 2; ++a) {
+        const double kw = 0.5 * (K[k_at(p, 2 * a + n, y, x)] + kg[2 * a + n]);
+        q[a] = (-T[a] + kw * s) / s;
+    }
 }
 
 /* Boundary moments r_bd and Pbar* for the anti-bounce-back rule (26) at node
@@ -436,7 +449,8 @@ static void traction_column(const oracle_params *p, const double *K, int y, int 
  * tractions (the tensor is symmetric); a tangential entry keeps the
  * populations' moment Pi at the node. At a corner the normal entries come
  * from the two walls and the off-diagonal is the mean of both (Q20). */
-static void traction_wall_moments(const oracle_params *p, const double *f, const double *K, int y, int x,
+static void traction_wall_moments(const oracle_params *p, const double *f, const double *K, const double *ue,
+                                  int y, int x,
                                   int sx, const double Tx[2], int sy, const double Ty[2],
                                   double *rbd, double Pstar[4])
 {
@@ -448,18 +462,18 @@ static void traction_wall_moments(const oracle_params *p, const double *f, const
     Pstar[2] = Pi0[2];
     Pstar[3] = Pi0[3];
     if (sx && sy) {
-        traction_column(p, K, y, x, 0, (double)sx, Tx, qx);
-        traction_column(p, K, y, x, 1, (double)sy, Ty, qy);
+        traction_column(p, K, ue, y, x, 0, (double)sx, Tx, qx);
+        traction_column(p, K, ue, y, x, 1, (double)sy, Ty, qy);
         Pstar[0] = qx[0];
         Pstar[3] = qy[1];
         Pstar[1] = Pstar[2] = 0.5 * (qx[1] + qy[0]);
     } else if (sy) {
-        traction_column(p, K, y, x, 1, (double)sy, Ty, qy);
+        traction_column(p, K, ue, y, x, 1, (double)sy, Ty, qy);
         Pstar[1] = qy[0];
         Pstar[2] = qy[0];
         Pstar[3] = qy[1];
     } else {
-        traction_column(p, K, y, x, 0, (double)sx, Tx, qx);
+        traction_column(p, K, ue, y, x, 0, (double)sx, Tx, qx);
         Pstar[0] = qx[0];
         Pstar[1] = qx[1];
         Pstar[2] = qx[1];
@@ -620,7 +634,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
                     int hx = ex && in_hole(p, y, x + ex), hy = ey && in_hole(p, y + ey, x);
                     if (!hx && !hy) hx = hy = 1; /* the diagonal through a hole corner */
                     double rbd, Pstar[4];
-                    traction_wall_moments(p, f, K, y, x, hx ? ex : 0, zero, hy ? ey : 0, zero, &rbd, Pstar);
+                    traction_wall_moments(p, f, K, ue, y, x, hx ? ex : 0, zero, hy ? ey : 0, zero, &rbd, Pstar);
                     fnew[opposite(i) * N + at(p, y, x)] = -fcol[i * N + at(p, y, x)] + abb_term(p, i, rbd, Pstar);
                     continue;
                 }
@@ -639,7 +653,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
                     v = fc + bb_term(p, i, js);
                 } else {
                     double rbd, Pstar[4];
-                    traction_wall_moments(p, f, K, y, x, sx, vx, sy, vy, &rbd, Pstar);
+                    traction_wall_moments(p, f, K, ue, y, x, sx, vx, sy, vy, &rbd, Pstar);
                     v = -fc + abb_term(p, i, rbd, Pstar);
                 }
                 fnew[opposite(i) * N + at(p, y, x)] = v;

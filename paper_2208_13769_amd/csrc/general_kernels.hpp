@@ -335,15 +335,17 @@ __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, i
     TC Pxx = (f[1] + f[3]) + dsum, Pyy = (f[2] + f[4]) + dsum, Pxy = (f[5] - f[6]) + (f[7] - f[8]);
     const TC *K = static_cast<const TC *>(p.K);
     TC qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
+    // K at a wall: the mean of the node and the neighbour beyond the wall (a
+    // ghost node, or a hole node holding the K its material neighbour sees)
     if (sx) {  // x wall: column x of Pbar*, q_a = -s T_a + K_ax
         const TC sg = TC(sx);
-        qx0 = -sg * TC(tx0) + K[k_index(p, 0, x, y)];
-        qx1 = -sg * TC(tx1) + K[k_index(p, 2, x, y)];
+        qx0 = -sg * TC(tx0) + TC(0.5) * (K[k_index(p, 0, x, y)] + K[k_index(p, 0, x + sx, y)]);
+        qx1 = -sg * TC(tx1) + TC(0.5) * (K[k_index(p, 2, x, y)] + K[k_index(p, 2, x + sx, y)]);
     }
     if (sy) {  // y wall: column y, q_a = -s T_a + K_ay
         const TC sg = TC(sy);
-        qy0 = -sg * TC(ty0) + K[k_index(p, 1, x, y)];
-        qy1 = -sg * TC(ty1) + K[k_index(p, 3, x, y)];
+        qy0 = -sg * TC(ty0) + TC(0.5) * (K[k_index(p, 1, x, y)] + K[k_index(p, 1, x, y + sy)]);
+        qy1 = -sg * TC(ty1) + TC(0.5) * (K[k_index(p, 3, x, y)] + K[k_index(p, 3, x, y + sy)]);
     }
     if (sx && sy) {
         Pxx = qx0;

@@ -180,7 +180,9 @@ __device__ __forceinline__ void collide(const TC f[9], TC jx, TC jy, TC Sx, TC S
 // Momentum wall, eq. (25): f_ibar = fc_i - 6 w_i e_i . j*.
 // Traction wall, eq. (26): f_ibar = -fc_i + 2 w_i (r_bd + 9/2 A* : (e_i e_i - I/3)),
 // A* = Pbar* - r_bd/3 I, with Pbar*_12 = Pbar*_21 = -s T*_1 + K_12,
-// Pbar*_22 = -s T*_2 + K_22, Pbar*_11 = Pi_11 (outward normal (0, s)).
+// Pbar*_22 = -s T*_2 + K_22, Pbar*_11 = Pi_11 (outward normal (0, s)); k12
+// and k22 are K at the wall (the caller passes the mean of the node row and
+// the ghost row).
 template <class TC>
 __device__ __forceinline__ void wall_populations(bool top, int kind, const TC fc[9], const double val[2],
                                                  TC r, TC pxx, TC k12, TC k22, TC out[3])
@@ -591,18 +593,20 @@ struct Pipe {
             jN.template push<PH>(1, jy);
             TC r, pxx;
             collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
+            // K at a wall: the mean of the node row and the ghost row beyond it
             if (WALLED && rC == 0) {
                 TC w[3];
-                wall_populations(false, bc_lo, fc, val_lo, r, pxx, kA2.template at<PH, 1>(0),
-                                 kA2.template at<PH, 1>(1), w);
+                wall_populations(false, bc_lo, fc, val_lo, r, pxx, TC(0.5) * (kA2.template at<PH, 1>(0) + k12d),
+                                 TC(0.5) * (kA2.template at<PH, 1>(1) + k22d), w);
                 L.wall[0][0][t] = w[0];
                 L.wall[0][1][t] = w[1];
                 L.wall[0][2][t] = w[2];
             }
             if (WALLED && rC == ny - 1) {
                 TC w[3];
-                wall_populations(true, bc_hi, fc, val_hi, r, pxx, kA2.template at<PH, 1>(0),
-                                 kA2.template at<PH, 1>(1), w);
+                wall_populations(true, bc_hi, fc, val_hi, r, pxx,
+                                 TC(0.5) * (kA2.template at<PH, 1>(0) + kA2.template at<PH, 0>(0)),
+                                 TC(0.5) * (kA2.template at<PH, 1>(1) + kA2.template at<PH, 0>(1)), w);
                 L.wall[WALLED ? 1 : 0][0][t] = w[0];
                 L.wall[WALLED ? 1 : 0][1][t] = w[1];
                 L.wall[WALLED ? 1 : 0][2][t] = w[2];

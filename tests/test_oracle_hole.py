@@ -162,7 +162,7 @@ def test_plate_with_hole_lengthens_by_about_18_percent():
     the geometry, load and timing of Sec. 7.2 (80 x 80 nodes, centred
     32 x 32 hole, lam = mu = 1, load held for t < 1) with tau/dt = 0.55
     (reading Q24: the paper gives no tau): the distance between the top and
-    bottom edge nodes on the centre line grows by 18.2 % at its peak, at
+    bottom edge nodes on the centre line grows by 18.0 % at its peak, at
     t = 1 when the load is removed. The band is the paper's 'about'."""
     n, h = 80, 32
     a = (n - h) // 2

@@ -127,11 +127,11 @@ def _edge_stretch(u, n):
 
 
 def test_slow_tension_settles_to_uniaxial_stress():
-    """Top and bottom pulled with T = 0.2 mu, ramped over t = 10, sides free;
-    the stretch averaged over t in [10, 16] against the homogeneous solution
-    F = diag(a, b) with P11 = 0, P22 = T of the Sec. 7 energy. At 40 x 40 the
-    traction walls of reading Q11 overshoot the axial strain by about a
-    quarter of its nonlinear part (1.3 % of the strain), hence the bounds."""
+    """Top and bottom pulled with T = 0.2 mu, ramped over t = 10, sides free,
+    tau/dt = 0.55 (the Sec. 7 value, reading Q24); the stretches averaged
+    over t in [10, 16] against the homogeneous solution F = diag(a, b) with
+    P11 = 0, P22 = T of the Sec. 7 energy, to a few per cent of their
+    nonlinear parts (the traction walls pass T* exactly, reading Q11)."""
     n, T, lam, mu, t_ramp, t_end = 40, 0.2, 1.0, 1.0, 10.0, 16.0
     # P11 = 0 gives a^2 = (mu + lam/2) / (mu + lam b^2 / 2); then P22(b) = T
     a_of = lambda b: np.sqrt((mu + lam / 2) / (mu + lam * b * b / 2))
@@ -140,7 +140,7 @@ def test_slow_tension_settles_to_uniaxial_stress():
     a = a_of(b)
     # linear elasticity (plane strain): eps_yy = T (lam + 2mu) / (4 mu (lam + mu)), eps_xx = -T lam / (4 mu (lam + mu))
     b_lin, a_lin = 1 + T * (lam + 2 * mu) / (4 * mu * (lam + mu)), 1 - T * lam / (4 * mu * (lam + mu))
-    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=lam, mu=mu, tau_over_dt=0.8,
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=lam, mu=mu, tau_over_dt=0.55,
                  bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_)
     s = O.Solver(p, np.zeros((2, n, n)), np.zeros((2, n, n)))
     dt = O.dt(p)
@@ -153,8 +153,8 @@ def test_slow_tension_settles_to_uniaxial_stress():
         if k * dt > t_ramp and k % 3 == 0:
             hist.append(_edge_stretch(s.u, n))
     ax, by = np.mean(hist, axis=0)
-    assert abs(by - b) < 0.3 * abs(b - b_lin)
-    assert abs(ax - a) < 0.1 * abs(a - a_lin)
+    assert abs(by - b) < 0.02 * abs(b - b_lin)
+    assert abs(ax - a) < 0.05 * abs(a - a_lin)
 
 
 def test_pure_shear_settles_to_the_homogeneous_state():
