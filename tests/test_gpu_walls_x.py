@@ -153,3 +153,57 @@ def test_x_walls_need_the_walled_workspace(gpu):
         s.set_boundary(lbm.LBM_EDGE_XMIN, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
     assert e.value.status == lbm.LBM_ERR_NOMEM
     s.close()
+
+
+def test_paper_tension_probe_series(gpu):
+    """Time series at the probe points of Sec. 7.1 (nodes at half-cell
+    offsets: P1 top centre, P2 top left corner, P3 left side centre) for
+    the paper's tension load (reading Q21, tau/dt = 0.55 by Q24), GPU node
+    samples against the oracle's fields every 26 steps."""
+    from paper_2208_13769_amd import lbm
+
+    n, steps, every = 40, 208, 26
+    xs = np.array([n // 2, 0, 0])
+    ys = np.array([n - 1, n - 1, n // 2])
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.55,
+                 bc_xmin=N_, bc_xmax=N_, bc_ymin=N_, bc_ymax=N_)
+    o = O.Solver(p, np.zeros((2, n, n)), np.zeros((2, n, n)))
+    g = lbm.Solver(n, n, 1.0 / n, "fp64", "pc", walled=True)
+    g.set_material(1.0, 1.0, 1.0, 0.55)
+    for e in range(4):
+        g.set_boundary(e, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
+    g.set_fields(np.zeros((2, n, n)), np.zeros((2, n, n)))
+    dt = O.dt(p)
+    ref, got = [], []
+    for k in range(steps):
+        f = min(k * dt, 1.0)
+        o.set_boundary_value("ymax", (0.0, f))
+        o.set_boundary_value("ymin", (0.0, -f))
+        g.set_boundary(lbm.LBM_EDGE_YMAX, lbm.LBM_BC_NEUMANN_T, (0.0, f))
+        g.set_boundary(lbm.LBM_EDGE_YMIN, lbm.LBM_BC_NEUMANN_T, (0.0, -f))
+        o.step(1)
+        g.step(1)
+        if (k + 1) % every == 0:
+            ref.append([o.u[1][ys[0], xs[0]], o.u[1][ys[1], xs[1]], o.u[0][ys[2], xs[2]]])
+            smp = g.sample(xs, ys)
+            got.append([smp[0, 1], smp[1, 1], smp[2, 0]])
+    g.close()
+    ref, got = np.array(ref), np.array(got)
+    print("u2(P1), u2(P2), u1(P3) at t = 3:", ref[-1], flush=True)
+    assert ref[:, 0].max() > 0.2 and ref[-1, 2] > 0.0  # the block stretches and narrows
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp16", 1e-3), ("bf16", 1e-2)])
+def test_general_passes_16bit_storage(gpu, precision, tol):
+    """The per-site passes with 16-bit populations (scaled, rounded to
+    nearest) on four walls, against the FP64 oracle."""
+    nx, ny, n = 50, 40, 100
+    u0, v0 = _case(nx, ny, 83)
+    kinds = (N_, N_, D_, N_)
+    vals = [VALS[N_][0], VALS[N_][1], VALS[D_][2], VALS[N_][3]]
+    uo, vo, Po, so = _oracle(nx, ny, u0, v0, n, kinds, vals)
+    ug, vg, Pg, sg = _gpu(nx, ny, u0, v0, n, kinds, vals, precision=precision)
+    eu, eP = rel_l2(ug, uo), rel_l2(Pg, Po)
+    print(f"general {precision}: rel-L2 u {eu:.3e} P {eP:.3e}", flush=True)
+    assert eu < tol and eP < tol
