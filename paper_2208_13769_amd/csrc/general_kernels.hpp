@@ -1,5 +1,6 @@
 // general_kernels.hpp -- the time step as plain per-site passes, for plates
-// with walls on any edge (Sec. 6), corners included.
+// with walls on the x edges and corners (Sec. 6), holes (Sec. 7.2) and the
+// j-extrapolation variant (end of Sec. 5).
 //
 // The fused step kernel marches rows with a register/LDS pipeline whose x
 // halo is periodic; walls on the x edges need ghost columns and wall rules
@@ -29,7 +30,8 @@
 // stress pass stores that K in the hole node's own slot (columns of the x
 // neighbour's K in entries 0 and 2, of the y neighbour's in 1 and 3, the
 // entries the divergence reads), and the source needs no special case.
-// Hole nodes hold zero state.
+// Hole nodes carry no state: no pass reads it (the read-outs report zeros
+// there), so only the hole nodes on a border are visited at all.
 // Same lattice units, arithmetic and storage rounding as the fused kernel.
 #pragma once
 
@@ -182,7 +184,7 @@ __device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int 
 // with the derivatives along n set to zero
 template <class PR>
 __device__ __forceinline__ void gen_k_hole(const GenParams &p, int x, int y, int which, int n,
-                                        typename PR::TC K[4])
+                                           typename PR::TC K[4])
 {
     using TU = typename PR::TU;
     using TC = typename PR::TC;
