@@ -81,6 +81,12 @@ def workload(name: str):
                          "predictor-corrector, FP32 arithmetic and storage with the displacement "
                          "accumulated in FP64; v0 Gaussian-filtered (sigma 32 cells, seed 2), "
                          "peak strain ~0.2 within 200 steps")
+    if name == "shear-wave-64":
+        n = 64
+        u0, v0 = inputs.shear_wave(n, n, 1e-4, n)
+        return dict(nx=n, ny=n, precision="fp64", u0=u0, v0=v0, lam=0.1, mu=0.05, tau=0.8,
+                    desc="periodic 64x64, FP64, standing shear wave v_y = 1e-4 sin(2 pi x / 64); a plate this "
+                         "small is latency-bound: read ms_per_step")
     if name == "fp16-4096":
         n = 4096
         u0, v0 = inputs.shear_wave(n, n, 1e-4, n)
@@ -362,7 +368,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="large-strain-4096",
-                    help="large-strain-4096 (default) | fp16-4096 | plates-256 | hole")
+                    help="large-strain-4096 (default) | fp16-4096 | shear-wave-64 | plates-256 | hole")
     ap.add_argument("--precision", default=None,
                     help="override the workload's precision (fp64, fp32, fp32u64, fp16, bf16)")
     ap.add_argument("--cpu-steps", type=int, default=16)
