@@ -143,6 +143,7 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
 /* Initial displacement u0 and velocity v0 (host, [2][ny][nx], physical
  * units). Builds f = f^eq(r0, j0, Pbar(H(u0))) with r0 = -rho0 div u0 and
  * j0 = rho0 v0 (Algorithm 1, initialisation) and resets the step count.
+ * Every value must be finite, hole nodes included (LBM_ERR_ARG otherwise).
  * Synchronises the stream. Needs the material to be set first. */
 lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0);
 

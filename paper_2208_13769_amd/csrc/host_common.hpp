@@ -288,6 +288,13 @@ inline hipError_t plate_start(const PlateIO &io, const double *u0, const double 
 {
     *nonfinite = false;
     const size_t n = (size_t)io.nx * io.ny;
+    // the start fields themselves, every value (a NaN would slip through the
+    // max |f| reduction below, and FP32/FP64 storage has no such pass)
+    for (size_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(u0[i]) || !std::isfinite(v0[i])) {
+            *nonfinite = true;
+            return hipSuccess;
+        }
     double *su = static_cast<double *>(io.f_other);  // the other copy holds >= 32 bytes per site
     double *sv = su + 2 * n;
     hipError_t e;
