@@ -183,8 +183,12 @@ lbm_status lbm_get_tiling(const lbm_solver *h, int *block, int *n_segs);
 /* Time steps per launch of the step kernel: 1, or 2 with the
  * predictor-corrector scheme (two steps fused in one pass over the state,
  * which halves the memory traffic per step; results are bitwise the same).
- * An odd remainder of lbm_step runs as a single step. With 2, blocks are at
- * most 256 threads (a 512-thread tiling is lowered to 256). */
+ * An odd remainder of lbm_step runs as a single step. With 2, the two
+ * pipelines' LDS must fit a compute unit: a 512-thread block does with FP32,
+ * and with the other forms except FP64 while the y edges are periodic.
+ * Otherwise lbm_set_tiling returns LBM_ERR_UNSUPPORTED, and a 512-thread
+ * tiling already set is lowered to 256 threads (by this call, or when
+ * lbm_set_boundary makes the y edges walls). */
 lbm_status lbm_set_steps_per_launch(lbm_solver *h, int k);
 lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k);
 

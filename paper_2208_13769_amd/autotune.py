@@ -45,12 +45,12 @@ def _store_cache(cache: dict) -> None:
 
 def strips(nx: int, block: int, precision: str, scheme: str, spl: int) -> int:
     """Column strips of a launch shape (the library's own rule: strips as wide
-    as the block minus both halos, rounded down to whole 128-byte lines)."""
+    as the block minus both halos, rounded down to a multiple of 32 columns)."""
     halo = HALO[scheme] * spl
     wmax = block - 2 * halo
     if nx <= wmax:
         return 1
-    align = 64 if precision in ("fp16", "bf16") else 32
+    align = 32
     w = wmax // align * align if wmax >= align else wmax
     return -(-nx // w)
 

@@ -67,15 +67,17 @@ struct Shape {
 };
 
 // When the plate is wider than one block's reach, each strip's output width
-// is a multiple of 128 bytes of the population type (32 floats / doubles,
-// 64 halves), so no cache line is written by two blocks; the spare threads
-// of the block extend the halo.
+// is a multiple of 32 columns: whole 128-byte lines of floats (two lines of
+// doubles), so no line is written by two blocks; with 16-bit populations two
+// blocks may write the two 64-byte halves of a line, which costs less than
+// the halo columns a 64-column rule wastes. The spare threads of the block
+// extend the halo.
 inline Shape make_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int block, int n_segs,
                         int steps_per_launch = 1)
 {
     const int halo = (s == LBM_SCHEME_PC ? 5 : 3) * steps_per_launch;
     const int wmax = block - 2 * halo;
-    const int align = (p == LBM_FP16_STORE || p == LBM_BF16_STORE) ? 64 : 32;
+    const int align = 32;
     Shape sh{};
     sh.block = block;
     if (nx <= wmax) {
@@ -150,25 +152,51 @@ struct Kernels {
         default: return step_b<256>(sp, nblocks, pc, st);
         }
     }
-    template <int B>
-    static void step2_b(const StepParams &sp, int nblocks, hipStream_t st)
+    // The two pipelines of a two-step block share one compute unit's 160 KiB
+    // of LDS: a 512-thread block fits with 32-bit values only, or with a
+    // double displacement on plates periodic in y.
+    template <int B, bool W>
+    static constexpr bool step2_fits()
     {
-        if (sp.bc_lo != BC_PERIODIC)
-            hipLaunchKernelGGL((step2_kernel<PR, B, true>), dim3(nblocks), dim3(B), 0, st, sp);
-        else
-            hipLaunchKernelGGL((step2_kernel<PR, B, false>), dim3(nblocks), dim3(B), 0, st, sp);
+        return 2 * sizeof(TileLds<PR, B, true, W>) <= size_t(160) * 1024;
+    }
+    template <int B>
+    static hipError_t step2_b(const StepParams &sp, int nblocks, hipStream_t st)
+    {
+        if (sp.bc_lo != BC_PERIODIC) {
+            if constexpr (step2_fits<B, true>())
+                hipLaunchKernelGGL((step2_kernel<PR, B, true>), dim3(nblocks), dim3(B), 0, st, sp);
+            else
+                return hipErrorInvalidConfiguration;
+        } else {
+            if constexpr (step2_fits<B, false>())
+                hipLaunchKernelGGL((step2_kernel<PR, B, false>), dim3(nblocks), dim3(B), 0, st, sp);
+            else
+                return hipErrorInvalidConfiguration;
+        }
+        return hipGetLastError();
+    }
+    // whether a two-step block of this many threads fits the LDS
+    static bool step2_ok(int block, bool walled)
+    {
+        switch (block) {
+        case 64: return walled ? step2_fits<64, true>() : step2_fits<64, false>();
+        case 128: return walled ? step2_fits<128, true>() : step2_fits<128, false>();
+        case 256: return walled ? step2_fits<256, true>() : step2_fits<256, false>();
+        case 512: return walled ? step2_fits<512, true>() : step2_fits<512, false>();
+        default: return false;
+        }
     }
     // two predictor-corrector steps per launch
     static hipError_t step2(const StepParams &sp, int block, int nblocks, hipStream_t st)
     {
-        // (two pipelines of LDS do not fit a 512-thread block)
         switch (block) {
-        case 64: step2_b<64>(sp, nblocks, st); break;
-        case 128: step2_b<128>(sp, nblocks, st); break;
-        case 256: step2_b<256>(sp, nblocks, st); break;
+        case 64: return step2_b<64>(sp, nblocks, st);
+        case 128: return step2_b<128>(sp, nblocks, st);
+        case 256: return step2_b<256>(sp, nblocks, st);
+        case 512: return step2_b<512>(sp, nblocks, st);
         default: return hipErrorInvalidConfiguration;
         }
-        return hipGetLastError();
     }
     // blocks of one step-kernel instantiation that a compute unit holds at once
     template <typename K>
@@ -180,9 +208,13 @@ struct Kernels {
     template <int B>
     static int resident_b(int spl, bool pc, bool walled)
     {
-        if constexpr (B <= 256) {
-            if (spl == 2)
-                return walled ? per_cu(step2_kernel<PR, B, true>, B) : per_cu(step2_kernel<PR, B, false>, B);
+        if (spl == 2) {
+            if (walled) {
+                if constexpr (step2_fits<B, true>()) return per_cu(step2_kernel<PR, B, true>, B);
+                return 0;
+            }
+            if constexpr (step2_fits<B, false>()) return per_cu(step2_kernel<PR, B, false>, B);
+            return 0;
         }
         if (pc)
             return walled ? per_cu(step_kernel<PR, B, true, true>, B) : per_cu(step_kernel<PR, B, true, false>, B);
@@ -194,7 +226,7 @@ struct Kernels {
         case 64: return resident_b<64>(spl, pc, walled);
         case 128: return resident_b<128>(spl, pc, walled);
         case 256: return resident_b<256>(spl, pc, walled);
-        default: return spl == 2 ? 0 : resident_b<512>(1, pc, walled);
+        default: return resident_b<512>(spl, pc, walled);
         }
     }
     static hipError_t init(const InitParams &ip, int nblocks, hipStream_t st)

@@ -179,6 +179,28 @@ int resident_blocks(const lbm_solver *h, int block, int spl)
     return per_cu * cus;
 }
 
+// whether two steps per launch fit the LDS with this block size, for the
+// handle's precision and y boundaries
+bool two_step_fits(const lbm_solver *h, int block)
+{
+    const bool walled = h->bc[LBM_EDGE_YMIN] != LBM_BC_PERIODIC;
+    switch (h->prec) {
+    case LBM_FP64: return Kernels<PrecF64>::step2_ok(block, walled);
+    case LBM_FP32: return Kernels<PrecF32>::step2_ok(block, walled);
+    case LBM_FP16_STORE: return Kernels<PrecF16>::step2_ok(block, walled);
+    case LBM_FP32_U64: return Kernels<PrecF32U64>::step2_ok(block, walled);
+    default: return Kernels<PrecBF16>::step2_ok(block, walled);
+    }
+}
+
+// a two-step tiling whose block no longer fits (the y edges stopped being
+// periodic) runs with 256 threads
+void refit_two_step(lbm_solver *h)
+{
+    if (h->spl == 2 && !two_step_fits(h, h->shape.block))
+        h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, 256, h->shape.n_segs, 2);
+}
+
 void plan_launch(lbm_solver *h)
 {
     const int halo = (h->scheme == LBM_SCHEME_PC ? 5 : 3) * h->spl;
@@ -304,6 +326,7 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
     if (was_periodic != (bc == LBM_BC_PERIODIC)) h->edges_dirty = true;
     h->bcval[e][0] = bc == LBM_BC_PERIODIC ? 0.0 : value[0];
     h->bcval[e][1] = bc == LBM_BC_PERIODIC ? 0.0 : value[1];
+    refit_two_step(h);
     return LBM_OK;
 }
 
@@ -314,7 +337,8 @@ lbm_status lbm_set_tiling(lbm_solver *h, int block, int n_segs)
         return fail(h, LBM_ERR_ARG, "block must be 64, 128, 256 or 512");
     if (n_segs < 1 || n_segs > h->ny) return fail(h, LBM_ERR_ARG, "n_segs must be in [1, ny]");
     if ((long long)h->nx * n_segs > (1LL << 30)) return fail(h, LBM_ERR_ARG, "too many blocks");
-    if (h->spl == 2 && block > 256) return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch need block <= 256");
+    if (h->spl == 2 && !two_step_fits(h, block))
+        return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch with this block size exceed the LDS");
     h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs, h->spl);
     return LBM_OK;
 }
@@ -326,8 +350,8 @@ lbm_status lbm_set_steps_per_launch(lbm_solver *h, int k)
     if (k == 2 && h->scheme != LBM_SCHEME_PC)
         return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch need the predictor-corrector scheme");
     h->spl = k;
-    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, k == 2 ? std::min(h->shape.block, 256) : h->shape.block,
-                          h->shape.n_segs, k);
+    const int block = k == 2 && !two_step_fits(h, h->shape.block) ? 256 : h->shape.block;
+    h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, h->shape.n_segs, k);
     return LBM_OK;
 }
 
@@ -337,7 +361,7 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
     *blocks = 0;
     if (block != 64 && block != 128 && block != 256 && block != 512) return LBM_OK;
     if (steps_per_launch != 1 && steps_per_launch != 2) return LBM_OK;
-    if (steps_per_launch == 2 && (h->scheme != LBM_SCHEME_PC || block > 256)) return LBM_OK;
+    if (steps_per_launch == 2 && h->scheme != LBM_SCHEME_PC) return LBM_OK;
     *blocks = resident_blocks(h, block, steps_per_launch);
     return LBM_OK;
 }

@@ -631,9 +631,9 @@ struct Pipe {
 };
 
 // Column/row geometry of one tile. Output strips start on multiples of
-// strip_w, which the host keeps a multiple of the 128-byte line, so row
-// writes cover whole lines; the threads outside [halo_a, halo_a + strip_w)
-// only feed the halo.
+// strip_w, which the host keeps a multiple of 32 columns, so row writes cover
+// whole lines (half lines with 16-bit populations); the threads outside
+// [halo_a, halo_a + strip_w) only feed the halo.
 struct TileGeom {
     int gx, y0, y1;
     bool out_col;

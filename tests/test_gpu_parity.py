@@ -105,7 +105,7 @@ def test_diagnostics_match_oracle(gpu):
     assert not dg.unstable and dg.steps == 40
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32u64"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32u64", "fp16", "bf16"])
 def test_tiling_does_not_change_results(gpu, precision):
     """Bitwise identical results for different blocks and row segmentations
     (catches halo and barrier mistakes at tile seams)."""
@@ -166,8 +166,13 @@ def test_two_steps_per_launch_bitwise(gpu, precision, walled):
         v0 = v0 + inputs.filtered_random_velocity(nx, ny, 2.0, 22, 0.002)[1]
     else:
         u0, v0, _, _ = random_case(nx, ny, 21, 0.05)
+    shapes = [(1, 256, 5), (2, 256, 5), (2, 128, 3), (2, 64, 7), (2, 256, 1)]
+    # 512-thread two-step blocks fit the LDS with FP32, and with a double
+    # displacement only on plates periodic in y
+    if precision == "fp32" or (precision != "fp64" and not walled):
+        shapes.append((2, 512, 2))
     outs = []
-    for spl, block, segs in [(1, 256, 5), (2, 256, 5), (2, 128, 3), (2, 64, 7), (2, 256, 1)]:
+    for spl, block, segs in shapes:
         s = lbm.Solver(nx, ny, 1.0, precision, "pc")
         s.set_material(1.0, 0.1, 0.05, 0.8)
         if walled:
@@ -175,6 +180,7 @@ def test_two_steps_per_launch_bitwise(gpu, precision, walled):
             s.set_boundary(lbm.LBM_EDGE_YMAX, lbm.LBM_BC_NEUMANN_T, (0.0, 0.001))
         s.set_steps_per_launch(spl)
         s.set_tiling(block, segs)
+        assert s.tiling() == (block, segs)
         s.set_fields(u0, v0)
         s.step(31)
         u, v, P, d, st = s.read()
@@ -199,10 +205,7 @@ def test_resident_blocks_and_default_tiling(gpu):
     for block in (64, 128, 256, 512):
         for spl in (1, 2):
             r = s.resident_blocks(block, spl)
-            if spl == 2 and block == 512:
-                assert r == 0
-            else:
-                assert r > 0 and r % cus == 0, (block, spl, r)
+            assert r > 0 and r % cus == 0, (block, spl, r)
     assert s.resident_blocks(96, 1) == 0
     block, segs = s.tiling()
     assert strips(1000, block, "fp32", "pc", 1) * segs <= s.resident_blocks(block, 1)
@@ -210,3 +213,39 @@ def test_resident_blocks_and_default_tiling(gpu):
     e = lbm.Solver(300, 90, 1.0, "fp32", "explicit")
     assert e.resident_blocks(128, 1) > 0 and e.resident_blocks(128, 2) == 0
     e.close()
+
+
+def test_two_step_block_must_fit_the_lds(gpu):
+    """A 512-thread two-step block holds two pipelines in LDS: it does not fit
+    with FP64 values, nor with a double displacement once the y edges are
+    walls. The tiling call refuses it there, and a wall set later lowers a
+    512-thread tiling to 256 threads."""
+    from paper_2208_13769_amd import lbm
+
+    d = lbm.Solver(300, 90, 1.0, "fp64", "pc")
+    d.set_steps_per_launch(2)
+    assert d.resident_blocks(512, 2) == 0
+    with pytest.raises(lbm.LbmError) as ei:
+        d.set_tiling(512, 2)
+    assert ei.value.status == lbm.LBM_ERR_UNSUPPORTED
+    d.close()
+
+    s = lbm.Solver(300, 90, 1.0, "fp32u64", "pc")
+    s.set_steps_per_launch(2)
+    assert s.resident_blocks(512, 2) > 0
+    s.set_tiling(512, 3)
+    assert s.tiling() == (512, 3)
+    s.set_boundary(lbm.LBM_EDGE_YMIN, lbm.LBM_BC_DIRICHLET_J, (0.0, 0.0))
+    assert s.resident_blocks(512, 2) == 0
+    assert s.tiling() == (256, 3)
+    u0, v0, _, _ = random_case(300, 90, 23, 0.01)
+    s.set_material(1.0, 0.1, 0.05, 0.8)
+    s.set_fields(u0, v0)
+    s.step(4)
+    *_, dg, st = s.read()
+    assert st == 0 and dg.steps == 4
+    # the single-step kernel keeps 512 threads
+    s.set_steps_per_launch(1)
+    s.set_tiling(512, 3)
+    assert s.tiling() == (512, 3)
+    s.close()
