@@ -283,18 +283,20 @@ def bench_plates(args):
         fields.append(inputs.top_pulse(pl.n, 0.01))
     sites = sum(sp.nx * sp.ny for sp in specs)
 
-    def run_batch(precision):
-        arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, precision) for sp in specs) + (64 << 20)
-        b = Batch(max_plates=len(specs), arena_bytes=arena, precision=precision, walled=True)
+    def run_batch(precision, keep=None):
+        keep = range(len(specs)) if keep is None else keep
+        sel = [(specs[i], fields[i]) for i in keep]
+        arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, precision) for sp, _ in sel) + (64 << 20)
+        b = Batch(max_plates=len(sel), arena_bytes=arena, precision=precision, walled=True)
         if args.batch_spl:
             b.set_steps_per_launch(args.batch_spl)
-        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
+        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in sel]
         b.step(args.chunk)  # warm-up chunk: graph capture, first touch
         torch.cuda.synchronize()
         # restart from the start fields for the timed run
         for s_ in slots:
             b.retire(s_)
-        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
+        slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in sel]
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(b.stream)
@@ -323,6 +325,13 @@ def bench_plates(args):
         errs_p.append(np.linalg.norm(p1 - p2) / np.linalg.norm(p2))
     b16.close()
     b64.close()
+    # second run without the plates beyond the interior's stability limit
+    # (lam/mu > 6), so that every plate completes
+    clean = [i for i in range(len(specs)) if specs[i].lam / specs[i].mu <= 6.0]
+    bc, sc, msc = run_batch("fp16", clean)
+    bad_c = sum(1 for s_ in sc if bc.query(s_)[2])
+    clean_sites = sum(specs[i].nx * specs[i].ny for i in clean)
+    bc.close()
     # plain FP32, one plate at a time, on every 16th plate
     sample = list(range(0, len(specs), 16))
     t_fp32, ups_fp32 = 0.0, 0
@@ -355,6 +364,9 @@ def bench_plates(args):
         "error_vs_fp64": {"median_rel_l2_u": float(np.median(errs_u)), "max_rel_l2_u": float(np.max(errs_u)),
                           "median_rel_l2_P": float(np.median(errs_p)), "max_rel_l2_P": float(np.max(errs_p)),
                           "reference": "the same batch in FP64 (bitwise equal to single-plate FP64)"},
+        "clean_run": {"rejected": "lam/mu > 6", "plates": len(clean), "sites": clean_sites,
+                      "diverged_plates": bad_c, "ms_per_step": round(msc / steps, 5),
+                      "MLUPS": round(clean_sites * steps / (msc / 1e3) / 1e6, 1)},
         "fp64_batch_MLUPS": round(sites * steps / (ms64 / 1e3) / 1e6, 1),
         "plain_fp32_one_at_a_time_MLUPS": round(ups_fp32 / t_fp32 / 1e6, 1),
         "plain_fp32_sample": f"every 16th plate ({len(sample)} plates), {steps} steps each",

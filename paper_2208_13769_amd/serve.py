@@ -210,6 +210,7 @@ def main():
     for frac in [float(x) for x in args.rates.split(",")]:
         set_arrivals(reqs, frac * cap, args.seed)
         s_b, *_ = srv.run(reqs)
+        print(json.dumps({"load": frac, "batched_fp16": s_b}), flush=True)
         s_s, *_ = SerialServer("fp32").run(reqs)
         out["runs"].append({"load": frac, "rate_req_per_s": frac * cap, "batched_fp16": s_b, "serial_fp32": s_s})
         print(json.dumps(out["runs"][-1]), flush=True)
