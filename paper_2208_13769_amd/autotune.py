@@ -106,7 +106,7 @@ def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
 def best_tiling(solver, nx: int, ny: int, precision: str, scheme: str):
     import torch
 
-    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v3"
+    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v4"
     cache = _load_cache()
     if key in cache:
         return tuple(cache[key]["tiling"])
