@@ -58,9 +58,11 @@ def strips(nx: int, block: int, precision: str, scheme: str, spl: int) -> int:
 def candidates(solver, nx: int, ny: int, precision: str, scheme: str):
     """(block, segments, steps per launch): block widths that fit the plate,
     one or two time steps per launch (two only with the predictor-corrector
-    and blocks of at most 256 threads), and segment counts that fill 1/2, 1,
-    2, 3 or 4 waves of the blocks the device holds at once (each segment at
-    least 8 rows)."""
+    and where the library can launch the shape), and segment counts that fill
+    1/2, 1, 2, 3 or 4 waves of the blocks the device holds at once (each
+    segment at least 8 rows). A plate whose grid fits one wave also tries
+    segments of ny, ny/2 and ny/4 rows: a block marches its rows one after
+    another, so on a small plate shorter segments cut the time of a step."""
     out = []
     for spl in ((1, 2) if scheme == "pc" else (1,)):
         for block in (64, 128, 256, 512):
@@ -75,6 +77,11 @@ def candidates(solver, nx: int, ny: int, precision: str, scheme: str):
             for waves in (0.5, 1, 2, 3, 4):
                 segs = max(1, min(max(1, ny // 8), int(waves * resident) // n_str))
                 if segs not in seen:
+                    seen.add(segs)
+                    out.append((block, segs, spl))
+            for rows in (1, 2, 4):
+                segs = max(1, ny // rows)
+                if n_str * segs <= resident and segs not in seen:
                     seen.add(segs)
                     out.append((block, segs, spl))
     return out

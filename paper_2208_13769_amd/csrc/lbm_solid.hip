@@ -211,9 +211,22 @@ void plan_launch(lbm_solver *h)
     else if (h->nx <= 128 - 2 * halo)
         block = 128;
     const Shape probe = make_shape(h->nx, h->ny, h->prec, h->scheme, block, 1, h->spl);
-    // as many segments as fit one wave of resident blocks (the last wave of a
-    // longer grid would run part-empty), each of at least 16 rows
     const int resident = std::max(resident_blocks(h, block, h->spl), probe.n_strips);
+    // A block marches its rows one after another, so on a small plate the
+    // step takes as long as the longest march: use the shortest segments (1,
+    // 2, 4 or 8 rows) whose recomputed halo rows keep the launch within one
+    // wave of resident blocks and about 1.5 M thread-rows (measured on 64^2
+    // to 512^2 plates: 1.6-2.5 times faster than 16-row segments).
+    for (int rows = 1; rows <= 8; rows *= 2) {
+        const long long segs = (h->ny + rows - 1) / rows;
+        const long long work = (long long)probe.n_strips * segs * (rows + 2 * halo + 1) * block;
+        if (probe.n_strips * segs <= resident && work <= 1500000) {
+            h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, (int)segs, h->spl);
+            return;
+        }
+    }
+    // otherwise as many segments as fit one wave of resident blocks (the last
+    // wave of a longer grid would run part-empty), each of at least 16 rows
     int n_segs = resident / probe.n_strips;
     n_segs = std::max(1, std::min(n_segs, h->ny / 16));
     h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, n_segs, h->spl);

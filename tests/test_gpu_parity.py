@@ -166,7 +166,7 @@ def test_two_steps_per_launch_bitwise(gpu, precision, walled):
         v0 = v0 + inputs.filtered_random_velocity(nx, ny, 2.0, 22, 0.002)[1]
     else:
         u0, v0, _, _ = random_case(nx, ny, 21, 0.05)
-    shapes = [(1, 256, 5), (2, 256, 5), (2, 128, 3), (2, 64, 7), (2, 256, 1)]
+    shapes = [(1, 256, 5), (2, 256, 5), (2, 128, 3), (2, 64, 7), (2, 256, 1), (2, 128, 90), (1, 64, 45)]
     # 512-thread two-step blocks fit the LDS with FP32, and with a double
     # displacement only on plates periodic in y
     if precision == "fp32" or (precision != "fp64" and not walled):
