@@ -273,7 +273,8 @@ typedef struct {
 
 /* Arena bytes one plate of nx * ny sites uses at precision p. */
 size_t lbm_batch_plate_bytes(int nx, int ny, lbm_precision p);
-/* Tile-table entries one plate uses (column strips times row segments). */
+/* Tile-table entries one plate reserves: column strips times row segments
+ * at the shortest segments the batch plans (4 rows, when few plates run). */
 int lbm_batch_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s);
 /* Workspace bytes of a batch with room for max_plates plates, max_tiles
  * tiles and arena_bytes of plate state. */

@@ -212,7 +212,7 @@ class Batch:
     """A batch of plates on one GPU; the workspace is a torch uint8 tensor."""
 
     def __init__(self, max_plates: int, arena_bytes: int, precision: str = "fp16", scheme: str = "pc",
-                 walled: bool = False, max_tiles: int = 1 << 16, device: str = "cuda:0", stream=None):
+                 walled: bool = False, max_tiles: int = 1 << 18, device: str = "cuda:0", stream=None):
         import torch
 
         self.precision = lbm.PRECISIONS[precision]

@@ -25,7 +25,7 @@ using namespace lbm;
 namespace {
 
 constexpr int kBatchBlock = 256;
-constexpr int kSegRowsMin = 16;  // shortest segment when few plates run
+constexpr int kSegRowsMin = 4;  // shortest segment when few plates run
 // rows per segment when the batch is full (the two-step halo is twice as deep)
 constexpr int seg_rows_max(int spl) { return spl == 2 ? 128 : 64; }
 
