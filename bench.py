@@ -182,7 +182,8 @@ def bench_hole(args):
     side l = 1 on n x n nodes (default 4096), a centred hole of 0.4 l, all four
     edges and the hole traction-free except for a normal traction of 0.02 mu
     on the top and bottom edges, lam = mu = rho0 = 1, tau/dt = 0.8, starting
-    at rest. It runs on the general per-site passes (five launches per step)."""
+    at rest. It runs on the general per-site passes (five passes, eight
+    launches per step)."""
     import torch
 
     from oracle import oracle as O

@@ -16,7 +16,7 @@ struct FieldParams {
     int bc_left, bc_right;      // x edges
     double uw_left[2], uw_right[2];
     double lam, mu;             // lattice units
-    const unsigned char *mask;  // [ny][nx] 1 material, 0 hole (Sec. 7.2); nullptr: no holes
+    const unsigned char *mask;  // [ny][nx] bit 0: material (1) or hole (0), Sec. 7.2; bit 1: interior; nullptr: no holes
 };
 
 // Node (x, y) lies in a hole; coordinates beyond a periodic edge wrap,
@@ -32,7 +32,7 @@ __device__ inline bool in_hole(const FieldParams &p, int x, int y)
         if (p.bc_left != BC_PERIODIC) return false;
         x = (x % p.nx + p.nx) % p.nx;
     }
-    return p.mask[(size_t)y * p.nx + x] == 0;
+    return (p.mask[(size_t)y * p.nx + x] & 1) == 0;
 }
 
 // Displacement of node (x, y), 0 <= x < nx, in lattice units, with the

@@ -60,7 +60,7 @@ struct GenParams {
     void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
     void *up;    // scratch [2][ny][nx] TU: predictor displacement
     unsigned *flag;
-    const unsigned char *mask;  // [ny][nx] 1 material, 0 hole; nullptr: no holes
+    const unsigned char *mask;  // [ny][nx] bit 0: material (1) or hole (0); bit 1: interior; nullptr: no holes
     const int *edge_k;          // ring indices (y + 1)(nx + 2) + x + 1 of the stress pass's edge nodes
     const int *edge_f;          // lattice indices of the stream pass's edge nodes
     int n_edge_k, n_edge_f;
@@ -142,7 +142,7 @@ __device__ __forceinline__ bool g_hole(const GenParams &p, int x, int y)
         if (p.bc[EDGE_XMIN] != BC_PERIODIC) return false;
         x = (x % p.nx + p.nx) % p.nx;
     }
-    return p.mask[(size_t)y * p.nx + x] == 0;
+    return (p.mask[(size_t)y * p.nx + x] & 1) == 0;
 }
 
 // central-difference gradient of u at (x, y) (lattice or ghost ring); a hole
@@ -169,10 +169,8 @@ __device__ __forceinline__ void gen_grad(const GenParams &p, const typename PR::
 __device__ __forceinline__ bool g_inner(const GenParams &p, int x, int y)
 {
     if (x < 1 || x > p.nx - 2 || y < 1 || y > p.ny - 2) return false;
-    if (!p.mask) return true;
-    const unsigned char *m = p.mask + (size_t)(y - 1) * p.nx + (x - 1);
-    const size_t r = (size_t)p.nx;
-    return (m[0] & m[1] & m[2] & m[r] & m[r + 1] & m[r + 2] & m[2 * r] & m[2 * r + 1] & m[2 * r + 2]) != 0;
+    // bit 1 of the mask: the host marked the node interior
+    return !p.mask || (p.mask[(size_t)y * p.nx + x] & 2) != 0;
 }
 
 __device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
@@ -206,28 +204,44 @@ __global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int 
 {
     using TU = typename PR::TU;
     using TC = typename PR::TC;
-    const int w = p.nx + 2;
-    const int tid = blockIdx.x * 256 + threadIdx.x;
-    if (tid >= (EDGE ? p.n_edge_k : w * (p.ny + 2))) return;
-    const int s = EDGE ? p.edge_k[tid] : tid;
-    const int y = s / w - 1, x = s % w - 1;
     const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
-    const double t = (double)(p.step + which);
     TC *Kp = static_cast<TC *>(p.K);
     if (!EDGE) {
-        if (!g_inner(p, x, y)) return;
+        // lattice rows of ceil(nx / 256) blocks each: the row index is the
+        // same for the whole block (no per-thread division)
+        const int nbx = (p.nx + 255) / 256;
+        const int y = (int)blockIdx.x / nbx;
+        const int x = ((int)blockIdx.x - y * nbx) * 256 + (int)threadIdx.x;
+        if (x < 1 || x > p.nx - 2 || y < 1 || y > p.ny - 2) return;
+        // the four neighbours lie in the lattice: load them before the mask
+        // test so that both loads are in flight together (a hole node's u is
+        // read for nothing; measured faster all the same)
         const size_t pl = (size_t)p.plane, o = (size_t)y * p.nx + x;
-        TC H[4], K[4];
+        TU v[2][4];
         for (int a = 0; a < 2; ++a) {
             const TU *ua = u + a * pl + o;
-            H[2 * a + 0] = TC((ua[1] - ua[-1]) * TU(0.5));
-            H[2 * a + 1] = TC((ua[p.nx] - ua[-(ptrdiff_t)p.nx]) * TU(0.5));
+            v[a][0] = ua[1];
+            v[a][1] = ua[-1];
+            v[a][2] = ua[p.nx];
+            v[a][3] = ua[-(ptrdiff_t)p.nx];
+        }
+        if (!g_inner(p, x, y)) return;
+        TC H[4], K[4];
+        for (int a = 0; a < 2; ++a) {
+            H[2 * a + 0] = TC((v[a][0] - v[a][1]) * TU(0.5));
+            H[2 * a + 1] = TC((v[a][2] - v[a][3]) * TU(0.5));
         }
         const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
         for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
         if (which == 0 && !(J > TC(0))) p.flag[0] = 1u;
         return;
     }
+    const int w = p.nx + 2;
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    if (tid >= p.n_edge_k) return;
+    const int s = p.edge_k[tid];
+    const int y = s / w - 1, x = s % w - 1;
+    const double t = (double)(p.step + which);
     if (g_hole(p, x, y)) {
         // K seen from the material neighbour across each axis (zero if none)
         TC kx[4] = {TC(0), TC(0), TC(0), TC(0)}, ky[4] = {TC(0), TC(0), TC(0), TC(0)};
@@ -528,15 +542,15 @@ inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
     p.jf = scratch + off;
     off += al(2 * n * sizeof(TC));
     p.up = scratch + off;
-    const int nb = (int)((n + 255) / 256), nbe = (int)((ne + 255) / 256);
+    const int nb = (int)((n + 255) / 256), nbi = (p.nx + 255) / 256 * p.ny;
     const int nbk = (p.n_edge_k + 255) / 256, nbf = (p.n_edge_f + 255) / 256;
-    hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbe), dim3(256), 0, st, p, 0);
+    hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbi), dim3(256), 0, st, p, 0);
     if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 0);
     hipLaunchKernelGGL((collide_pass<PR>), dim3(nb), dim3(256), 0, st, p);
     hipLaunchKernelGGL((stream_pass<PR, false>), dim3(nb), dim3(256), 0, st, p);
     if (nbf) hipLaunchKernelGGL((stream_pass<PR, true>), dim3(nbf), dim3(256), 0, st, p);
     if (p.pc) {
-        hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbe), dim3(256), 0, st, p, 1);
+        hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbi), dim3(256), 0, st, p, 1);
         if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 1);
         hipLaunchKernelGGL((update_pass<PR>), dim3(nb), dim3(256), 0, st, p);
     }

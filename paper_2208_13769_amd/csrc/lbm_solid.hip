@@ -421,8 +421,23 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
     if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
     h->mask_host.assign(solid, solid + (size_t)nx * ny);
     for (auto &m : h->mask_host) m = m ? 1 : 0;
-    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, h->mask_host.data(), (size_t)nx * ny, hipMemcpyHostToDevice,
-                              h->stream));
+    // The device copy also marks interior nodes in bit 1: the node and its
+    // eight neighbours are material nodes of the lattice, so the interior
+    // launches of the general passes read one byte instead of nine.
+    std::vector<unsigned char> dev(h->mask_host);
+    const unsigned char *mh = h->mask_host.data();
+    for (int y = 1; y < ny - 1; ++y)
+        for (int x = 1; x < nx - 1; ++x) {
+            bool in = true;
+            for (int dy = -1; dy <= 1 && in; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    if (!mh[(size_t)(y + dy) * nx + (x + dx)]) {
+                        in = false;
+                        break;
+                    }
+            if (in) dev[(size_t)y * nx + x] |= 2;
+        }
+    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, dev.data(), (size_t)nx * ny, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->has_mask = true;
     h->edges_dirty = true;
