@@ -213,6 +213,15 @@ def test_resident_blocks_and_default_tiling(gpu):
     e = lbm.Solver(300, 90, 1.0, "fp32", "explicit")
     assert e.resident_blocks(128, 1) > 0 and e.resident_blocks(128, 2) == 0
     e.close()
+    # a small plate is latency-bound: the default plan marches one-row
+    # segments; a large one keeps segments of at least 16 rows
+    small = lbm.Solver(64, 64, 1.0, "fp64", "pc")
+    assert small.tiling() == (128, 64)
+    small.close()
+    large = lbm.Solver(2048, 2048, 1.0, "fp32", "pc")
+    block, segs = large.tiling()
+    assert 2048 // segs >= 16
+    large.close()
 
 
 def test_two_step_block_must_fit_the_lds(gpu):
