@@ -944,8 +944,11 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
 }
 
 // Single-plate step: one block per tile. Blocks are dealt round-robin to the
-// 8 XCDs; the remap gives each XCD a run of consecutive tiles, which are
-// vertical neighbours sharing their halo rows in that XCD's L2.
+// 8 XCDs; the remap gives each XCD a run of consecutive tiles, ordered row
+// segment by row segment: horizontal neighbours march the same rows at the
+// same time, so the halo columns they share are read once into that XCD's
+// L2. (Vertical neighbours reach their shared halo rows a whole segment
+// apart, long after L2 has dropped them.)
 template <class PR, int BLOCK, bool PC, bool WALLED>
 __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
 {
@@ -954,8 +957,8 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int xq = nb >> 3, xr = nb & 7;
     const int xcd = bid & 7, loc = bid >> 3;
     const int logical = xcd * xq + min(xcd, xr) + loc;
-    const int strip = logical / p.n_segs;
-    const int seg = logical - strip * p.n_segs;
+    const int seg = logical / p.n_strips;
+    const int strip = logical - seg * p.n_strips;
     __shared__ TileLds<PR, BLOCK, PC, WALLED> lds;
     step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg, lds);
 }
@@ -969,8 +972,8 @@ __global__ void __launch_bounds__(BLOCK) step2_kernel(const StepParams p)
     const int xq = nb >> 3, xr = nb & 7;
     const int xcd = bid & 7, loc = bid >> 3;
     const int logical = xcd * xq + min(xcd, xr) + loc;
-    const int strip = logical / p.n_segs;
-    const int seg = logical - strip * p.n_segs;
+    const int seg = logical / p.n_strips;
+    const int strip = logical - seg * p.n_strips;
     __shared__ TileLds<PR, BLOCK, true, WALLED> lds[2];
     step2_tile<PR, BLOCK, WALLED>(p, strip, seg, lds[0], lds[1]);
 }
