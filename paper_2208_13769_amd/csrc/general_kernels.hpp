@@ -54,7 +54,7 @@ struct GenParams {
     int sr;
     unsigned long long seed;
     int pc;  // explicit (0), predictor-corrector (1), j extrapolated for the predictor (2)
-    void *K;     // scratch [4][ny + 2][nx + 2] TC: stress sum with one ghost ring
+    void *K;     // scratch [4][ny + 2][k_pitch(nx)] TC: stress sum with one ghost ring
     void *fcol;  // scratch [9][ny][nx] TC: post-collision populations
     void *S;     // scratch [2][ny][nx] TC: source S_n
     void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
@@ -173,9 +173,13 @@ __device__ __forceinline__ bool g_inner(const GenParams &p, int x, int y)
     return !p.mask || (p.mask[(size_t)y * p.nx + x] & 2) != 0;
 }
 
+// Row pitch of K: column x sits at x + 32, so the lattice columns of every
+// row start on a 128-byte line and a wave's store covers whole lines.
+__host__ __device__ __forceinline__ size_t k_pitch(int nx) { return ((size_t)nx + 33 + 31) / 32 * 32; }
+
 __device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
 {
-    return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * (p.nx + 2) + (size_t)(x + 1);
+    return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * k_pitch(p.nx) + (size_t)(x + 32);
 }
 
 // K at the hole neighbour of (x, y) across axis n: K of the node's gradient
@@ -518,7 +522,7 @@ inline size_t general_scratch_bytes(int nx, int ny)
 {
     using TU = typename PR::TU;
     using TC = typename PR::TC;
-    const size_t n = (size_t)nx * ny, ne = (size_t)(nx + 2) * (ny + 2);
+    const size_t n = (size_t)nx * ny, ne = k_pitch(nx) * (ny + 2);
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     return al(4 * ne * sizeof(TC)) + al(9 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) +
            al(2 * n * sizeof(TU));
@@ -530,7 +534,7 @@ template <class PR>
 inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
 {
     using TC = typename PR::TC;
-    const size_t n = (size_t)p.nx * p.ny, ne = (size_t)(p.nx + 2) * (p.ny + 2);
+    const size_t n = (size_t)p.nx * p.ny, ne = k_pitch(p.nx) * (p.ny + 2);
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     size_t off = 0;
     p.K = scratch + off;
