@@ -50,7 +50,8 @@ def _specs(walled):
 
 
 @pytest.mark.parametrize("precision,walled,spl", [("fp16", True, 2), ("fp32", False, 2), ("fp64", True, 2),
-                                                  ("fp16", True, 1), ("fp32", False, 1)])
+                                                  ("fp16", True, 1), ("fp32", False, 1), ("fp32u64", False, 2),
+                                                  ("fp32u64", True, 1), ("bf16", True, 1), ("bf16", False, 2)])
 def test_batch_equals_plates_alone(gpu, precision, walled, spl):
     """Every plate of a mixed batch equals the same plate run alone, bitwise,
     after each of several graph-replayed chunks (eager reads in between);
