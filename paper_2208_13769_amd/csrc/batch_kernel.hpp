@@ -31,6 +31,8 @@ struct PlateDesc {
     unsigned long long seed;
 };
 
+// One tile of the persistent grid's table; plate < 0 marks an empty entry
+// (a block with fewer tiles than others in a packed table).
 struct TileDesc {
     int plate, strip, seg, pad;
 };
@@ -81,6 +83,7 @@ __global__ void __launch_bounds__(BLOCK)
     const int nt = *n_tiles;
     for (int tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         const TileDesc td = tiles[tile];
+        if (td.plate < 0) continue;  // empty entry (uniform over the block)
         const PlateDesc &pd = plates[td.plate];
         if (k >= pd.nsteps) continue;  // uniform over the block
         const StepParams sp = plate_step_params(pd, (pd.parity0 + k) & 1, pd.step0 + k);
@@ -102,6 +105,7 @@ __global__ void __launch_bounds__(BLOCK)
     const int nt = *n_tiles;
     for (int tile = blockIdx.x; tile < nt; tile += gridDim.x) {
         const TileDesc td = tiles[tile];
+        if (td.plate < 0) continue;  // empty entry (uniform over the block)
         const PlateDesc &pd = plates[td.plate];
         const int left = pd.nsteps - 2 * k;
         if (left <= 0) continue;  // uniform over the block

@@ -12,8 +12,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -26,7 +28,8 @@ namespace {
 
 constexpr int kBatchBlock = 256;
 constexpr int kSegRowsMin = 4;  // shortest segment when few plates run
-// rows per segment when the batch is full (the two-step halo is twice as deep)
+// The planner tries segment heights from kSegRowsMin up to twice this (the
+// two-step halo is twice as deep).
 constexpr int seg_rows_max(int spl) { return spl == 2 ? 128 : 64; }
 
 struct Slot {
@@ -505,21 +508,80 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     const int w = b->buf;
     if (b->ev_used[w]) BHIP_TRY(b, hipEventSynchronize(b->ev[w]));
     const bool tiles_changed = !b->tables_valid || run != b->running;
+    std::vector<std::vector<int>> bins;  // tiles per block of the persistent grid (packed plan)
+    std::vector<TileDesc> plan;
     if (tiles_changed) {
-        // Segment height for the running set: about two tiles per block of
-        // the persistent grid, segments between kSegRowsMin and seg_rows_max
-        // rows (short segments keep a step short when few plates run; long
-        // ones keep the halo rows few when many do).
-        long long strip_rows = 0;
-        for (int i : run) {
-            const Shape one = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, 1 << 30, b->spl);
-            strip_rows += (long long)one.n_strips * b->slots[i].ny;
+        // Segment height and placement for the running set. Block g of the
+        // persistent grid takes entries g, g + G, g + 2G, ... of the table, and
+        // a tile costs its rows plus the pipeline's fill. Each candidate height
+        // (kSegRowsMin up to twice seg_rows_max) splits the strips into
+        // tiles, which are packed longest first onto the least loaded block;
+        // the height whose busiest block has the least work is kept (the
+        // larger one on a tie: fewer halo rows). Short segments win when few
+        // plates run, long ones when many do.
+        const int G = b->grid;
+        const int fill = (b->scheme == LBM_SCHEME_PC ? 11 : 7) * b->spl;
+        long long best = -1;
+        int best_rows = kSegRowsMin;
+        for (int rows = kSegRowsMin; rows <= 2 * seg_rows_max(b->spl); rows *= 2) {
+            std::vector<long long> cost;
+            for (int i : run) {
+                const Shape sh = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, rows, b->spl);
+                const int ny = b->slots[i].ny;
+                for (int st = 0; st < sh.n_strips; ++st)
+                    for (int sg = 0; sg < sh.n_segs; ++sg)
+                        cost.push_back((long long)(sg + 1) * ny / sh.n_segs - (long long)sg * ny / sh.n_segs + fill);
+            }
+            std::sort(cost.begin(), cost.end(), std::greater<long long>());
+            std::priority_queue<long long, std::vector<long long>, std::greater<long long>> load;
+            for (int g = 0; g < G; ++g) load.push(0);
+            long long top = 0;
+            for (long long c : cost) {
+                const long long l = load.top() + c;
+                load.pop();
+                load.push(l);
+                top = std::max(top, l);
+            }
+            if (best < 0 || top <= best) {
+                best = top;
+                best_rows = rows;
+            }
         }
-        const long long want = 2LL * b->grid;
-        const int seg_rows = (int)std::max<long long>(
-            kSegRowsMin, std::min<long long>(seg_rows_max(b->spl), strip_rows / want));
         for (int i : run)
-            b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, seg_rows, b->spl);
+            b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, best_rows, b->spl);
+        // pack the chosen tiles (longest first, least loaded block first)
+        std::vector<std::pair<int, TileDesc>> tl;
+        for (int i : run) {
+            const Shape &sh = b->slots[i].shape;
+            const int ny = b->slots[i].ny;
+            for (int st = 0; st < sh.n_strips; ++st)
+                for (int sg = 0; sg < sh.n_segs; ++sg)
+                    tl.push_back({(int)((long long)(sg + 1) * ny / sh.n_segs - (long long)sg * ny / sh.n_segs),
+                                  TileDesc{i, st, sg, 0}});
+        }
+        std::stable_sort(tl.begin(), tl.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
+        bins.assign(G, {});
+        std::priority_queue<std::pair<long long, int>, std::vector<std::pair<long long, int>>,
+                            std::greater<std::pair<long long, int>>>
+            load;
+        for (int g = 0; g < G; ++g) load.push({0, g});
+        for (int t = 0; t < (int)tl.size(); ++t) {
+            auto [l, g] = load.top();
+            load.pop();
+            bins[g].push_back(t);
+            load.push({l + tl[t].first + fill, g});
+        }
+        size_t depth = 0;
+        for (const auto &bn : bins) depth = std::max(depth, bn.size());
+        if (depth * (size_t)G <= (size_t)b->max_tiles) {
+            // block g's k-th tile at entry g + kG; empty entries elsewhere
+            plan.assign(depth * (size_t)G, TileDesc{-1, 0, 0, 0});
+            for (int g = 0; g < G; ++g)
+                for (size_t q = 0; q < bins[g].size(); ++q) plan[g + q * (size_t)G] = tl[bins[g][q]].second;
+        } else {
+            // the packed table would not fit: tiles in plan order, dealt by the stride
+            for (const auto &e : tl) plan.push_back(e.second);
+        }
     }
     int max_slot = 0;
     for (int i : run) max_slot = std::max(max_slot, i + 1);
@@ -527,13 +589,8 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     for (int i : run) b->h_plates[w][i] = describe(b, i, (int)std::min<int64_t>(K, b->slots[i].target - b->slots[i].done));
     int nt = 0;
     if (tiles_changed) {
-        // plate by plate, strip by strip; consecutive tiles are vertical
-        // neighbours of one strip
-        for (int i : run) {
-            const Shape &sh = b->slots[i].shape;
-            for (int st = 0; st < sh.n_strips; ++st)
-                for (int sg = 0; sg < sh.n_segs; ++sg) b->h_tiles[w][nt++] = TileDesc{i, st, sg, 0};
-        }
+        nt = (int)plan.size();
+        std::memcpy(b->h_tiles[w], plan.data(), sizeof(TileDesc) * plan.size());
         *b->h_ntiles[w] = nt;
     }
     BHIP_TRY(b, hipMemcpyAsync(b->d_plates(), b->h_plates[w], sizeof(PlateDesc) * max_slot, hipMemcpyHostToDevice,
