@@ -549,27 +549,37 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
         }
         for (int i : run)
             b->slots[i].shape = batch_shape(b->slots[i].nx, b->slots[i].ny, b->prec, b->scheme, best_rows, b->spl);
-        // pack the chosen tiles (longest first, least loaded block first)
+        // Pack the chosen tiles: longest first, onto the least loaded block.
+        // A plate's tiles are listed segment by segment and equally loaded
+        // blocks are taken XCD by XCD (blocks are dealt round-robin to the 8
+        // XCDs), so horizontal neighbours tend to run at the same time on
+        // one XCD and share their halo columns in its L2.
         std::vector<std::pair<int, TileDesc>> tl;
         for (int i : run) {
             const Shape &sh = b->slots[i].shape;
             const int ny = b->slots[i].ny;
-            for (int st = 0; st < sh.n_strips; ++st)
-                for (int sg = 0; sg < sh.n_segs; ++sg)
+            for (int sg = 0; sg < sh.n_segs; ++sg)
+                for (int st = 0; st < sh.n_strips; ++st)
                     tl.push_back({(int)((long long)(sg + 1) * ny / sh.n_segs - (long long)sg * ny / sh.n_segs),
                                   TileDesc{i, st, sg, 0}});
         }
         std::stable_sort(tl.begin(), tl.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
         bins.assign(G, {});
+        const int per_xcd = (G + 7) / 8;
+        auto rank = [&](int g) { return (g & 7) * per_xcd + (g >> 3); };  // XCD-major order of block g
         std::priority_queue<std::pair<long long, int>, std::vector<std::pair<long long, int>>,
                             std::greater<std::pair<long long, int>>>
-            load;
-        for (int g = 0; g < G; ++g) load.push({0, g});
+            load;  // (work, rank)
+        std::vector<int> block_of(8 * per_xcd, -1);
+        for (int g = 0; g < G; ++g) {
+            block_of[rank(g)] = g;
+            load.push({0, rank(g)});
+        }
         for (int t = 0; t < (int)tl.size(); ++t) {
-            auto [l, g] = load.top();
+            auto [l, r] = load.top();
             load.pop();
-            bins[g].push_back(t);
-            load.push({l + tl[t].first + fill, g});
+            bins[block_of[r]].push_back(t);
+            load.push({l + tl[t].first + fill, r});
         }
         size_t depth = 0;
         for (const auto &bn : bins) depth = std::max(depth, bn.size());
