@@ -148,3 +148,30 @@ def test_batch_unstable_plate_is_isolated(gpu):
     u2, v2, *_ = _single(good, ug, vg, 300, "fp32")
     assert np.array_equal(u1, u2) and np.array_equal(v1, v2)
     b.close()
+
+
+def test_packed_tile_table_with_many_tiles_per_block(gpu):
+    """A batch with several tiles per block of the persistent grid (the
+    packed table then has empty entries and blocks with different tile
+    counts): sampled plates still equal the same plates run alone, bitwise."""
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+
+    rng = np.random.default_rng(11)
+    sizes = [int(s) for s in rng.integers(300, 700, size=48)]
+    specs = [PlateSpec(nx=n, ny=n + 7 * (k % 5), lam=0.1, mu=0.05, tau_over_dt=0.8,
+                       bc_ymin=lbm.LBM_BC_DIRICHLET_J, bc_ymax=lbm.LBM_BC_NEUMANN_T)
+             for k, n in enumerate(sizes)]
+    arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, "fp16") for sp in specs) + (64 << 20)
+    b = Batch(max_plates=len(specs), arena_bytes=arena, precision="fp16", walled=True)
+    ins = [_plate_inputs(sp.nx, sp.ny, 60 + k, True) for k, sp in enumerate(specs)]
+    steps = [5 if k % 3 else 4 for k in range(len(specs))]
+    slots = [b.add(sp, u0, v0, steps[k]) for k, (sp, (u0, v0)) in enumerate(zip(specs, ins))]
+    assert None not in slots
+    b.step(5)
+    for k in (0, 7, 19, 30, 47):
+        ub, vb, Pb, db, st = b.read(slots[k])
+        us, vs, Ps, ds, st2 = _single(specs[k], *ins[k], steps[k], "fp16")
+        assert st == 0 and st2 == 0 and db.steps == steps[k]
+        assert np.array_equal(ub, us) and np.array_equal(vb, vs) and np.array_equal(Pb, Ps), k
+    b.close()
