@@ -71,3 +71,42 @@ def test_full_size_sampled_regions(gpu, start_fields, precision, tiling, tol):
         worst = max(worst, eu, eP)
     s.close()
     assert worst < tol
+
+
+def test_plates_256_fp64_batch_against_oracle_on_sampled_plates(gpu):
+    """The batched workload at full size, in the benchmark's launch
+    configuration: all 256 seeded plates (side log-uniform in 64..1024,
+    clamped bottom, traction-free top, top pulse 0.01) in one FP64 batch,
+    2000 steps in graph-captured chunks of 200. Whole plates are sampled:
+    the three smallest within the interior's stability range (lam/mu <= 6)
+    and one of about 200 nodes against the oracle. FP64 rounding differences
+    between the two grow about in proportion to the step count, so the bound
+    is the 1e-12 of the 1000-step FP64 workload scaled to 2000 steps."""
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+    from tests.helpers import oracle_run
+
+    plates = inputs.plate_batch(256, seed=4)
+    steps, chunk = 2000, 200
+    specs = [PlateSpec(nx=pl.n, ny=pl.n, lam=pl.lam, mu=pl.mu, tau_over_dt=0.8,
+                       bc_ymin=lbm.LBM_BC_DIRICHLET_J, bc_ymax=lbm.LBM_BC_NEUMANN_T) for pl in plates]
+    fields = [inputs.top_pulse(pl.n, 0.01) for pl in plates]
+    arena = sum(Batch.plate_bytes_for(sp.nx, sp.ny, "fp64") for sp in specs) + (64 << 20)
+    b = Batch(max_plates=len(specs), arena_bytes=arena, precision="fp64", walled=True)
+    slots = [b.add(sp, u0, v0, steps) for sp, (u0, v0) in zip(specs, fields)]
+    assert None not in slots
+    for _ in range(steps // chunk):
+        b.step(chunk)
+    stable = [i for i, pl in enumerate(plates) if pl.lam / pl.mu <= 6.0]
+    picks = sorted(stable, key=lambda i: plates[i].n)[:3]
+    picks.append(min(stable, key=lambda i: abs(plates[i].n - 200)))
+    for i in picks:
+        sp, (u0, v0) = specs[i], fields[i]
+        ub, vb, Pb, db, st = b.read(slots[i])
+        assert st == 0 and db.steps == steps
+        uo, vo, Po, _ = oracle_run(sp.nx, sp.ny, u0, v0, steps, lam=sp.lam, mu=sp.mu, tau=0.8,
+                                   bc_lo=("dirichlet", (0.0, 0.0)), bc_hi=("neumann", (0.0, 0.0)))
+        eu, ep = rel_l2(ub, uo), rel_l2(Pb, Po)
+        print(f"plate {i}: n {sp.nx}, lam/mu {sp.lam / sp.mu:.2f}: rel-L2 u {eu:.2e} P {ep:.2e}", flush=True)
+        assert eu < 2e-12 and ep < 2e-12, (i, eu, ep)
+    b.close()
