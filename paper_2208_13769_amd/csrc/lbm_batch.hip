@@ -508,7 +508,6 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
     const int w = b->buf;
     if (b->ev_used[w]) BHIP_TRY(b, hipEventSynchronize(b->ev[w]));
     const bool tiles_changed = !b->tables_valid || run != b->running;
-    std::vector<std::vector<int>> bins;  // tiles per block of the persistent grid (packed plan)
     std::vector<TileDesc> plan;
     if (tiles_changed) {
         // Segment height and placement for the running set. Block g of the
@@ -564,7 +563,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps)
                                   TileDesc{i, st, sg, 0}});
         }
         std::stable_sort(tl.begin(), tl.end(), [](const auto &a, const auto &c) { return a.first > c.first; });
-        bins.assign(G, {});
+        std::vector<std::vector<int>> bins(G);  // tiles of each block of the persistent grid
         const int per_xcd = (G + 7) / 8;
         auto rank = [&](int g) { return (g & 7) * per_xcd + (g >> 3); };  // XCD-major order of block g
         std::priority_queue<std::pair<long long, int>, std::vector<std::pair<long long, int>>,
