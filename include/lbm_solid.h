@@ -253,7 +253,10 @@ const char *lbm_last_error(const lbm_solver *h);
  * share the precision, the scheme and the kind of y edges (all periodic, or
  * all walls with per-plate rules and values); x edges are periodic.
  * The batch uses 256-thread blocks; plates are cut into column strips and
- * segments of about 64 rows.
+ * row segments. Whenever the set of running plates changes, the segment
+ * height (4 to 128 rows, 4 to 256 with two steps per launch) and the
+ * placement of the tiles on the blocks of the persistent grid are chosen
+ * on the host so that the busiest block has the least work.
  * ------------------------------------------------------------------------ */
 
 typedef struct lbm_batch lbm_batch;
@@ -299,8 +302,9 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps);
 
 /* Time steps per launch of the batch kernel: 1, or 2 with the
- * predictor-corrector scheme (the default when the two-step kernel of the
- * batch's precision and edges keeps two waves per SIMD). With 2, a launch advances
+ * predictor-corrector scheme (the default with FP64, and with the other
+ * forms when their two-step kernel keeps two waves per SIMD for the batch's
+ * edges). With 2, a launch advances
  * every running plate by two steps in one pass over its state, or by one
  * step when that is the plate's last; results equal one step per launch
  * bitwise. Changing it synchronises the stream and re-plans the tiles. */
