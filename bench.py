@@ -400,7 +400,7 @@ def main():
     ap.add_argument("--hole-n", type=int, default=4096, help="hole: nodes per side")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the single-plate path has no multi-GPU decomposition).", file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ typedef enum {
     LBM_ERR_HIP = -3,         /* a HIP runtime call failed */
     LBM_ERR_STATE = -4,       /* call out of order (e.g. step before set_fields) */
     LBM_ERR_UNSTABLE = -5,    /* J <= 0 or a non-finite value appeared */
-    LBM_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+    LBM_ERR_UNSUPPORTED = -6  /* valid request the library does not implement */
 } lbm_status;
 
 /* Storage and arithmetic precision.
