@@ -245,6 +245,9 @@ class Batch:
         return lbm_batch_plate_bytes(nx, ny, lbm.PRECISIONS[precision])
 
     def add(self, spec: PlateSpec, u0, v0, nsteps: int):
+        for name, a in (("u0", u0), ("v0", v0)):
+            if np.shape(a) != (2, spec.ny, spec.nx):
+                raise ValueError(f"{name} of shape {np.shape(a)}; expected (2, {spec.ny}, {spec.nx})")
         slot = lbm_batch_add(self.h, spec.c(), u0, v0, nsteps)
         if slot is not None:
             self.specs[slot] = spec

@@ -158,7 +158,7 @@ def lbm_set_mask(h, solid):
     if solid is None:
         _check(load_library().lbm_set_mask(h, None), h)
         return
-    m = np.ascontiguousarray(solid, dtype=np.uint8)
+    m = np.ascontiguousarray(np.asarray(solid) != 0, dtype=np.uint8)
     _check(load_library().lbm_set_mask(h, m.ctypes.data_as(ctypes.c_void_p)), h)
 
 
@@ -174,12 +174,16 @@ def lbm_set_material(h, rho0, lam, mu, tau_over_dt):
 
 
 def lbm_set_body_force(h, b):
-    b = np.ascontiguousarray(b, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    if b.size != 2:
+        raise ValueError(f"body force of {b.size} values; expected 2")
     _check(load_library().lbm_set_body_force(h, _dptr(b)), h)
 
 
 def lbm_set_boundary(h, edge, bc, value=None):
-    v = None if value is None else np.ascontiguousarray(value, dtype=np.float64)
+    v = None if value is None else np.ascontiguousarray(value, dtype=np.float64).ravel()
+    if v is not None and v.size != 2:
+        raise ValueError(f"boundary value of {v.size} values; expected 2")
     _check(load_library().lbm_set_boundary(h, edge, bc, _dptr(v)), h)
 
 
@@ -207,8 +211,10 @@ def lbm_read_derived(h, sigma=None, E=None, W=None):
 
 def lbm_sample(h, xs, ys) -> np.ndarray:
     """[n][17] values at the nodes (xs[k], ys[k]); columns as SAMPLE_FIELDS."""
-    xs = np.ascontiguousarray(xs, dtype=np.int32)
-    ys = np.ascontiguousarray(ys, dtype=np.int32)
+    xs = np.ascontiguousarray(xs, dtype=np.int32).ravel()
+    ys = np.ascontiguousarray(ys, dtype=np.int32).ravel()
+    if len(xs) != len(ys):
+        raise ValueError(f"{len(xs)} x coordinates for {len(ys)} y coordinates")
     out = np.empty((len(xs), 17))
     _check(load_library().lbm_sample(h, len(xs), _iptr(xs), _iptr(ys), _dptr(out)), h)
     return out
@@ -328,9 +334,15 @@ class Solver:
 
     def set_mask(self, solid):
         """solid: [ny][nx] array, nonzero for material, 0 for holes; None removes it."""
+        if solid is not None and np.shape(solid) != (self.ny, self.nx):
+            raise ValueError(f"mask of shape {np.shape(solid)} for a {self.ny} x {self.nx} plate")
         lbm_set_mask(self.h, solid)
 
     def set_fields(self, u0, v0):
+        """u0, v0: [2][ny][nx] start displacement and velocity (physical units)."""
+        for name, a in (("u0", u0), ("v0", v0)):
+            if np.shape(a) != (2, self.ny, self.nx):
+                raise ValueError(f"{name} of shape {np.shape(a)}; expected (2, {self.ny}, {self.nx})")
         lbm_set_fields(self.h, u0, v0)
 
     def step(self, n: int):

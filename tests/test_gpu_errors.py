@@ -68,3 +68,45 @@ def test_nonfinite_start_fields_rejected(gpu):
     u0[0, 3, 4] = np.nan
     assert _status(s.set_fields, u0, np.zeros((2, 24, 24))) == lbm.LBM_ERR_ARG
     s.close()
+
+
+def test_binding_rejects_wrong_shapes_before_the_library(gpu):
+    """Host arrays of the wrong shape never reach the library (it reads
+    exactly the sizes the plate implies); a mask is material where nonzero."""
+    from paper_2208_13769_amd.batch import Batch, PlateSpec
+
+    lbm, s = _solver()
+    s.set_material(1.0, 0.1, 0.05, 0.8)
+    z = np.zeros((2, 24, 24))
+    with pytest.raises(ValueError):
+        s.set_fields(np.zeros((2, 24, 23)), z)
+    with pytest.raises(ValueError):
+        s.set_fields(z, np.zeros((24, 24)))
+    with pytest.raises(ValueError):
+        s.set_body_force([0.0])
+    with pytest.raises(ValueError):
+        s.set_boundary(lbm.LBM_EDGE_YMIN, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0, 0.0))
+    s.set_fields(z, z)
+    with pytest.raises(ValueError):
+        s.sample([1, 2], [3])
+    s.close()
+
+    w = lbm.Solver(24, 24, 1.0, "fp64", "pc", walled=True)
+    w.set_material(1.0, 0.1, 0.05, 0.8)
+    for e in (lbm.LBM_EDGE_XMIN, lbm.LBM_EDGE_XMAX, lbm.LBM_EDGE_YMIN, lbm.LBM_EDGE_YMAX):
+        w.set_boundary(e, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))
+    with pytest.raises(ValueError):
+        w.set_mask(np.ones((24, 23)))
+    m = np.full((24, 24), 0.5)  # fractional values are material, not truncated to holes
+    m[8:16, 8:16] = 0.0
+    w.set_mask(m)
+    w.set_fields(z, z)
+    w.step(2)
+    u, v, P, d, st = w.read()
+    assert st == 0 and np.all(u[:, 8:16, 8:16] == 0.0)
+    w.close()
+
+    b = Batch(max_plates=2, arena_bytes=16 << 20, precision="fp32")
+    with pytest.raises(ValueError):
+        b.add(PlateSpec(nx=32, ny=20), np.zeros((2, 32, 20)), np.zeros((2, 32, 20)), 4)
+    b.close()
