@@ -86,6 +86,12 @@ def _summary(name, reqs, finish):
             "makespan_s": span, "MLUPS": ups / span / 1e6}
 
 
+def _progress(name, done, total, every):
+    """One line per `every` finished requests (0: silent)."""
+    if every and done % every == 0:
+        print(json.dumps({"server": name, "finished": done, "of": total}), flush=True)
+
+
 def _wait_until(start, t):
     while True:
         d = t - (time.perf_counter() - start)
@@ -97,8 +103,9 @@ def _wait_until(start, t):
 class SerialServer:
     """One request at a time on a single-plate solver (FIFO)."""
 
-    def __init__(self, precision: str = "fp32"):
+    def __init__(self, precision: str = "fp32", progress: int = 0):
         self.precision = precision
+        self.progress = progress
 
     def serve_one(self, r: Request):
         s = lbm.Solver(r.n, r.n, 1.0, self.precision, "pc")
@@ -118,16 +125,19 @@ class SerialServer:
             finish[r.rid] = time.perf_counter() - start
             if keep is not None and r.rid in keep:
                 results[r.rid] = out
+            _progress(f"serial-{self.precision}", len(finish), len(reqs), self.progress)
         return _summary(f"serial-{self.precision}", reqs, finish), finish, results
 
 
 class BatchServer:
     """Continuous batching: resident plates advanced together in chunks."""
 
-    def __init__(self, arena_bytes: int, precision: str = "fp16", chunk: int = 200, max_plates: int = 512):
+    def __init__(self, arena_bytes: int, precision: str = "fp16", chunk: int = 200, max_plates: int = 512,
+                 progress: int = 0):
         self.batch = Batch(max_plates=max_plates, arena_bytes=arena_bytes, precision=precision, walled=False)
         self.precision = precision
         self.chunk = chunk
+        self.progress = progress
 
     def close(self):
         self.batch.close()
@@ -169,6 +179,7 @@ class BatchServer:
                         results[r.rid] = out
                     b.retire(slot)
                     del live[slot]
+                    _progress(f"batched-{self.precision}", len(finish), len(reqs), self.progress)
         summ = _summary(f"batched-{self.precision}", reqs, finish)
         summ["max_resident"] = max_live
         summ["chunk"] = self.chunk
@@ -192,6 +203,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=200)
     ap.add_argument("--arena-gib", type=float, default=16.0)
     ap.add_argument("--steps-max", type=int, default=20000)
+    ap.add_argument("--progress", type=int, default=0, help="print a line every N finished requests")
+    ap.add_argument("--capacity", type=float, default=0.0,
+                    help="serial FP32 capacity in requests/s to set the rates from (0: measure it)")
     args = ap.parse_args()
     import torch
 
@@ -199,10 +213,10 @@ def main():
     # warm both paths (kernels, graphs, allocator) on a few small requests
     warm = make_requests(3, args.seed + 1, n_median=64, steps_max=600)
     capacity(warm)
-    srv = BatchServer(int(args.arena_gib * (1 << 30)), chunk=args.chunk)
+    srv = BatchServer(int(args.arena_gib * (1 << 30)), chunk=args.chunk, progress=args.progress)
     set_arrivals(warm, 1e6, 0)
     srv.run(warm)
-    cap = capacity(reqs[: max(4, len(reqs) // 6)])
+    cap = args.capacity if args.capacity > 0 else capacity(reqs[: max(4, len(reqs) // 6)])
     out = {"capacity_serial_fp32_req_per_s": cap, "requests": args.requests,
            "mix": "N lognormal(median 256, sd_ln 0.83) in [32, 2048], steps U[500, %d], periodic, "
                   "lam=0.1 mu=0.05 tau/dt=0.8, Gaussian-filtered start velocity" % args.steps_max,
@@ -211,7 +225,7 @@ def main():
         set_arrivals(reqs, frac * cap, args.seed)
         s_b, *_ = srv.run(reqs)
         print(json.dumps({"load": frac, "batched_fp16": s_b}), flush=True)
-        s_s, *_ = SerialServer("fp32").run(reqs)
+        s_s, *_ = SerialServer("fp32", progress=args.progress).run(reqs)
         out["runs"].append({"load": frac, "rate_req_per_s": frac * cap, "batched_fp16": s_b, "serial_fp32": s_s})
         print(json.dumps(out["runs"][-1]), flush=True)
     srv.close()
