@@ -43,7 +43,12 @@ def _patch(a, x0, y0):
     return np.ascontiguousarray(a[:, ys][:, :, xs])
 
 
-@pytest.mark.parametrize("precision,tiling,tol", [("fp32u64", (256, 26, 2), 1e-5), ("fp64", None, 1e-12)])
+# The 16-bit forms run in their own benchmark's launch shape (512-thread
+# two-step blocks, 28 segments) on the same large-strain start. FP16 meets
+# the 1e-3 target (worst region P 9.9e-4); BF16 does not (P up to 1.0e-2),
+# and its bound only holds that measured error.
+@pytest.mark.parametrize("precision,tiling,tol", [("fp32u64", (256, 26, 2), 1e-5), ("fp64", None, 1e-12),
+                                                  ("fp16", (512, 28, 2), 1e-3), ("bf16", (512, 28, 2), 2e-2)])
 def test_full_size_sampled_regions(gpu, start_fields, precision, tiling, tol):
     from paper_2208_13769_amd import lbm
 
