@@ -37,8 +37,9 @@ def test_counter_record_only_for_its_kernel_and_shape():
     # another launch shape or plate size: no traffic figure
     assert bench.traffic_for("fp32u64", n, t["block"], t["n_segs"] + 1, t["steps_per_launch"]) is None
     assert bench.traffic_for("fp32u64", n // 4, t["block"], t["n_segs"], t["steps_per_launch"]) is None
-    # a storage form without a record
+    # another storage form's record is for its own launch shape; no record at all
     assert bench.traffic_for("fp64", n, t["block"], t["n_segs"], t["steps_per_launch"]) is None
+    assert bench.traffic_for("no-such-form", n, t["block"], t["n_segs"], t["steps_per_launch"]) is None
 
 
 def test_code_hash_ignores_comments(tmp_path, monkeypatch):
