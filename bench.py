@@ -15,15 +15,22 @@ Prints one JSON line with MLUPS, the HBM roofline fraction of the step kernel,
 the FP64 oracle timed on the host cores on a bounded sample, and the rel-L2
 error of the GPU against that oracle sample.
 
-Roofline accounting: a launch must read the 13-value state (f, u, j) of every
-site once and write it once, however many time steps it fuses, so its
-algorithmic bytes are BYTES_PER_SITE_PASS x sites per launch (104 B per site
-in FP32). With two steps per launch that is 52 B per lattice update; the
-per-step figure of a one-step-per-launch pass (104 B per update in FP32) is
-reported beside it as ``per_step_equivalent_GBps`` for comparison only, with
-MLUPS as a fraction of that one-pass-per-step ceiling
-(``mlups_frac_of_that_ceiling``; 8 TB/s / 120 B = 66,667 MLUPS in FP32 with
-an FP64 displacement).
+Timing: after the warm-up steps, --repeats windows of --steps time steps
+each are timed with HIP events on the plate's stream; ms_per_step and the
+roofline use the median window (every window's time is listed).
+
+Roofline accounting (per lattice update): a lattice update reads the 13-value
+state (f, u, j) of a site and writes it once, so its algorithmic bytes are
+BYTES_PER_UPDATE of the storage form (208 B in FP64, 104 B in FP32, 120 B in
+FP32 with an FP64 displacement, 84 B with 16-bit populations). A launch of
+the step kernel processes sites x steps-per-launch updates, so
+``achieved`` = BYTES_PER_UPDATE x sites x steps-per-launch / launch time, and
+``frac`` is that over the HBM peak: the fraction of the ceiling of a scheme
+that streams the state once per time step (MLUPS / (8 TB/s / BYTES_PER_UPDATE)).
+With two steps per launch the kernel streams the state once per two updates,
+so this figure can exceed what the HBM moves; the rate of the launch's own
+minimum traffic (the state read and written once per launch) is reported
+beside it as ``per_launch_state_GBps``.
 """
 from __future__ import annotations
 
@@ -41,11 +48,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (fp64/fp32/fp16-storage) at stated error vs FP64 oracle; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per site per pass over the state: f (9), u (2), j (2)
-# read once and written once
-BYTES_PER_SITE_PASS = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp32u64": 2 * (9 * 4 + 2 * 8 + 2 * 4),
-                       "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
-                       "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
+# algorithmic bytes of one lattice update: the state f (9), u (2), j (2) of
+# a site read once and written once
+BYTES_PER_UPDATE = {"fp64": 2 * 13 * 8, "fp32": 2 * 13 * 4, "fp32u64": 2 * (9 * 4 + 2 * 8 + 2 * 4),
+                    "fp16": 2 * (9 * 2 + 2 * 8 + 2 * 4),
+                    "bf16": 2 * (9 * 2 + 2 * 8 + 2 * 4)}
+# one pass of a launch over the state moves the same bytes per site
+BYTES_PER_SITE_PASS = BYTES_PER_UPDATE
 DTYPE = {"fp64": "f64", "fp32": "f32", "fp32u64": "f32 (f64 displacement)", "fp16": "f16-storage/f32",
          "bf16": "bf16-storage/f32"}
 
@@ -110,6 +119,44 @@ def traffic_for(precision: str, sites: int, block: int, segs: int, spl: int):
             or rec.get("tiling") != {"block": block, "n_segs": segs, "steps_per_launch": spl}):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def timed_windows(solver, stream, steps: int, repeats: int):
+    """Time `repeats` windows of `steps` time steps each with HIP events on
+    the solver's stream (a device synchronisation on both sides of each).
+    Returns the window times in ms and the host wall time of all windows."""
+    import torch
+
+    out = []
+    wall0 = time.perf_counter()
+    for _ in range(repeats):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        solver.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out.append(ev0.elapsed_time(ev1))
+    return out, time.perf_counter() - wall0
+
+
+def step_roofline(prec: str, sites: int, spl: int, ms_step: float, traffic):
+    """Roofline object of the step kernel: algorithmic bytes per launch are
+    BYTES_PER_UPDATE x the updates one launch processes (sites x spl), over
+    the launch's duration (spl time steps)."""
+    ms_launch = spl * ms_step
+    updates_launch = sites * spl
+    bytes_launch = BYTES_PER_UPDATE[prec] * updates_launch
+    achieved = bytes_launch / (ms_launch / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "step2_kernel" if spl == 2 else "step_kernel", "steps_per_launch": spl,
+            "launch_us": round(ms_launch * 1e3, 2), "bytes_per_update": BYTES_PER_UPDATE[prec],
+            "updates_per_launch": updates_launch, "algorithmic_bytes_per_launch": bytes_launch,
+            # the launch's own minimum traffic: the state read and written once
+            "per_launch_state_GBps": round(BYTES_PER_SITE_PASS[prec] * sites / (ms_launch / 1e3) / 1e9, 1),
+            "mlups_ceiling_at_peak": round(HBM_PEAK_GBS * 1e3 / BYTES_PER_UPDATE[prec], 1)}
 
 
 def cpu_baseline(wl, steps: int):
@@ -212,12 +259,8 @@ def bench_hole(args):
     copy_probe(args.copy_probe_mib, s.device)
     s.step(args.warmup)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(s.stream)
-    s.step(args.steps)
-    e1.record(s.stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    windows_ms, _ = timed_windows(s, s.stream, args.steps, args.repeats)
+    ms_step = float(np.median(windows_ms)) / args.steps
     u, v, P, d, st = s.read()
     s.close()
     per_pass = general_bytes_per_site(prec)
@@ -233,7 +276,8 @@ def bench_hole(args):
                                f"{h}x{h}, all edges and the hole traction-free except 0.02 mu normal traction on "
                                "top and bottom, lam = mu = 1, tau/dt = 0.8, predictor-corrector; general per-site "
                                "passes; MLUPS counts material nodes",
-                   "grid": [n, n], "material_sites": material, "precision": prec, "scheme": "pc"},
+                   "grid": [n, n], "material_sites": material, "precision": prec, "scheme": "pc",
+                   "repeats": args.repeats, "window_ms": [round(w, 4) for w in windows_ms]},
         # whole-step roofline: the passes of one step as one unit (bytes each pass must move)
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -383,6 +427,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--repeats", type=int, default=5, help="timed windows of --steps steps; the median is reported")
     ap.add_argument("--workload", default="large-strain-4096",
                     help="large-strain-4096 (default) | fp16-4096 | shear-wave-64 | plates-256 | hole")
     ap.add_argument("--precision", default=None,
@@ -442,34 +487,14 @@ def main():
     copy_probe(args.copy_probe_mib, s.device)
     s.step(args.warmup)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1)
+    windows_ms, wall = timed_windows(s, stream, args.steps, args.repeats)
+    ms = float(np.median(windows_ms))
     _, _, _, diag, status = s.read(want_fields=False)
 
     sites = nx * ny
     ms_step = ms / args.steps
     mlups = sites * args.steps / (ms / 1e3) / 1e6
-    # a launch advances every site by `spl` time steps in one pass over the state
-    ms_launch = spl * ms_step
-    bytes_launch = BYTES_PER_SITE_PASS[prec] * sites
-    achieved = bytes_launch / (ms_launch / 1e3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(prec, sites, block, segs, spl),
-                "kernel": "step2_kernel" if spl == 2 else "step_kernel", "steps_per_launch": spl,
-                "launch_us": round(ms_launch * 1e3, 2), "bytes_per_site_per_launch": BYTES_PER_SITE_PASS[prec],
-                "per_step_equivalent_GBps": round(BYTES_PER_SITE_PASS[prec] * sites / (ms_step / 1e3) / 1e9, 1),
-                # MLUPS against the ceiling of a pass that reads and writes
-                # the state once per time step at the HBM peak
-                "mlups_ceiling_one_pass_per_step": round(HBM_PEAK_GBS * 1e3 / BYTES_PER_SITE_PASS[prec], 1),
-                "mlups_frac_of_that_ceiling": round(mlups / (HBM_PEAK_GBS * 1e3 / BYTES_PER_SITE_PASS[prec]), 4)}
+    roofline = step_roofline(prec, sites, spl, ms_step, traffic_for(prec, sites, block, segs, spl))
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -477,6 +502,7 @@ def main():
         "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [nx, ny], "sites": sites, "precision": prec, "scheme": "pc",
                    "tiling": {"block": block, "n_segs": segs, "steps_per_launch": spl, "source": tiling_source},
+                   "repeats": args.repeats, "window_ms": [round(w, 4) for w in windows_ms],
                    "wall_s": round(wall, 4)},
         "roofline": roofline,
         "run": {"status": int(status), "max_strain": diag.max_strain, "min_J": diag.min_J},

@@ -215,9 +215,11 @@ lbm_status lbm_set_general_path(lbm_solver *h, int on);
  * neighbour takes the node's own displacement. Hole nodes hold no
  * material: their fields read as zero and they add nothing to the
  * diagnostics. Holes must keep off the rows and columns next to a wall
- * edge (they may cross periodic edges), and neither a material node nor a
- * hole node may have nodes of the other kind on both sides along one axis
- * (material and holes at least two nodes thick; LBM_ERR_ARG otherwise). Once a mask
+ * edge (they may cross periodic edges), and no material node may have hole
+ * nodes on both sides along one axis (material at least two nodes thick;
+ * LBM_ERR_ARG otherwise; the method gives such a node no gradient). A hole
+ * one node wide is valid for the method but not implemented here
+ * (LBM_ERR_UNSUPPORTED): holes must be at least two nodes wide. Once a mask
  * is set, lbm_set_boundary may change boundary values and kinds but may not
  * make an edge periodic or not (LBM_ERR_STATE). Set
  * the boundaries first, then the mask, then the fields (LBM_ERR_STATE

@@ -273,10 +273,28 @@ static double ghost(int kind, double uw, double u0, double u1, int k)
     return u0;
 }
 
-/* Ghost displacements (Q11, Q20) around the lattice. t is the time at which
- * u is taken; a momentum wall with value j* has moved by j* t / rho0 (it
- * starts at rest). Periodic edges copy the opposite side. */
-static void extend_u(const oracle_params *p, const double *u, double t, double *ue)
+/* Wall displacements: wall[e][a] for the edges e = xmin, xmax, ymin, ymax
+ * (component a) is the displacement of a momentum wall at the time of the
+ * state. Every wall starts at rest (zero displacement) and moves with the
+ * velocity j* / rho0 of the value in effect, so one step of length dt moves
+ * it by j* dt / rho0 (the wall is a rigid body driven by its prescribed
+ * momentum, Sec. 6). */
+enum { WALL_XMIN = 0, WALL_XMAX = 1, WALL_YMIN = 2, WALL_YMAX = 3 };
+
+static void advance_walls(const oracle_params *p, const double wall[8], double out[8])
+{
+    const int kind[4] = {p->bc_xmin, p->bc_xmax, p->bc_ymin, p->bc_ymax};
+    const double *val[4] = {p->val_xmin, p->val_xmax, p->val_ymin, p->val_ymax};
+    double dt = oracle_dt(p);
+    for (int e = 0; e < 4; ++e)
+        for (int a = 0; a < 2; ++a)
+            out[2 * e + a] = wall[2 * e + a] + (kind[e] == ORACLE_DIRICHLET_J ? val[e][a] * dt / p->rho0 : 0.0);
+}
+
+/* Ghost displacements (Q11, Q20) around the lattice, with the momentum
+ * walls at the displacements wall[] (see advance_walls). Periodic edges copy
+ * the opposite side. */
+static void extend_u(const oracle_params *p, const double *u, const double wall[8], double *ue)
 {
     int nx = p->nx, ny = p->ny;
     for (int a = 0; a < 2; ++a) {
@@ -284,7 +302,7 @@ static void extend_u(const oracle_params *p, const double *u, double t, double *
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) ue[ue_at(p, a, y, x)] = ua[at(p, y, x)];
         /* ghost rows of the lattice columns */
-        double uwlo = p->val_ymin[a] * t / p->rho0, uwhi = p->val_ymax[a] * t / p->rho0;
+        double uwlo = wall[2 * WALL_YMIN + a], uwhi = wall[2 * WALL_YMAX + a];
         for (int x = 0; x < nx; ++x)
             for (int k = 1; k <= 2; ++k) {
                 if (p->bc_ymin == ORACLE_PERIODIC) {
@@ -297,7 +315,7 @@ static void extend_u(const oracle_params *p, const double *u, double t, double *
                 }
             }
         /* ghost columns of every extended row (corners included) */
-        double uwl = p->val_xmin[a] * t / p->rho0, uwr = p->val_xmax[a] * t / p->rho0;
+        double uwl = wall[2 * WALL_XMIN + a], uwr = wall[2 * WALL_XMAX + a];
         for (int y = -2; y < ny + 2; ++y)
             for (int k = 1; k <= 2; ++k) {
                 if (p->bc_xmin == ORACLE_PERIODIC) {
@@ -394,12 +412,12 @@ static void source_field(const oracle_params *p, const double *ue, const double 
         }
 }
 
-/* source 1S(u) at time t for the whole lattice */
-static void source_of_u(const oracle_params *p, const double *u, double t, double *S)
+/* source 1S(u) for the whole lattice, walls at the displacements wall[] */
+static void source_of_u(const oracle_params *p, const double *u, const double wall[8], double *S)
 {
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     double *K = malloc(sizeof(double) * 4 * k_plane(p));
-    extend_u(p, u, t, ue);
+    extend_u(p, u, wall, ue);
     stress_sum(p, ue, K);
     source_field(p, ue, K, S);
     free(ue);
@@ -500,8 +518,9 @@ static double bb_term(const oracle_params *p, int i, const double jstar[2])
 }
 
 /* Periodic edges come in pairs. Hole nodes (Q23) keep off rows and columns
- * next to a wall, and neither a material node nor a hole node has nodes of
- * the other kind on both sides along one axis. */
+ * next to a wall, and no material node has hole nodes on both sides along
+ * one axis (the method gives such a node no gradient along that axis). A
+ * hole may be a single node wide. */
 static int edges_valid(const oracle_params *p)
 {
     if ((p->bc_xmin == ORACLE_PERIODIC) != (p->bc_xmax == ORACLE_PERIODIC) ||
@@ -513,9 +532,6 @@ static int edges_valid(const oracle_params *p)
             int hole = in_hole(p, y, x);
             if (hole && (((y == 0 || y == p->ny - 1) && p->bc_ymin != ORACLE_PERIODIC) ||
                          ((x == 0 || x == p->nx - 1) && p->bc_xmin != ORACLE_PERIODIC)))
-                return 0;
-            if (hole && ((!in_hole(p, y, x - 1) && !in_hole(p, y, x + 1)) ||
-                         (!in_hole(p, y - 1, x) && !in_hole(p, y + 1, x))))
                 return 0;
             if (!hole && ((in_hole(p, y, x - 1) && in_hole(p, y, x + 1)) ||
                           (in_hole(p, y - 1, x) && in_hole(p, y + 1, x))))
@@ -532,7 +548,8 @@ int oracle_init(const oracle_params *p, const double *u0, const double *v0,
     int nx = p->nx, ny = p->ny;
     if (nx < 5 || ny < 5 || !edges_valid(p)) return -1;
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
-    extend_u(p, u0, 0.0, ue);
+    static const double rest[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    extend_u(p, u0, rest, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
@@ -558,13 +575,16 @@ int oracle_init(const oracle_params *p, const double *u0, const double *v0,
     return 0;
 }
 
-/* One time step of Algorithm 1 with readings R1/R2. step is the index n of
- * the state on entry (time t = n dt). */
-static void one_step(const oracle_params *p, double *f, double *u, double *j, double *jprev, long step)
+/* One time step of Algorithm 1 with readings R1/R2. wall[] holds the
+ * momentum walls' displacements at the time of the state on entry and is
+ * advanced with it. */
+static void one_step(const oracle_params *p, double *f, double *u, double *j, double *jprev, double wall[8])
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
-    double dt = oracle_dt(p), t = step * dt;
+    double dt = oracle_dt(p);
+    double wall_next[8];
+    advance_walls(p, wall, wall_next);
     double omega = 1.0 / p->tau_over_dt; /* dt / tau */
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
     double *K = malloc(sizeof(double) * 4 * k_plane(p));
@@ -575,7 +595,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
     double *Sp = malloc(sizeof(double) * 2 * N);
 
     /* 1. stress sum K(u_n) and source 1S_n (eq. (23)) */
-    extend_u(p, u, t, ue);
+    extend_u(p, u, wall, ue);
     stress_sum(p, ue, K);
     source_field(p, ue, K, S);
 
@@ -689,7 +709,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
                                            : 2.0 * j[a * N + s] - jprev[a * N + s];
                 up[a * N + s] = u[a * N + s] + dt / (2.0 * p->rho0) * (jp + j[a * N + s]);
             }
-        source_of_u(p, up, t + dt, Sp);
+        source_of_u(p, up, wall_next, Sp);
         free(up);
     } else {
         memcpy(Sp, S, sizeof(double) * 2 * N);
@@ -704,6 +724,7 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
             j[a * N + s] = jnew;
         }
     memcpy(f, fnew, sizeof(double) * 9 * N);
+    memcpy(wall, wall_next, sizeof(wall_next));
 
     free(ue);
     free(K);
@@ -714,33 +735,36 @@ static void one_step(const oracle_params *p, double *f, double *u, double *j, do
     free(Sp);
 }
 
-int oracle_step(const oracle_params *p, double *f, double *u, double *j, long step0, int nsteps)
+/* nsteps steps of the predictor-corrector or explicit scheme; wall[8] (see
+ * advance_walls) is advanced with the state. */
+int oracle_step(const oracle_params *p, double *f, double *u, double *j, double *wall, int nsteps)
 {
     if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p) || p->scheme < 0 || p->scheme > 1)
         return -1;
-    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, NULL, step0 + n);
+    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, NULL, wall);
     return 0;
 }
 
 /* any scheme; jprev holds j one step before the state (j itself before the
- * first step) and is advanced with it */
-int oracle_step_prev(const oracle_params *p, double *f, double *u, double *j, double *jprev, long step0,
+ * first step) and is advanced with it, as is wall[8] */
+int oracle_step_prev(const oracle_params *p, double *f, double *u, double *j, double *jprev, double *wall,
                      int nsteps)
 {
     if (p->nx < 5 || p->ny < 5 || p->tau_over_dt <= 0.5 || !edges_valid(p) || p->scheme < 0 || p->scheme > 2)
         return -1;
-    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, jprev, step0 + n);
+    for (int n = 0; n < nsteps; ++n) one_step(p, f, u, j, jprev, wall);
     return 0;
 }
 
-/* Output fields: v = j / rho0 and the first Piola-Kirchhoff stress P(H(u)). */
-int oracle_fields(const oracle_params *p, const double *u, const double *j, double t,
+/* Output fields: v = j / rho0 and the first Piola-Kirchhoff stress P(H(u)),
+ * with the walls at the displacements wall[8]. */
+int oracle_fields(const oracle_params *p, const double *u, const double *j, const double *wall,
                   double *v, double *P)
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
-    extend_u(p, u, t, ue);
+    extend_u(p, u, wall, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
@@ -764,12 +788,12 @@ int oracle_fields(const oracle_params *p, const double *u, const double *j, doub
  * Green-Lagrange strain E[a][b][y][x] and strain-energy density W[y][x], all
  * from the same central-difference H(u) as the Piola stress of
  * oracle_fields. Any output may be NULL. */
-int oracle_derived(const oracle_params *p, const double *u, double t, double *sig, double *E, double *W)
+int oracle_derived(const oracle_params *p, const double *u, const double *wall, double *sig, double *E, double *W)
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
-    extend_u(p, u, t, ue);
+    extend_u(p, u, wall, ue);
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             size_t s = at(p, y, x);
@@ -802,12 +826,12 @@ int oracle_derived(const oracle_params *p, const double *u, double t, double *si
  * the Green-Lagrange strain E = (F^T F - I)/2, out[6] = 1 if any value is not
  * finite or J <= 0. Sums run in plain row-major order. */
 int oracle_diagnostics(const oracle_params *p, const double *f, const double *u,
-                       const double *j, double t, double out[7])
+                       const double *j, const double *wall, double out[7])
 {
     int nx = p->nx, ny = p->ny;
     size_t N = plane(p);
     double *ue = malloc(sizeof(double) * 2 * ue_plane(p));
-    extend_u(p, u, t, ue);
+    extend_u(p, u, wall, ue);
     double sj0 = 0, sj1 = 0, sr = 0, en = 0, minJ = INFINITY, maxE = 0;
     int bad = 0;
     for (int y = 0; y < ny; ++y)

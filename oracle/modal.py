@@ -45,7 +45,14 @@ def _source_hat(u_hat, sk, lam_l, mu_l):
 
 
 def step_map(state, k, lam_over_mu, tau_over_dt, scheme="pc"):
-    """Apply one step to a 13-vector of Fourier amplitudes."""
+    """Apply one step to a 13-vector of Fourier amplitudes.
+
+    scheme: "pc" (reading R2), "explicit" (the source time level printed in
+    Algorithm 1), both with the populations' own second moment in the
+    equilibrium (reading R1); or "literal": Algorithm 1 as printed, whose
+    equilibrium takes the Poisson stress Pbar(H(u)) of the current
+    displacement (eq. (15)) in place of the populations' second moment, with
+    the explicit source."""
     mu_l = 1.0 / 3.0
     lam_l = lam_over_mu / 3.0
     omega = 1.0 / tau_over_dt
@@ -56,7 +63,11 @@ def step_map(state, k, lam_over_mu, tau_over_dt, scheme="pc"):
 
     S = _source_hat(u, sk, lam_l, mu_l)
     r = f.sum()
-    Pi = np.einsum("i,ia,ib->ab", f, E, E)
+    if scheme == "literal":
+        H = np.array([[1j * sk[b] * u[a] for b in range(2)] for a in range(2)])
+        Pi = -mu_l * (H + H.T + (H[0, 0] + H[1, 1]) * np.eye(2))
+    else:
+        Pi = np.einsum("i,ia,ib->ab", f, E, E)
     A = Pi - r / 3.0 * np.eye(2)
     feq = np.array([W[i] * (r + 3.0 * E[i] @ j + 4.5 * np.sum(A * (np.outer(E[i], E[i]) - np.eye(2) / 3.0)))
                     for i in range(9)])

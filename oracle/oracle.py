@@ -66,15 +66,15 @@ def lib():
         _lib.oracle_dt.restype = ctypes.c_double
         _lib.oracle_dt.argtypes = [pp]
         _lib.oracle_init.argtypes = [pp, dp, dp, dp, dp, dp]
-        _lib.oracle_step.argtypes = [pp, dp, dp, dp, ctypes.c_long, ctypes.c_int]
-        _lib.oracle_step_prev.argtypes = [pp, dp, dp, dp, dp, ctypes.c_long, ctypes.c_int]
-        _lib.oracle_fields.argtypes = [pp, dp, dp, ctypes.c_double, dp, dp]
-        _lib.oracle_diagnostics.argtypes = [pp, dp, dp, dp, ctypes.c_double, dp]
+        _lib.oracle_step.argtypes = [pp, dp, dp, dp, dp, ctypes.c_int]
+        _lib.oracle_step_prev.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_int]
+        _lib.oracle_fields.argtypes = [pp, dp, dp, dp, dp, dp]
+        _lib.oracle_diagnostics.argtypes = [pp, dp, dp, dp, dp, dp]
         _lib.oracle_piola.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.oracle_poisson.argtypes = [ctypes.c_double, dp, dp]
         _lib.oracle_cauchy.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.oracle_green_lagrange.argtypes = [dp, dp]
-        _lib.oracle_derived.argtypes = [pp, dp, ctypes.c_double, dp, dp, dp]
+        _lib.oracle_derived.argtypes = [pp, dp, dp, dp, dp, dp]
         _lib.oracle_strain_energy.restype = ctypes.c_double
         _lib.oracle_strain_energy.argtypes = [ctypes.c_double, ctypes.c_double, dp]
         _lib.oracle_equilibrium.argtypes = [pp, ctypes.c_double, dp, dp, dp]
@@ -147,6 +147,9 @@ class Solver:
         self.u = np.zeros((2, ny, nx))
         self.j = np.zeros((2, ny, nx))
         self.jprev = np.zeros((2, ny, nx))  # j one step back (the extrapolation variant)
+        # displacement of each momentum wall (edges xmin, xmax, ymin, ymax),
+        # zero at the start and advanced by the oracle with every step
+        self.wall = np.zeros((4, 2))
         self.step_index = 0
         u0 = np.ascontiguousarray(u0, dtype=np.float64)
         v0 = np.ascontiguousarray(v0, dtype=np.float64)
@@ -164,7 +167,7 @@ class Solver:
 
     def step(self, n: int) -> None:
         rc = lib().oracle_step_prev(ctypes.byref(self._pc), _ptr(self.f), _ptr(self.u), _ptr(self.j),
-                                    _ptr(self.jprev), self.step_index, int(n))
+                                    _ptr(self.jprev), _ptr(self.wall), int(n))
         if rc != 0:
             raise ValueError("oracle_step rejected the parameters")
         self.step_index += int(n)
@@ -180,7 +183,7 @@ class Solver:
         ny, nx = self.p.ny, self.p.nx
         v = np.zeros((2, ny, nx))
         P = np.zeros((2, 2, ny, nx))
-        lib().oracle_fields(ctypes.byref(self._pc), _ptr(self.u), _ptr(self.j), self.t, _ptr(v), _ptr(P))
+        lib().oracle_fields(ctypes.byref(self._pc), _ptr(self.u), _ptr(self.j), _ptr(self.wall), _ptr(v), _ptr(P))
         return self.u.copy(), v, P
 
     def derived(self):
@@ -190,13 +193,13 @@ class Solver:
         sig = np.zeros((2, 2, ny, nx))
         E = np.zeros((2, 2, ny, nx))
         W = np.zeros((ny, nx))
-        lib().oracle_derived(ctypes.byref(self._pc), _ptr(self.u), self.t, _ptr(sig), _ptr(E), _ptr(W))
+        lib().oracle_derived(ctypes.byref(self._pc), _ptr(self.u), _ptr(self.wall), _ptr(sig), _ptr(E), _ptr(W))
         return sig, E, W
 
     def diagnostics(self) -> dict:
         out = np.zeros(7)
         lib().oracle_diagnostics(ctypes.byref(self._pc), _ptr(self.f), _ptr(self.u), _ptr(self.j),
-                                 self.t, _ptr(out))
+                                 _ptr(self.wall), _ptr(out))
         return {"momentum": out[0:2].copy(), "mass_moment": out[2], "energy": out[3],
                 "min_J": out[4], "max_strain": out[5], "unstable": bool(out[6])}
 

@@ -224,6 +224,8 @@ class Batch:
         self.h = lbm_batch_create(max_plates, max_tiles, self.precision, self.scheme, walled,
                                   ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                   ctypes.c_void_p(self.stream.cuda_stream))
+        self.arena_bytes = arena_bytes
+        self.max_tiles = max_tiles
         self.specs = {}
 
     def close(self):
@@ -244,6 +246,12 @@ class Batch:
     def plate_bytes_for(nx, ny, precision: str):
         return lbm_batch_plate_bytes(nx, ny, lbm.PRECISIONS[precision])
 
+    def fits_empty(self, nx, ny) -> bool:
+        """Whether a plate of nx x ny sites fits the batch when no other plate
+        is resident (its arena bytes and tile-table entries)."""
+        return (lbm_batch_plate_bytes(nx, ny, self.precision) <= self.arena_bytes
+                and lbm_batch_plate_tiles(nx, ny, self.precision, self.scheme) <= self.max_tiles)
+
     def add(self, spec: PlateSpec, u0, v0, nsteps: int):
         for name, a in (("u0", u0), ("v0", v0)):
             if np.shape(a) != (2, spec.ny, spec.nx):
@@ -255,6 +263,10 @@ class Batch:
 
     def step(self, nsteps: int):
         lbm_batch_step(self.h, nsteps)
+
+    def synchronize(self):
+        """Wait for the work enqueued on the batch's stream."""
+        self.stream.synchronize()
 
     def query(self, slot):
         return lbm_batch_query(self.h, slot)

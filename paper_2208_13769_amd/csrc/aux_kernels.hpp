@@ -173,6 +173,16 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
     }
 }
 
+// Multiply the n stored 16-bit populations at f by a power of two (lowering
+// the per-plate scale when a new load needs more headroom). Exact unless a
+// value drops below the format's normal range.
+template <class TF>
+__global__ void __launch_bounds__(256) rescale_kernel(TF *f, long long n, float factor)
+{
+    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (s < n) f[s] = FStore<TF>::conv(FStore<TF>::cvt(f[s], 1.0f) * factor, 1.0f);
+}
+
 // ---------------------------------------------------------------- read-out
 
 struct ReadParams {

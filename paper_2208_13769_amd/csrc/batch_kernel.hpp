@@ -61,6 +61,8 @@ __device__ __forceinline__ StepParams plate_step_params(const PlateDesc &pd, int
     sp.val_lo[1] = pd.val_lo[1];
     sp.val_hi[0] = pd.val_hi[0];
     sp.val_hi[1] = pd.val_hi[1];
+    // a batch plate's wall values never change: its walls are at j* n
+    sp.uwb_lo[0] = sp.uwb_lo[1] = sp.uwb_hi[0] = sp.uwb_hi[1] = 0.0;
     sp.f_scale = pd.f_scale;
     sp.f_inv_scale = pd.f_inv_scale;
     sp.strip_w = pd.strip_w;

@@ -49,6 +49,7 @@ struct GenParams {
     double omega, lam, mu, bx, by;  // lattice units
     int bc[4];                      // rule of each edge (BC_*), EDGE_* order
     double val[4][2];               // j* or T* of each edge, lattice units
+    double uwb[4][2];               // momentum walls: displacement uwb + j* n at step n
     double f_scale, f_inv_scale;
     long long step;                 // index n of the input state
     int sr;
@@ -87,11 +88,11 @@ __device__ __forceinline__ TU gen_ghost(int kind, TU uw, TU a, TU b, int k)
     return k == 1 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
 }
 
-// wall displacement of edge e at step t (lattice units)
+// momentum-wall displacement of edge e at step t (lattice units)
 template <class TU>
 __device__ __forceinline__ TU gen_uw(const GenParams &p, int e, int a, double t)
 {
-    return TU(p.val[e][a] * t);
+    return TU(p.uwb[e][a] + p.val[e][a] * t);
 }
 
 // u of column x (0 <= x < nx) at row y (-2 <= y <= ny + 1): ghost rows of
@@ -531,7 +532,7 @@ inline size_t general_scratch_bytes(int nx, int ny)
 // Enqueue one time step of the passes on the stream; scratch is
 // general_scratch_bytes<PR>(nx, ny) bytes, 256-byte aligned.
 template <class PR>
-inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
+hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
 {
     using TC = typename PR::TC;
     const size_t n = (size_t)p.nx * p.ny, ne = k_pitch(p.nx) * (p.ny + 2);
@@ -560,5 +561,13 @@ inline hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
     }
     return hipGetLastError();
 }
+
+// Each precision's passes are compiled in an object of their own
+// (instantiate.hip).
+extern template hipError_t general_step<PrecF64>(GenParams, char *, hipStream_t);
+extern template hipError_t general_step<PrecF32>(GenParams, char *, hipStream_t);
+extern template hipError_t general_step<PrecF32U64>(GenParams, char *, hipStream_t);
+extern template hipError_t general_step<PrecF16>(GenParams, char *, hipStream_t);
+extern template hipError_t general_step<PrecBF16>(GenParams, char *, hipStream_t);
 
 }  // namespace lbm

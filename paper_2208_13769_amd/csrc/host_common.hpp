@@ -143,15 +143,6 @@ struct Kernels {
             step_w<B, false>(sp, nblocks, st);
         return hipGetLastError();
     }
-    static hipError_t step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st)
-    {
-        switch (block) {
-        case 64: return step_b<64>(sp, nblocks, pc, st);
-        case 128: return step_b<128>(sp, nblocks, pc, st);
-        case 512: return step_b<512>(sp, nblocks, pc, st);
-        default: return step_b<256>(sp, nblocks, pc, st);
-        }
-    }
     // The two pipelines of a two-step block share one compute unit's 160 KiB
     // of LDS: a 512-thread block fits with 32-bit values only, or with a
     // double displacement on plates periodic in y.
@@ -176,28 +167,6 @@ struct Kernels {
         }
         return hipGetLastError();
     }
-    // whether a two-step block of this many threads fits the LDS
-    static bool step2_ok(int block, bool walled)
-    {
-        switch (block) {
-        case 64: return walled ? step2_fits<64, true>() : step2_fits<64, false>();
-        case 128: return walled ? step2_fits<128, true>() : step2_fits<128, false>();
-        case 256: return walled ? step2_fits<256, true>() : step2_fits<256, false>();
-        case 512: return walled ? step2_fits<512, true>() : step2_fits<512, false>();
-        default: return false;
-        }
-    }
-    // two predictor-corrector steps per launch
-    static hipError_t step2(const StepParams &sp, int block, int nblocks, hipStream_t st)
-    {
-        switch (block) {
-        case 64: return step2_b<64>(sp, nblocks, st);
-        case 128: return step2_b<128>(sp, nblocks, st);
-        case 256: return step2_b<256>(sp, nblocks, st);
-        case 512: return step2_b<512>(sp, nblocks, st);
-        default: return hipErrorInvalidConfiguration;
-        }
-    }
     // blocks of one step-kernel instantiation that a compute unit holds at once
     template <typename K>
     static int per_cu(K kernel, int block)
@@ -220,31 +189,94 @@ struct Kernels {
             return walled ? per_cu(step_kernel<PR, B, true, true>, B) : per_cu(step_kernel<PR, B, true, false>, B);
         return walled ? per_cu(step_kernel<PR, B, false, true>, B) : per_cu(step_kernel<PR, B, false, false>, B);
     }
-    static int resident_per_cu(int block, int spl, bool pc, bool walled)
-    {
-        switch (block) {
-        case 64: return resident_b<64>(spl, pc, walled);
-        case 128: return resident_b<128>(spl, pc, walled);
-        case 256: return resident_b<256>(spl, pc, walled);
-        default: return resident_b<512>(spl, pc, walled);
-        }
-    }
-    static hipError_t init(const InitParams &ip, int nblocks, hipStream_t st)
-    {
-        hipLaunchKernelGGL((init_kernel<PR>), dim3(nblocks), dim3(256), 0, st, ip);
-        return hipGetLastError();
-    }
-    static hipError_t readout(const ReadParams &rp, int nblocks, hipStream_t st)
-    {
-        hipLaunchKernelGGL((readout_kernel<PR>), dim3(nblocks), dim3(256), 0, st, rp);
-        return hipGetLastError();
-    }
-    static hipError_t diag(const DiagParams &dp, int nblocks, hipStream_t st)
-    {
-        hipLaunchKernelGGL((diag_kernel<PR>), dim3(nblocks), dim3(256), 0, st, dp);
-        return hipGetLastError();
-    }
+
+    // The entry points below are defined out of the class (not inline), so
+    // that each precision is instantiated in one object only.
+    static hipError_t step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st);
+    // whether a two-step block of this many threads fits the LDS
+    static bool step2_ok(int block, bool walled);
+    // two predictor-corrector steps per launch
+    static hipError_t step2(const StepParams &sp, int block, int nblocks, hipStream_t st);
+    static int resident_per_cu(int block, int spl, bool pc, bool walled);
+    static hipError_t init(const InitParams &ip, int nblocks, hipStream_t st);
+    static hipError_t readout(const ReadParams &rp, int nblocks, hipStream_t st);
+    static hipError_t diag(const DiagParams &dp, int nblocks, hipStream_t st);
 };
+
+template <class PR>
+hipError_t Kernels<PR>::step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st)
+{
+    switch (block) {
+    case 64: return step_b<64>(sp, nblocks, pc, st);
+    case 128: return step_b<128>(sp, nblocks, pc, st);
+    case 512: return step_b<512>(sp, nblocks, pc, st);
+    default: return step_b<256>(sp, nblocks, pc, st);
+    }
+}
+
+template <class PR>
+bool Kernels<PR>::step2_ok(int block, bool walled)
+{
+    switch (block) {
+    case 64: return walled ? step2_fits<64, true>() : step2_fits<64, false>();
+    case 128: return walled ? step2_fits<128, true>() : step2_fits<128, false>();
+    case 256: return walled ? step2_fits<256, true>() : step2_fits<256, false>();
+    case 512: return walled ? step2_fits<512, true>() : step2_fits<512, false>();
+    default: return false;
+    }
+}
+
+template <class PR>
+hipError_t Kernels<PR>::step2(const StepParams &sp, int block, int nblocks, hipStream_t st)
+{
+    switch (block) {
+    case 64: return step2_b<64>(sp, nblocks, st);
+    case 128: return step2_b<128>(sp, nblocks, st);
+    case 256: return step2_b<256>(sp, nblocks, st);
+    case 512: return step2_b<512>(sp, nblocks, st);
+    default: return hipErrorInvalidConfiguration;
+    }
+}
+
+template <class PR>
+int Kernels<PR>::resident_per_cu(int block, int spl, bool pc, bool walled)
+{
+    switch (block) {
+    case 64: return resident_b<64>(spl, pc, walled);
+    case 128: return resident_b<128>(spl, pc, walled);
+    case 256: return resident_b<256>(spl, pc, walled);
+    default: return resident_b<512>(spl, pc, walled);
+    }
+}
+
+template <class PR>
+hipError_t Kernels<PR>::init(const InitParams &ip, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((init_kernel<PR>), dim3(nblocks), dim3(256), 0, st, ip);
+    return hipGetLastError();
+}
+
+template <class PR>
+hipError_t Kernels<PR>::readout(const ReadParams &rp, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((readout_kernel<PR>), dim3(nblocks), dim3(256), 0, st, rp);
+    return hipGetLastError();
+}
+
+template <class PR>
+hipError_t Kernels<PR>::diag(const DiagParams &dp, int nblocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((diag_kernel<PR>), dim3(nblocks), dim3(256), 0, st, dp);
+    return hipGetLastError();
+}
+
+// Each precision's kernels and launch helpers are compiled in an object of
+// their own (instantiate.hip), so the precisions build in parallel.
+extern template struct Kernels<PrecF64>;
+extern template struct Kernels<PrecF32>;
+extern template struct Kernels<PrecF32U64>;
+extern template struct Kernels<PrecF16>;
+extern template struct Kernels<PrecBF16>;
 
 #define LBM_DISPATCH(prec, expr_with_PR)                                  \
     [&]() -> hipError_t {                                                 \
@@ -276,6 +308,8 @@ struct PlateIO {
     double val_lo[2], val_hi[2];
     int bc_left, bc_right;      // x edges (periodic unless set)
     double val_left[2], val_right[2];
+    // momentum walls: displacement uwb + j* n at step n, lattice units
+    double uwb_lo[2], uwb_hi[2], uwb_left[2], uwb_right[2];
     const unsigned char *mask;  // device [ny][nx] material mask, or nullptr
     void *f, *u, *j;            // current state copy
     void *f_other;              // the other copy (staging for start-up)
@@ -288,7 +322,7 @@ struct PlateIO {
 };
 
 // Geometry/material view used by the start-up, read-out and diagnostics
-// kernels at step t_steps (momentum walls have moved by j* t).
+// kernels at step t_steps (a momentum wall is at uwb + j* t).
 inline FieldParams field_params(const PlateIO &io, double t_steps)
 {
     const Units &U = io.U;
@@ -300,12 +334,14 @@ inline FieldParams field_params(const PlateIO &io, double t_steps)
     fp.bc_hi = io.bc_hi;
     fp.bc_left = io.bc_left;
     fp.bc_right = io.bc_right;
-    auto uw = [&](int bc, double v) { return bc == LBM_BC_DIRICHLET_J ? v / U.momentum() * t_steps : 0.0; };
+    auto uw = [&](int bc, double v, double base) {
+        return bc == LBM_BC_DIRICHLET_J ? base + v / U.momentum() * t_steps : 0.0;
+    };
     for (int a = 0; a < 2; ++a) {
-        fp.uw_lo[a] = uw(io.bc_lo, io.val_lo[a]);
-        fp.uw_hi[a] = uw(io.bc_hi, io.val_hi[a]);
-        fp.uw_left[a] = uw(io.bc_left, io.val_left[a]);
-        fp.uw_right[a] = uw(io.bc_right, io.val_right[a]);
+        fp.uw_lo[a] = uw(io.bc_lo, io.val_lo[a], io.uwb_lo[a]);
+        fp.uw_hi[a] = uw(io.bc_hi, io.val_hi[a], io.uwb_hi[a]);
+        fp.uw_left[a] = uw(io.bc_left, io.val_left[a], io.uwb_left[a]);
+        fp.uw_right[a] = uw(io.bc_right, io.val_right[a], io.uwb_right[a]);
     }
     fp.lam = U.lam / U.stress();
     fp.mu = U.mu / U.stress();
@@ -313,10 +349,62 @@ inline FieldParams field_params(const PlateIO &io, double t_steps)
     return fp;
 }
 
+// Largest population magnitude (lattice units) that a plate's loads drive,
+// with a margin: a traction T* enters the wall populations and the stresses
+// near the wall through the boundary Poisson stress (about |T*|); a wall
+// momentum j* through 6 w_i e_i . j* and the stress of the wave it launches
+// (about |j*|); a body force builds stresses of about |rho0 b| times the
+// plate's extent. (A body force on a plate without walls accelerates it
+// without bound; no scale covers that.) val: j* or T* of the edges in
+// physical units, body: b per unit mass.
+inline double load_population_bound(const Units &U, int nx, int ny, const int bc[4], const double val[4][2],
+                                    const double body[2])
+{
+    double m = 0.0;
+    for (int e = 0; e < 4; ++e)
+        for (int a = 0; a < 2; ++a) {
+            if (bc[e] == LBM_BC_NEUMANN_T) m = std::max(m, 2.0 * std::fabs(val[e][a]) / U.stress());
+            if (bc[e] == LBM_BC_DIRICHLET_J) m = std::max(m, 2.0 * std::fabs(val[e][a]) / U.momentum());
+        }
+    const double bl = std::hypot(body[0], body[1]) * U.dt() / U.c();  // rho0 b per step, lattice units
+    return std::max(m, 2.0 * bl * std::max(nx, ny));
+}
+
+// Power-of-two scale of 16-bit populations that puts a largest magnitude mx
+// near 2^12 (binary16 tops out at 65504); the exponent stays within +-60 so
+// the scale and its inverse are normal floats. 1 for mx = 0.
+inline double population_scale(double mx)
+{
+    if (!(mx > 0.0)) return 1.0;
+    return std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(std::log2(4096.0 / mx)))));
+}
+
+// Largest scaled magnitude a 16-bit plate may reach before its scale is
+// lowered: 16 times the start target, 4 times below the binary16 maximum.
+constexpr double kScaledHeadroom = 16384.0;
+
+// Lower a 16-bit plate's population scale to new_scale (a power of two below
+// the current one) by rescaling the stored populations f of its current
+// state copy on the stream. Returns the error of the launch.
+inline hipError_t plate_rescale(lbm_precision prec, void *f, size_t sites, double factor, hipStream_t st)
+{
+    const long long n = 9 * (long long)sites;
+    const int nb = (int)((n + 255) / 256);
+    if (prec == LBM_FP16_STORE)
+        hipLaunchKernelGGL(rescale_kernel<__half>, dim3(nb), dim3(256), 0, st, static_cast<__half *>(f), n,
+                           (float)factor);
+    else if (prec == LBM_BF16_STORE)
+        hipLaunchKernelGGL(rescale_kernel<__hip_bfloat16>, dim3(nb), dim3(256), 0, st,
+                           static_cast<__hip_bfloat16 *>(f), n, (float)factor);
+    return hipGetLastError();
+}
+
 // f = f^eq of the start fields (u0, v0 host arrays). For 16-bit storage the
-// population scale is chosen here (returned in *scale); *nonfinite is set if
-// the start populations are not finite. Synchronises.
-inline hipError_t plate_start(const PlateIO &io, const double *u0, const double *v0, double *scale, bool *nonfinite)
+// population scale is chosen here (returned in *scale) from the largest start
+// population and load_bound (load_population_bound of the plate's loads);
+// *nonfinite is set if the start populations are not finite. Synchronises.
+inline hipError_t plate_start(const PlateIO &io, const double *u0, const double *v0, double load_bound,
+                              double *scale, bool *nonfinite)
 {
     *nonfinite = false;
     const size_t n = (size_t)io.nx * io.ny;
@@ -359,8 +447,7 @@ inline hipError_t plate_start(const PlateIO &io, const double *u0, const double 
             *nonfinite = true;
             return hipSuccess;
         }
-        // (exponent kept within +-60 so the scale and its inverse stay normal floats)
-        if (mx > 0.0) *scale = std::ldexp(1.0, std::max(-60, std::min(60, (int)std::floor(std::log2(4096.0 / mx)))));
+        *scale = population_scale(std::max(mx, load_bound));
     }
     ip.mode = 1;
     ip.f_scale = *scale;

@@ -473,7 +473,12 @@ lbm_status lbm_batch_add(lbm_batch *b, const lbm_plate_desc *d, const double *u0
     double scale = 1.0;
     bool nonfinite = false;
     hipError_t e = hipMemsetAsync(b->d_flags() + s, 0, sizeof(unsigned), b->stream);
-    if (!e) e = plate_start(b->io(s), u0, v0, &scale, &nonfinite);
+    if (!e) {
+        const int bc4[4] = {LBM_BC_PERIODIC, LBM_BC_PERIODIC, sl.bc_lo, sl.bc_hi};
+        const double val4[4][2] = {{0, 0}, {0, 0}, {sl.val_lo[0], sl.val_lo[1]}, {sl.val_hi[0], sl.val_hi[1]}};
+        e = plate_start(b->io(s), u0, v0, load_population_bound(sl.U, sl.nx, sl.ny, bc4, val4, sl.body), &scale,
+                        &nonfinite);
+    }
     if (e || nonfinite) {
         arena_free(b, off, L.bytes);
         if (e) return bhip(b, e, "start-up");

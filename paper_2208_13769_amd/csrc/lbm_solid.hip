@@ -77,6 +77,10 @@ struct lbm_solver {
     double body[2] = {0, 0};
     int bc[4] = {LBM_BC_PERIODIC, LBM_BC_PERIODIC, LBM_BC_PERIODIC, LBM_BC_PERIODIC};
     double bcval[4][2] = {};
+    // Momentum walls move with velocity j* / rho0: the wall of edge e is at
+    // uwb[e] + j*_L n at step n (lattice units). Changing j* at step n moves
+    // uwb so that the displacement stays continuous.
+    double uwb[4][2] = {};
     double f_scale = 1.0;
     int64_t steps = 0;
     Shape shape{};
@@ -105,6 +109,37 @@ struct lbm_solver {
     unsigned *flag() const { return reinterpret_cast<unsigned *>(ws + L.small); }
     Units units() const { return Units{dx, rho0, lam, mu}; }
 
+    // lattice velocity of edge e's wall (zero unless a momentum wall)
+    double wall_speed(int e, int a) const
+    {
+        return bc[e] == LBM_BC_DIRICHLET_J && material ? bcval[e][a] / units().momentum() : 0.0;
+    }
+    double load_bound() const { return load_population_bound(units(), nx, ny, bc, bcval, body); }
+    // 16-bit storage: lower the population scale (rescaling the stored
+    // populations on the stream) when the loads now set could drive the
+    // populations beyond the headroom of the current scale
+    hipError_t refit_scale()
+    {
+        if (!fields || (prec != LBM_FP16_STORE && prec != LBM_BF16_STORE)) return hipSuccess;
+        const double need = load_bound();
+        if (!(need * f_scale > kScaledHeadroom)) return hipSuccess;
+        const double ns = population_scale(need);
+        const hipError_t e = plate_rescale(prec, fptr(cur), (size_t)nx * ny, ns / f_scale, stream);
+        if (e == hipSuccess) f_scale = ns;
+        return e;
+    }
+    // set edge e's rule and value, keeping its wall displacement continuous
+    // at the current step
+    void set_edge(int e, int kind, double v0, double v1)
+    {
+        const double n = (double)steps;
+        const double now[2] = {uwb[e][0] + wall_speed(e, 0) * n, uwb[e][1] + wall_speed(e, 1) * n};
+        bc[e] = kind;
+        bcval[e][0] = v0;
+        bcval[e][1] = v1;
+        for (int a = 0; a < 2; ++a) uwb[e][a] = now[a] - wall_speed(e, a) * n;
+    }
+
     PlateIO io() const
     {
         PlateIO p{};
@@ -121,6 +156,10 @@ struct lbm_solver {
             p.val_hi[a] = bcval[LBM_EDGE_YMAX][a];
             p.val_left[a] = bcval[LBM_EDGE_XMIN][a];
             p.val_right[a] = bcval[LBM_EDGE_XMAX][a];
+            p.uwb_lo[a] = uwb[LBM_EDGE_YMIN][a];
+            p.uwb_hi[a] = uwb[LBM_EDGE_YMAX][a];
+            p.uwb_left[a] = uwb[LBM_EDGE_XMIN][a];
+            p.uwb_right[a] = uwb[LBM_EDGE_XMAX][a];
         }
         p.f = fptr(cur);
         p.u = uptr(cur);
@@ -305,6 +344,7 @@ lbm_status lbm_set_body_force(lbm_solver *h, const double b[2])
     if (!std::isfinite(b[0]) || !std::isfinite(b[1])) return fail(h, LBM_ERR_ARG, "body force not finite");
     h->body[0] = b[0];
     h->body[1] = b[1];
+    HIP_TRY(h, h->refit_scale());
     return LBM_OK;
 }
 
@@ -325,21 +365,18 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
         return fail(h, LBM_ERR_STATE, "a mask was checked against the edges: make edges periodic or not before it");
     if (bc == LBM_BC_PERIODIC && h->bc[other] != LBM_BC_PERIODIC) {
         // periodic edges come in pairs
-        h->bc[other] = LBM_BC_PERIODIC;
-        h->bcval[other][0] = h->bcval[other][1] = 0.0;
+        h->set_edge(other, LBM_BC_PERIODIC, 0.0, 0.0);
     }
     if (bc != LBM_BC_PERIODIC && h->bc[other] == LBM_BC_PERIODIC) {
         // the opposite edge stops being periodic: it becomes a wall at rest until set
-        h->bc[other] = LBM_BC_DIRICHLET_J;
-        h->bcval[other][0] = h->bcval[other][1] = 0.0;
+        h->set_edge(other, LBM_BC_DIRICHLET_J, 0.0, 0.0);
     }
     const bool was_periodic = h->bc[e] == LBM_BC_PERIODIC;
-    h->bc[e] = bc;
     // the edge lists depend only on which edges are periodic (and the mask)
     if (was_periodic != (bc == LBM_BC_PERIODIC)) h->edges_dirty = true;
-    h->bcval[e][0] = bc == LBM_BC_PERIODIC ? 0.0 : value[0];
-    h->bcval[e][1] = bc == LBM_BC_PERIODIC ? 0.0 : value[1];
+    h->set_edge(e, bc, bc == LBM_BC_PERIODIC ? 0.0 : value[0], bc == LBM_BC_PERIODIC ? 0.0 : value[1]);
     refit_two_step(h);
+    HIP_TRY(h, h->refit_scale());
     return LBM_OK;
 }
 
@@ -404,14 +441,14 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
         }
         return solid[(size_t)y * nx + x] == 0;
     };
-    bool any_material = false;
+    bool any_material = false, thin_hole = false;
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (hole(x, y)) {
                 if (((y == 0 || y == ny - 1) && !pery) || ((x == 0 || x == nx - 1) && !perx))
                     return fail(h, LBM_ERR_ARG, "a hole touches a wall edge");
                 if ((!hole(x - 1, y) && !hole(x + 1, y)) || (!hole(x, y - 1) && !hole(x, y + 1)))
-                    return fail(h, LBM_ERR_ARG, "hole one node wide");
+                    thin_hole = true;
                 continue;
             }
             any_material = true;
@@ -419,6 +456,10 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
                 return fail(h, LBM_ERR_ARG, "material one node thick between holes");
         }
     if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
+    // The method allows a hole one node wide; the stress pass keeps the K a
+    // border node needs in its hole neighbour's slot, which the two material
+    // nodes on either side of such a hole would both claim.
+    if (thin_hole) return fail(h, LBM_ERR_UNSUPPORTED, "a hole one node wide (the library needs holes two nodes wide)");
     h->mask_host.assign(solid, solid + (size_t)nx * ny);
     for (auto &m : h->mask_host) m = m ? 1 : 0;
     // The device copy also marks interior nodes in bit 1: the node and its
@@ -493,9 +534,10 @@ lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0)
     if (!u0 || !v0) return fail(h, LBM_ERR_ARG, "u0 or v0 is NULL");
     if (!h->material) return fail(h, LBM_ERR_STATE, "set the material before the fields");
     h->cur = 0;
+    for (auto &w : h->uwb) w[0] = w[1] = 0.0;  // every wall starts undisplaced
     double scale = 1.0;
     bool nonfinite = false;
-    const hipError_t e = plate_start(h->io(), u0, v0, &scale, &nonfinite);
+    const hipError_t e = plate_start(h->io(), u0, v0, h->load_bound(), &scale, &nonfinite);
     if (e != hipSuccess) return hip_fail(h, e, "start-up");
     if (nonfinite) return fail(h, LBM_ERR_ARG, "initial fields not finite");
     h->f_scale = scale;
@@ -577,6 +619,10 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
     sp.plane = (long long)h->nx * h->ny;
     fill_physics(sp, h->units(), h->tau, h->body, h->bc[LBM_EDGE_YMIN], h->bcval[LBM_EDGE_YMIN],
                  h->bc[LBM_EDGE_YMAX], h->bcval[LBM_EDGE_YMAX]);
+    for (int a = 0; a < 2; ++a) {
+        sp.uwb_lo[a] = h->uwb[LBM_EDGE_YMIN][a];
+        sp.uwb_hi[a] = h->uwb[LBM_EDGE_YMAX][a];
+    }
     sp.f_scale = h->f_scale;
     sp.f_inv_scale = 1.0 / h->f_scale;
     sp.strip_w = h->shape.strip_w;
@@ -601,9 +647,11 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         const Units U = h->units();
         for (int e = 0; e < 4; ++e) {
             gp.bc[e] = h->bc[e];
-            for (int a = 0; a < 2; ++a)  // j* -> lattice momentum, T* -> lattice stress
+            for (int a = 0; a < 2; ++a) {  // j* -> lattice momentum, T* -> lattice stress
                 gp.val[e][a] = h->bc[e] == LBM_BC_DIRICHLET_J ? h->bcval[e][a] / U.momentum()
                                                               : h->bcval[e][a] / U.stress();
+                gp.uwb[e][a] = h->uwb[e][a];
+            }
         }
         gp.f_scale = sp.f_scale;
         gp.f_inv_scale = sp.f_inv_scale;

@@ -32,8 +32,9 @@
 //
 // Walls (y edges only) lie half a spacing outside the node rows 0 and ny-1.
 // Ghost displacement rows for the finite differences: momentum wall -- the
-// quadratic through the wall displacement u_w = j* t / rho0 and the two
-// nearest rows; traction wall -- the nearest row repeated. Rows above the
+// quadratic through the wall displacement u_w and the two nearest rows (the
+// wall moves with j* / rho0, so u_w is the integral of the values of j* in
+// effect); traction wall -- the nearest row repeated. Rows above the
 // top wall follow from rows already walked; the ghost row below the bottom
 // wall is folded into the source of row 0 when that row is reached.
 #pragma once
@@ -58,6 +59,9 @@ struct StepParams {
     double bx, by;          // rho0 b in lattice units (source per step)
     int bc_lo, bc_hi;       // rule of the y edges (BC_*)
     double val_lo[2], val_hi[2];  // j* or T* in lattice units
+    // momentum walls: displacement uwb + j* n at step n (lattice units); uwb
+    // carries the displacement accumulated under earlier values of j*
+    double uwb_lo[2], uwb_hi[2];
     double f_scale, f_inv_scale;  // 16-bit population scaling (1 otherwise)
     int strip_w, n_strips, n_segs;
     int halo_a;             // threads left of the first output column (>= the stencil halo)
@@ -322,6 +326,7 @@ struct Pipe {
     const int bc_lo, bc_hi;
     const TC omega, lam, mu, bx, by;
     const double *val_lo, *val_hi;
+    const double *uwb_lo, *uwb_hi;
     const double tn;  // step index n of the input state
 
     // rings (row k = k rows before the stage's current row)
@@ -345,7 +350,8 @@ struct Pipe {
                                     bool out_col_)
         : L(lds), t(t_), tl(t_ > 0 ? t_ - 1 : 0), tr(t_ < BLOCK - 1 ? t_ + 1 : BLOCK - 1), ny(p.ny), y0(y0_),
           y1(y1_), out_col(out_col_), bc_lo(p.bc_lo), bc_hi(p.bc_hi), omega(TC(p.omega)), lam(TC(p.lam)),
-          mu(TC(p.mu)), bx(TC(p.bx)), by(TC(p.by)), val_lo(p.val_lo), val_hi(p.val_hi), tn((double)step),
+          mu(TC(p.mu)), bx(TC(p.bx)), by(TC(p.by)), val_lo(p.val_lo), val_hi(p.val_hi), uwb_lo(p.uwb_lo),
+          uwb_hi(p.uwb_hi), tn((double)step),
           bad(false)
     {
         uR.zero();
@@ -366,9 +372,9 @@ struct Pipe {
 
     __device__ __forceinline__ bool is_node(int r) const { return !WALLED || (r >= 0 && r < ny); }
 
-    // wall displacement u_w = j* t (lattice units) at t = n + dn
-    __device__ __forceinline__ TU uw_lo(int a, int dn) const { return TU(val_lo[a] * (tn + dn)); }
-    __device__ __forceinline__ TU uw_hi(int a, int dn) const { return TU(val_hi[a] * (tn + dn)); }
+    // momentum-wall displacement (lattice units) at step n + dn
+    __device__ __forceinline__ TU uw_lo(int a, int dn) const { return TU(uwb_lo[a] + val_lo[a] * (tn + dn)); }
+    __device__ __forceinline__ TU uw_hi(int a, int dn) const { return TU(uwb_hi[a] + val_hi[a] * (tn + dn)); }
 
     // ghost rows above the top wall from the two rows below it
     __device__ __forceinline__ TU ghost_hi(int which, TU a, TU b, TU uw) const

@@ -77,13 +77,19 @@ def set_arrivals(reqs, rate: float, seed: int):
         t += rng.exponential(1.0 / rate)
 
 
-def _summary(name, reqs, finish):
-    lat = np.array([finish[r.rid] - r.arrival for r in reqs])
-    span = max(finish.values()) - min(r.arrival for r in reqs)
-    ups = sum(r.updates for r in reqs)
-    return {"server": name, "requests": len(reqs), "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-            "makespan_s": span, "MLUPS": ups / span / 1e6}
+def _summary(name, reqs, finish, rejected=()):
+    """Latency percentiles and MLUPS over the requests that were served;
+    rejected requests (too large for the server) are counted apart."""
+    done = [r for r in reqs if r.rid in finish]
+    out = {"server": name, "requests": len(reqs), "rejected": len(rejected)}
+    if not done:
+        return out
+    lat = np.array([finish[r.rid] - r.arrival for r in done])
+    span = max(finish.values()) - min(r.arrival for r in done)
+    ups = sum(r.updates for r in done)
+    out.update({"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "mean_s": float(lat.mean()), "makespan_s": span, "MLUPS": ups / span / 1e6})
+    return out
 
 
 def _progress(name, done, total, every):
@@ -133,8 +139,9 @@ class BatchServer:
     """Continuous batching: resident plates advanced together in chunks."""
 
     def __init__(self, arena_bytes: int, precision: str = "fp16", chunk: int = 200, max_plates: int = 512,
-                 progress: int = 0):
-        self.batch = Batch(max_plates=max_plates, arena_bytes=arena_bytes, precision=precision, walled=False)
+                 progress: int = 0, batch=None):
+        self.batch = batch if batch is not None else Batch(max_plates=max_plates, arena_bytes=arena_bytes,
+                                                           precision=precision, walled=False)
         self.precision = precision
         self.chunk = chunk
         self.progress = progress
@@ -143,13 +150,11 @@ class BatchServer:
         self.batch.close()
 
     def run(self, reqs, keep=None):
-        import torch
-
         b = self.batch
         pending = deque(sorted(reqs, key=lambda q: q.arrival))
         waiting = deque()
         live = {}
-        finish, results = {}, {}
+        finish, results, rejected = {}, {}, []
         max_live = 0
         start = time.perf_counter()
         while pending or waiting or live:
@@ -158,8 +163,16 @@ class BatchServer:
                 waiting.append(pending.popleft())
             while waiting:
                 r = waiting[0]
+                if not b.fits_empty(r.n, r.n):
+                    # larger than the whole batch: it would wait forever and
+                    # hold up every request behind it
+                    rejected.append(waiting.popleft().rid)
+                    continue
                 slot = b.add(PlateSpec(nx=r.n, ny=r.n, lam=r.lam, mu=r.mu, tau_over_dt=r.tau), r.u0, r.v0, r.steps)
                 if slot is None:
+                    if not live:  # no room even in an empty batch (e.g. no free slot)
+                        rejected.append(waiting.popleft().rid)
+                        continue
                     break  # no room: wait for plates to finish
                 waiting.popleft()
                 live[slot] = r
@@ -169,7 +182,7 @@ class BatchServer:
                     _wait_until(start, pending[0].arrival)
                 continue
             b.step(self.chunk)
-            torch.cuda.current_stream(b.device).synchronize()
+            b.synchronize()
             for slot, r in list(live.items()):
                 done, left, bad = b.query(slot)
                 if left == 0 or bad:
@@ -180,7 +193,8 @@ class BatchServer:
                     b.retire(slot)
                     del live[slot]
                     _progress(f"batched-{self.precision}", len(finish), len(reqs), self.progress)
-        summ = _summary(f"batched-{self.precision}", reqs, finish)
+        summ = _summary(f"batched-{self.precision}", reqs, finish, rejected)
+        summ["rejected_ids"] = rejected
         summ["max_resident"] = max_live
         summ["chunk"] = self.chunk
         return summ, finish, results

@@ -58,3 +58,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_roofline_counts_updates_per_launch():
+    # a two-step launch of 2^24 sites in 536.8 us at 104 B per update (FP32):
+    # 104 * 2 * 2^24 B / 536.8 us = 6.50 TB/s, 0.81 of the 8 TB/s peak
+    sites = 1 << 24
+    r = bench.step_roofline("fp32", sites, 2, 0.5368 / 2, None)
+    assert r["updates_per_launch"] == 2 * sites
+    assert r["algorithmic_bytes_per_launch"] == 104 * 2 * sites
+    assert abs(r["achieved"] - 104 * 2 * sites / 536.8e-6 / 1e9) < 0.1
+    assert abs(r["frac"] - 0.8126) < 1e-3
+    # the launch's own state traffic is half of that
+    assert abs(r["per_launch_state_GBps"] - r["achieved"] / 2) < 0.1
+    # one step per launch: one update per site
+    r1 = bench.step_roofline("fp16", sites, 1, 0.2, None)
+    assert r1["updates_per_launch"] == sites and r1["bytes_per_update"] == 84

@@ -181,11 +181,16 @@ def test_mask_errors(gpu):
         s.set_mask(bad)
     assert e.value.status == lbm.LBM_ERR_ARG
     thin = np.ones((n, n), np.uint8)
-    thin[4:10, 4] = 0
-    thin[4:10, 6] = 0
+    thin[4:10, 3:5] = 0
+    thin[4:10, 6:8] = 0  # column 5 is material one node thick
     with pytest.raises(lbm.LbmError) as e:
         s.set_mask(thin)
     assert e.value.status == lbm.LBM_ERR_ARG
+    narrow = np.ones((n, n), np.uint8)
+    narrow[4:10, 4] = 0  # a hole one node wide: valid, not implemented
+    with pytest.raises(lbm.LbmError) as e:
+        s.set_mask(narrow)
+    assert e.value.status == lbm.LBM_ERR_UNSUPPORTED
     s.set_mask(m)
     with pytest.raises(lbm.LbmError) as e:  # periodicity is fixed once a mask is set
         s.set_boundary(lbm.LBM_EDGE_XMIN, lbm.LBM_BC_NEUMANN_T, (0.0, 0.0))

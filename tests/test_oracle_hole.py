@@ -1,8 +1,9 @@
 """Pins of the oracle's holes (Sec. 7.2; reading Q23), against results that do
 not use the hole code:
 
-- A hole that is a band of whole rows (columns) in a plate periodic in y (x)
-  leaves a strip bounded by two traction-free walls: the result must equal
+- A hole that is a band of whole rows (columns) in a plate periodic in y (x),
+  one node wide or more, leaves a strip bounded by two traction-free walls:
+  the result must equal
   the strip run with traction walls on its edges (Q11), which the resonance
   pins already tie down. Bands of rows and columns together leave a block
   with four walls and four corners (Q20).
@@ -36,9 +37,10 @@ def _pad(a, shape):
     return out
 
 
+@pytest.mark.parametrize("k", [1, 3])
 @pytest.mark.parametrize("scheme", [O.PC, O.EXPLICIT])
-def test_row_band_equals_traction_walls(scheme):
-    nx, ny, k, n = 12, 15, 3, 80
+def test_row_band_equals_traction_walls(scheme, k):
+    nx, ny, n = 12, 15, 80
     rng = np.random.Generator(np.random.PCG64(21))
     u0 = 0.01 * rng.standard_normal((2, ny - k, nx))
     v0 = 0.01 * rng.standard_normal((2, ny - k, nx))
@@ -52,8 +54,9 @@ def test_row_band_equals_traction_walls(scheme):
     assert np.abs(uh[:, ny - k:]).max() == 0.0 and np.abs(Ph[:, :, ny - k:]).max() == 0.0
 
 
-def test_column_band_equals_traction_walls():
-    nx, ny, k, n = 15, 12, 2, 80
+@pytest.mark.parametrize("k", [1, 2])
+def test_column_band_equals_traction_walls(k):
+    nx, ny, n = 15, 12, 80
     rng = np.random.Generator(np.random.PCG64(22))
     u0 = 0.01 * rng.standard_normal((2, ny, nx - k))
     v0 = 0.01 * rng.standard_normal((2, ny, nx - k))
