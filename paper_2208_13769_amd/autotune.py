@@ -43,11 +43,18 @@ def _store_cache(cache: dict) -> None:
         pass
 
 
+def halo(precision: str, scheme: str, spl: int) -> int:
+    """Halo columns of a launch: the stencil reach of its steps, one more per
+    step with 16-bit (deviation) storage, whose store needs the gradient of
+    the new displacement."""
+    return (HALO[scheme] + (1 if precision in ("fp16", "bf16") else 0)) * spl
+
+
 def strips(nx: int, block: int, precision: str, scheme: str, spl: int) -> int:
     """Column strips of a launch shape (the library's own rule: strips as wide
     as the block minus both halos, rounded down to a multiple of 32 columns)."""
-    halo = HALO[scheme] * spl
-    wmax = block - 2 * halo
+    halo_ = halo(precision, scheme, spl)
+    wmax = block - 2 * halo_
     if nx <= wmax:
         return 1
     align = 32
@@ -69,9 +76,9 @@ def candidates(solver, nx: int, ny: int, precision: str, scheme: str):
             resident = solver.resident_blocks(block, spl)
             if resident <= 0:
                 continue
-            halo = HALO[scheme] * spl
+            h = halo(precision, scheme, spl)
             n_str = strips(nx, block, precision, scheme, spl)
-            if block > 64 and n_str == 1 and nx <= (block // 2) - 2 * halo:
+            if block > 64 and n_str == 1 and nx <= (block // 2) - 2 * h:
                 continue  # a narrower block already covers the width
             seen = set()
             for waves in (0.5, 1, 2, 3, 4):
@@ -113,7 +120,7 @@ def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
 def best_tiling(solver, nx: int, ny: int, precision: str, scheme: str):
     import torch
 
-    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v4"
+    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v5"
     cache = _load_cache()
     if key in cache:
         return tuple(cache[key]["tiling"])

@@ -104,13 +104,16 @@ struct InitParams {
 };
 
 // f = f^eq(r0, j0, Pbar(H(u0))) with r0 = -div u0, j0 = rho0 v0
-// (Algorithm 1, initialisation; eqs. (15), (18), (20)), lattice units.
+// (Algorithm 1, initialisation; eqs. (15), (18), (20)), lattice units. With
+// deviation storage the stored value is f minus ref_eq of the stored state,
+// which the start state equals up to rounding (the same moments).
 template <class PR>
 __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
     using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
     __shared__ double red[256];
     const FieldParams &fp = p.fp;
     const size_t pl = (size_t)fp.plane;
@@ -147,11 +150,18 @@ __global__ void __launch_bounds__(256) init_kernel(const InitParams p)
         const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
         const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
         const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        TC fr[9] = {};
+        if constexpr (FStore<TF>::kDeviation) {
+            if (!hole) {
+                const TC Hc[4] = {TC(H[0]), TC(H[1]), TC(H[2]), TC(H[3])};
+                ref_eq(Hc, TC(TJ(jx)), TC(TJ(jy)), fr);
+            }
+        }
         for (int i = 0; i < 9; ++i) {
             const double fi = hole ? 0.0 : w[i] * (r + 3.0 * (ex[i] * jx + ey[i] * jy) + 4.5 * q[i]);
             m = fmax(m, fabs(fi));
-            if (p.mode == 1) FStore<TF>::store(static_cast<TF *>(p.f), i * pl + s, (typename PR::TC)fi,
-                                               (typename PR::TC)p.f_scale);
+            if (p.mode == 1)
+                FStore<TF>::store(static_cast<TF *>(p.f), i * pl + s, TC(fi - (double)fr[i]), TC(p.f_scale));
         }
         if (p.mode == 1) {
             TU *u = static_cast<TU *>(p.u);
@@ -297,6 +307,15 @@ __global__ void __launch_bounds__(256) diag_kernel(const DiagParams p)
         grad_at(u, fp, x, y, H);
         double r = 0.0;
         for (int i = 0; i < 9; ++i) r += (double)FStore<TF>::load(f, i * pl + s, (typename PR::TC)p.f_inv_scale);
+        if constexpr (FStore<TF>::kDeviation) {
+            // the stored deviations plus the reference equilibrium's zeroth
+            // moment, sum_i ref_eq_i = -tr H
+            using TC = typename PR::TC;
+            const TC Hc[4] = {TC(H[0]), TC(H[1]), TC(H[2]), TC(H[3])};
+            TC fr[9];
+            ref_eq(Hc, TC(j[s]), TC(j[pl + s]), fr);
+            for (int i = 0; i < 9; ++i) r += (double)fr[i];
+        }
         const double F11 = 1.0 + H[0], F12 = H[1], F21 = H[2], F22 = 1.0 + H[3];
         const double J = F11 * F22 - F12 * F21;
         const double E11 = 0.5 * (F11 * F11 + F21 * F21 - 1.0);

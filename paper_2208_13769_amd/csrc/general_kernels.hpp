@@ -17,6 +17,10 @@
 //      predictor u^p (stream_pass);
 //   4. K of u^p at t + dt (stress_pass again), then S^p, j_{n+1} and
 //      u_{n+1} (update_pass). The explicit scheme stops after pass 3.
+// With deviation storage (16-bit populations) pass 3 keeps the new
+// populations in scratch and a last pass (store_pass) stores their
+// deviation from the reference equilibrium of the new state; the passes that
+// load populations add the reference of the input state back.
 // In the extrapolation variant (end of Sec. 5) u^p takes 2 j_n - j_{n-1}
 // for j at t + dt; j_{n-1} is still in the output buffer of j, which pass 3
 // reads at its own site before pass 4b overwrites it.
@@ -60,6 +64,7 @@ struct GenParams {
     void *S;     // scratch [2][ny][nx] TC: source S_n
     void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
     void *up;    // scratch [2][ny][nx] TU: predictor displacement
+    void *fnew;  // scratch [9][ny][nx] TC: new populations (deviation storage only)
     unsigned *flag;
     const unsigned char *mask;  // [ny][nx] bit 0: material (1) or hole (0); bit 1: interior; nullptr: no holes
     const int *edge_k;          // ring indices (y + 1)(nx + 2) + x + 1 of the stress pass's edge nodes
@@ -162,6 +167,29 @@ __device__ __forceinline__ void gen_grad(const GenParams &p, const typename PR::
         const TU yp = hyp ? c : gen_u(u, p, a, x, y + 1, t), ym = hym ? c : gen_u(u, p, a, x, y - 1, t);
         H[2 * a + 0] = TC((xp - xm) * TU(0.5));
         H[2 * a + 1] = TC((yp - ym) * TU(0.5));
+    }
+}
+
+// The populations of state n at node (x, y), site s: the stored values or,
+// with deviation storage, the stored deviations plus the reference
+// equilibrium of the stored state (gradient at step n, stored momentum).
+template <class PR>
+__device__ __forceinline__ void gen_load_f(const GenParams &p, int x, int y, size_t s, typename PR::TC f[9])
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const size_t pl = (size_t)p.plane;
+    const TF *fin = static_cast<const TF *>(p.f_in);
+    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+    if constexpr (FS::kDeviation) {
+        TC H[4], fr[9];
+        gen_grad<PR>(p, static_cast<const TU *>(p.u_in), x, y, (double)p.step, H);
+        const TJ *jin = static_cast<const TJ *>(p.j_in);
+        ref_eq(H, TC(jin[s]), TC(jin[pl + s]), fr);
+        for (int i = 0; i < 9; ++i) f[i] = fr[i] + f[i];
     }
 }
 
@@ -288,21 +316,18 @@ __device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, typ
 template <class PR>
 __global__ void __launch_bounds__(256) collide_pass(const GenParams p)
 {
-    using TF = typename PR::TF;
     using TJ = typename PR::TJ;
     using TC = typename PR::TC;
-    using FS = FStore<TF>;
     const int n = p.nx * p.ny;
     const int s = blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     const int y = s / p.nx, x = s - y * p.nx;
     if (g_hole(p, x, y)) return;
     const size_t pl = (size_t)p.plane;
-    const TF *fin = static_cast<const TF *>(p.f_in);
     const TJ *jin = static_cast<const TJ *>(p.j_in);
     TC S[2], f[9], fc[9], r, pxx;
     gen_source<PR>(p, x, y, S);
-    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+    gen_load_f<PR>(p, x, y, (size_t)s, f);
     collide(f, TC(jin[s]), TC(jin[pl + s]), S[0], S[1], TC(p.omega), fc, r, pxx);
     TC *fcol = static_cast<TC *>(p.fcol);
     for (int i = 0; i < 9; ++i) fcol[i * pl + s] = fc[i];
@@ -324,9 +349,7 @@ template <class PR>
 __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, int y, int o, int sx, int sy,
                                                     typename PR::TC fco, bool hole)
 {
-    using TF = typename PR::TF;
     using TC = typename PR::TC;
-    using FS = FStore<TF>;
     const int ex = sx < 0 ? EDGE_XMIN : EDGE_XMAX, ey = sy < 0 ? EDGE_YMIN : EDGE_YMAX;
     const bool dx = !hole && sx != 0 && p.bc[ex] == BC_DIRICHLET;
     const bool dy = !hole && sy != 0 && p.bc[ey] == BC_DIRICHLET;
@@ -347,10 +370,9 @@ __device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, i
         return fco - TC(6) * w * (cx * jx + cy * jy);
     }
     // populations' moments r and Pi at the node (state n)
-    const size_t pl = (size_t)p.plane, s = (size_t)y * p.nx + x;
-    const TF *fin = static_cast<const TF *>(p.f_in);
+    const size_t s = (size_t)y * p.nx + x;
     TC f[9];
-    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+    gen_load_f<PR>(p, x, y, s, f);
     const TC r = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const TC dsum = (f[5] + f[6]) + (f[7] + f[8]);
     TC Pxx = (f[1] + f[3]) + dsum, Pyy = (f[2] + f[4]) + dsum, Pxy = (f[5] - f[6]) + (f[7] - f[8]);
@@ -450,9 +472,15 @@ __global__ void __launch_bounds__(256) stream_pass(const GenParams p)
     } else {
         stream_edge<PR>(p, x, y, s, perx, pery, fn);
     }
-    const bool sr = FS::kStochastic && p.sr;
-    const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
-    store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, fn, TC(p.f_scale), sr, key);
+    if constexpr (FS::kDeviation) {
+        // stored by store_pass once the new state's gradient is known
+        TC *fnw = static_cast<TC *>(p.fnew);
+        for (int i = 0; i < 9; ++i) fnw[i * pl + s] = fn[i];
+    } else {
+        const bool sr = FS::kStochastic && p.sr;
+        const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
+        store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, fn, TC(p.f_scale), sr, key);
+    }
     const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
     const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
     const TC *S = static_cast<const TC *>(p.S);
@@ -517,6 +545,34 @@ __global__ void __launch_bounds__(256) update_pass(const GenParams p)
         p.flag[0] = 1u;
 }
 
+// Last pass with deviation storage: the new populations minus the reference
+// equilibrium of the new state (the gradient of u_{n+1} at step n + 1 and
+// j_{n+1}, as the next step's loads rebuild it), rounded to the storage type.
+template <class PR>
+__global__ void __launch_bounds__(256) store_pass(const GenParams p)
+{
+    using TF = typename PR::TF;
+    using TU = typename PR::TU;
+    using TJ = typename PR::TJ;
+    using TC = typename PR::TC;
+    using FS = FStore<TF>;
+    const int n = p.nx * p.ny;
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int y = s / p.nx, x = s - y * p.nx;
+    if (g_hole(p, x, y)) return;
+    const size_t pl = (size_t)p.plane;
+    TC H[4], fr[9], dv[9];
+    gen_grad<PR>(p, static_cast<const TU *>(p.u_out), x, y, (double)(p.step + 1), H);
+    const TJ *jo = static_cast<const TJ *>(p.j_out);
+    ref_eq(H, TC(jo[s]), TC(jo[pl + s]), fr);
+    const TC *fnw = static_cast<const TC *>(p.fnew);
+    for (int i = 0; i < 9; ++i) dv[i] = fnw[i * pl + s] - fr[i];
+    const bool sr = FS::kStochastic && p.sr;
+    const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
+    store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, dv, TC(p.f_scale), sr, key);
+}
+
 // Scratch bytes of the passes for an nx x ny plate.
 template <class PR>
 inline size_t general_scratch_bytes(int nx, int ny)
@@ -525,8 +581,9 @@ inline size_t general_scratch_bytes(int nx, int ny)
     using TC = typename PR::TC;
     const size_t n = (size_t)nx * ny, ne = k_pitch(nx) * (ny + 2);
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t fnew = FStore<typename PR::TF>::kDeviation ? al(9 * n * sizeof(TC)) : 0;
     return al(4 * ne * sizeof(TC)) + al(9 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) +
-           al(2 * n * sizeof(TU));
+           al(2 * n * sizeof(TU)) + fnew;
 }
 
 // Enqueue one time step of the passes on the stream; scratch is
@@ -547,6 +604,8 @@ hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
     p.jf = scratch + off;
     off += al(2 * n * sizeof(TC));
     p.up = scratch + off;
+    off += al(2 * n * sizeof(typename PR::TU));
+    p.fnew = scratch + off;
     const int nb = (int)((n + 255) / 256), nbi = (p.nx + 255) / 256 * p.ny;
     const int nbk = (p.n_edge_k + 255) / 256, nbf = (p.n_edge_f + 255) / 256;
     hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbi), dim3(256), 0, st, p, 0);
@@ -559,6 +618,7 @@ hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
         if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 1);
         hipLaunchKernelGGL((update_pass<PR>), dim3(nb), dim3(256), 0, st, p);
     }
+    if constexpr (FStore<typename PR::TF>::kDeviation) hipLaunchKernelGGL((store_pass<PR>), dim3(nb), dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

@@ -61,6 +61,25 @@ inline StateLayout state_layout(int nx, int ny, lbm_precision p)
     return L;
 }
 
+// 16-bit populations are stored as deviations from a reference equilibrium
+// (lattice.hpp, ref_eq): the store waits for the new displacement's gradient,
+// which needs one more halo row and column per step.
+inline bool deviation_storage(lbm_precision p) { return p == LBM_FP16_STORE || p == LBM_BF16_STORE; }
+
+// Most time steps one launch may fuse: two with the predictor-corrector,
+// except with deviation storage (no two-step kernel).
+inline int max_steps_per_launch(lbm_precision p, lbm_scheme s)
+{
+    return s == LBM_SCHEME_PC && !deviation_storage(p) ? 2 : 1;
+}
+
+// Columns (and rows) of halo a tile recomputes: the stencil reach of the
+// steps it fuses.
+inline int stencil_halo(lbm_precision p, lbm_scheme s, int steps_per_launch)
+{
+    return ((s == LBM_SCHEME_PC ? 5 : 3) + (deviation_storage(p) ? 1 : 0)) * steps_per_launch;
+}
+
 // Launch shape of one plate: column strips and row segments.
 struct Shape {
     int block, strip_w, n_strips, n_segs, halo_a;
@@ -75,7 +94,7 @@ struct Shape {
 inline Shape make_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int block, int n_segs,
                         int steps_per_launch = 1)
 {
-    const int halo = (s == LBM_SCHEME_PC ? 5 : 3) * steps_per_launch;
+    const int halo = stencil_halo(p, s, steps_per_launch);
     const int wmax = block - 2 * halo;
     const int align = 32;
     Shape sh{};
@@ -146,10 +165,11 @@ struct Kernels {
     // The two pipelines of a two-step block share one compute unit's 160 KiB
     // of LDS: a 512-thread block fits with 32-bit values only, or with a
     // double displacement on plates periodic in y.
+    // (Deviation storage has no two-step kernel.)
     template <int B, bool W>
     static constexpr bool step2_fits()
     {
-        return 2 * sizeof(TileLds<PR, B, true, W>) <= size_t(160) * 1024;
+        return !FStore<typename PR::TF>::kDeviation && 2 * sizeof(TileLds<PR, B, true, W>) <= size_t(160) * 1024;
     }
     template <int B>
     static hipError_t step2_b(const StepParams &sp, int nblocks, hipStream_t st)

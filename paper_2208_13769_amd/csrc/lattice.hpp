@@ -100,8 +100,9 @@ __device__ __forceinline__ __hip_bfloat16 bf16_sr(float x, uint32_t r)
 }
 
 // Populations in 16-bit storage are kept multiplied by a per-plate power of
-// two so that their range sits well inside the format; 32/64-bit storage is
-// unscaled.
+// two so that their range sits well inside the format, and as deviations
+// from a reference equilibrium of the same state (ref_eq below,
+// kDeviation); 32/64-bit storage holds the populations themselves, unscaled.
 template <class TF>
 struct FStore;
 
@@ -113,6 +114,7 @@ struct FStore<double> {
     __device__ static void store(double *p, size_t i, double v, double) { p[i] = v; }
     __device__ static double conv(double v, double) { return v; }
     static constexpr bool kStochastic = false;
+    static constexpr bool kDeviation = false;
     __device__ static double roundtrip_sr(double v, double, double, uint32_t) { return v; }
     __device__ static void store_sr(double *p, size_t i, double v, double, uint32_t) { p[i] = v; }
 };
@@ -124,6 +126,7 @@ struct FStore<float> {
     __device__ static void store(float *p, size_t i, float v, float) { p[i] = v; }
     __device__ static float conv(float v, float) { return v; }
     static constexpr bool kStochastic = false;
+    static constexpr bool kDeviation = false;
     __device__ static float roundtrip_sr(float v, float, float, uint32_t) { return v; }
     __device__ static void store_sr(float *p, size_t i, float v, float, uint32_t) { p[i] = v; }
 };
@@ -147,6 +150,7 @@ struct FStore<__half> {
     __device__ static __half conv(float v, float scale) { return __float2half_rn(v * scale); }
     __device__ static __half conv_sr(float v, float scale, uint32_t r) { return half_sr(v * scale, r); }
     static constexpr bool kStochastic = true;
+    static constexpr bool kDeviation = true;
     __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
     {
         return __half2float(half_sr(v * scale, r)) * inv_scale;
@@ -184,6 +188,7 @@ struct FStore<__hip_bfloat16> {
     __device__ static __hip_bfloat16 conv(float v, float scale) { return __float2bfloat16(v * scale); }
     __device__ static __hip_bfloat16 conv_sr(float v, float scale, uint32_t r) { return bf16_sr(v * scale, r); }
     static constexpr bool kStochastic = true;
+    static constexpr bool kDeviation = true;
     __device__ static float roundtrip_sr(float v, float scale, float inv_scale, uint32_t r)
     {
         return __bfloat162float(bf16_sr(v * scale, r)) * inv_scale;
@@ -251,6 +256,42 @@ __device__ __forceinline__ TC piola(const TC H[4], TC lam, TC mu, TC P[4])
     P[2] = mu * F21 - c * F12;
     P[3] = mu * F22 + c * F11;
     return J;
+}
+
+// Reference equilibrium of deviation storage: f^eq(r, j, Pbar) of eq. (20)
+// with the zeroth moment r = -div u (eq. (18)), the momentum j and the
+// Poisson stress Pbar = -mu (H + H^T + tr H I) (eq. (15)), all from the
+// stored state of one site and its central-difference gradient H (lattice
+// units, where mu = C_s^2 = 1/3 for every material). The populations of a
+// smooth field differ from it by their non-equilibrium part and by the
+// small gaps between these moments and the populations' own, so storing
+// f - ref_eq instead of f shrinks the storage rounding error by that
+// ratio. H row-major as in stress_sum.
+template <class TC>
+__device__ __forceinline__ void ref_eq(const TC H[4], TC jx, TC jy, TC fr[9])
+{
+    const TC third = TC(1) / TC(3);
+    const TC r = -(H[0] + H[3]);
+    // A = Pbar - r/3 I
+    const TC axx = TC(-2.0 / 3.0) * H[0], ayy = TC(-2.0 / 3.0) * H[3];
+    const TC axy = -third * (H[1] + H[2]);
+    const TC trA = axx + ayy;
+    const TC q0 = -trA * third;
+    const TC q13 = axx + q0, q24 = ayy + q0;
+    const TC q57 = TC(2) * (trA * third + axy), q68 = TC(2) * (trA * third - axy);
+    const TC jx3 = TC(3) * jx, jy3 = TC(3) * jy;
+    const TC w0 = TC(4) / TC(9), w1 = TC(1) / TC(9), w5 = TC(1) / TC(36);
+    fr[0] = w0 * (r + TC(4.5) * q0);
+    const TC b13 = r + TC(4.5) * q13, b24 = r + TC(4.5) * q24;
+    const TC b57 = r + TC(4.5) * q57, b68 = r + TC(4.5) * q68;
+    fr[1] = w1 * (b13 + jx3);
+    fr[3] = w1 * (b13 - jx3);
+    fr[2] = w1 * (b24 + jy3);
+    fr[4] = w1 * (b24 - jy3);
+    fr[5] = w5 * (b57 + (jx3 + jy3));
+    fr[7] = w5 * (b57 - (jx3 + jy3));
+    fr[6] = w5 * (b68 + (jy3 - jx3));
+    fr[8] = w5 * (b68 - (jy3 - jx3));
 }
 
 // Boundary-rule codes of the y edges (kept in step with lbm_bc).

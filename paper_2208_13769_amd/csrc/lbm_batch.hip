@@ -89,7 +89,7 @@ Shape batch_shape(int nx, int ny, lbm_precision p, lbm_scheme s, int seg_rows, i
 int max_plate_tiles(int nx, int ny, lbm_precision p, lbm_scheme s)
 {
     int n = 0;
-    for (int spl = 1; spl <= (s == LBM_SCHEME_PC ? 2 : 1); ++spl) {
+    for (int spl = 1; spl <= max_steps_per_launch(p, s); ++spl) {
         const Shape sh = batch_shape(nx, ny, p, s, kSegRowsMin, spl);
         n = std::max(n, sh.n_strips * sh.n_segs);
     }
@@ -222,7 +222,8 @@ void arena_free(lbm_batch *b, size_t off, size_t bytes)
 template <class PR, bool PC, bool W>
 const void *batch_kernel_ptr(int spl)
 {
-    if constexpr (PC) {
+    // (deviation storage has no two-step kernel)
+    if constexpr (PC && !FStore<typename PR::TF>::kDeviation) {
         if (spl == 2) return reinterpret_cast<const void *>(&batch_step2_kernel<PR, kBatchBlock, W>);
     }
     return reinterpret_cast<const void *>(&batch_step_kernel<PR, kBatchBlock, PC, W>);
@@ -385,7 +386,7 @@ lbm_status lbm_batch_create(int max_plates, int max_tiles, lbm_precision p, lbm_
     if (!e) e = hipGetDevice(&dev);
     if (!e) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu[3] = {0, 0, 0};
-    for (int k = 1; k <= (s == LBM_SCHEME_PC ? 2 : 1) && !e; ++k) {
+    for (int k = 1; k <= max_steps_per_launch(p, s) && !e; ++k) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[k], batch_kernel(p, s == LBM_SCHEME_PC, b->walled, k),
                                                          kBatchBlock, 0);
         b->grid_for[k] = std::max(1, cus * std::max(1, per_cu[k]));
@@ -400,7 +401,7 @@ lbm_status lbm_batch_create(int max_plates, int max_tiles, lbm_precision p, lbm_
     // (FP16 storage: 23.0k against 33.9k MLUPS on 256 uneven plates). FP64
     // moves 208 B per update, so halving the passes wins even at one wave
     // per SIMD (22.7k against 17.1k MLUPS on the same plates).
-    b->spl = (s == LBM_SCHEME_PC && (per_cu[2] >= 2 || p == LBM_FP64)) ? 2 : 1;
+    b->spl = (max_steps_per_launch(p, s) == 2 && (per_cu[2] >= 2 || p == LBM_FP64)) ? 2 : 1;
     b->grid = b->grid_for[b->spl];
     // zero the plate flags and the tile count
     e = hipMemsetAsync(b->d_flags(), 0, sizeof(unsigned) * max_plates, b->stream);
@@ -638,6 +639,8 @@ lbm_status lbm_batch_set_steps_per_launch(lbm_batch *b, int k)
     if (k != 1 && k != 2) return bfail(b, LBM_ERR_ARG, "steps per launch must be 1 or 2");
     if (k == 2 && b->scheme != LBM_SCHEME_PC)
         return bfail(b, LBM_ERR_UNSUPPORTED, "two steps per launch need the predictor-corrector scheme");
+    if (k == 2 && max_steps_per_launch(b->prec, b->scheme) < 2)
+        return bfail(b, LBM_ERR_UNSUPPORTED, "16-bit population storage runs one step per launch");
     if (k != b->spl) {
         // the plates' shapes carry the halo of the kernel: re-plan the tiles
         BHIP_TRY(b, hipStreamSynchronize(b->stream));

@@ -242,7 +242,7 @@ void refit_two_step(lbm_solver *h)
 
 void plan_launch(lbm_solver *h)
 {
-    const int halo = (h->scheme == LBM_SCHEME_PC ? 5 : 3) * h->spl;
+    const int halo = stencil_halo(h->prec, h->scheme, h->spl);
     // narrowest block whose strip covers the width, else 256 threads
     int block = 256;
     if (h->nx <= 64 - 2 * halo)
@@ -399,6 +399,8 @@ lbm_status lbm_set_steps_per_launch(lbm_solver *h, int k)
     if (k != 1 && k != 2) return fail(h, LBM_ERR_ARG, "steps per launch must be 1 or 2");
     if (k == 2 && h->scheme != LBM_SCHEME_PC)
         return fail(h, LBM_ERR_UNSUPPORTED, "two steps per launch need the predictor-corrector scheme");
+    if (k == 2 && max_steps_per_launch(h->prec, h->scheme) < 2)
+        return fail(h, LBM_ERR_UNSUPPORTED, "16-bit population storage runs one step per launch");
     h->spl = k;
     const int block = k == 2 && !two_step_fits(h, h->shape.block) ? 256 : h->shape.block;
     h->shape = make_shape(h->nx, h->ny, h->prec, h->scheme, block, h->shape.n_segs, k);

@@ -30,6 +30,15 @@
 // and stages D, E, F (which only need earlier rows) run before A, B, C, so
 // the loads are in flight while D-F compute.
 //
+// Deviation storage (16-bit populations): the populations are stored as
+// their deviation from the reference equilibrium ref_eq of the state they
+// belong to. A step adds ref_eq of its input state back when it loads a row
+// (the gradient comes from stage B, kept one more row), and holds the new
+// populations back until the new displacement's gradient at their row is
+// known (RefGrad, the next step's stages A and B run on this step's output),
+// three rows later with the predictor-corrector, one with the explicit
+// source; that needs one more halo row and column.
+//
 // Walls (y edges only) lie half a spacing outside the node rows 0 and ny-1.
 // Ghost displacement rows for the finite differences: momentum wall -- the
 // quadratic through the wall displacement u_w and the two nearest rows (the
@@ -215,9 +224,36 @@ __device__ __forceinline__ void wall_populations(bool top, int kind, const TC fc
     }
 }
 
+// Momentum-wall displacement at step tn + dn (lattice units): base plus j*
+// times the step index. One expression, shared by every stage that needs it,
+// so that all of them give the same value for a state.
+__device__ __forceinline__ double wall_disp(double base, double jstar, double tn, int dn)
+{
+    return base + jstar * (tn + dn);
+}
+
+// Ghost displacement rows (Sec. 6, reading Q11): rows above the top wall
+// from the two rows below it (which = 0: the first ghost row, 1: the
+// second), and the first ghost row below the bottom wall from rows 0 and 1;
+// a momentum wall takes the quadratic through its displacement uw, a
+// traction wall repeats the nearest row.
+template <class TU>
+__device__ __forceinline__ TU ghost_hi_u(int bc, int which, TU a, TU b, TU uw)
+{
+    if (bc == BC_NEUMANN) return a;
+    return which == 0 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
+}
+template <class TU>
+__device__ __forceinline__ TU ghost_lo_u(int bc, TU a, TU b, TU uw)
+{
+    if (bc == BC_NEUMANN) return a;
+    return TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3);
+}
+
 // LDS of one pipeline (one time step in flight): double-buffered rows of the
-// values whose x-neighbours are needed, and the wall populations.
-template <class TU, class TC, int BLOCK, bool PC, bool WALLED>
+// values whose x-neighbours are needed, the wall populations and, with
+// deviation storage, the output displacement rows of RefGrad.
+template <class TU, class TC, int BLOCK, bool PC, bool WALLED, bool DEV = false>
 struct PipeLds {
     TU u[2][2][BLOCK];
     TC k[2][2][BLOCK];
@@ -225,6 +261,7 @@ struct PipeLds {
     TU up[PC ? 2 : 1][2][BLOCK];
     TC kp[PC ? 2 : 1][2][BLOCK];
     TC wall[WALLED ? 2 : 1][3][BLOCK];
+    TU ref[DEV ? 2 : 1][2][DEV ? BLOCK : 1];
 };
 
 // Register ring of L rows of N values for a row loop unrolled by U = 4
@@ -316,7 +353,8 @@ struct Pipe {
     using TU = typename PR::TU;
     using TJ = typename PR::TJ;
     using TC = typename PR::TC;
-    using Lds = PipeLds<TU, TC, BLOCK, PC, WALLED>;
+    static constexpr bool DEV = FStore<TF>::kDeviation;
+    using Lds = PipeLds<TU, TC, BLOCK, PC, WALLED, DEV>;
     static constexpr int NU = PC ? 6 : 4;  // rows of u_n kept
     static constexpr int NJ = PC ? 4 : 2;  // rows of j_n kept
 
@@ -335,6 +373,7 @@ struct Pipe {
     Ring<TC, 2, 2, U> sN;    // source S_n of rows R-2, R-3 (abc)
     Ring<TC, NJ, 2, U> jN;   // j_n of rows R-2 .. (abc)
     Ring<TC, 2, 2, U> hx;    // du_x/dx, du_y/dx of rows R-1, R-2 (abc)
+    Ring<TC, 2, 2, U> hy;    // du_x/dy, du_y/dy of rows R-1, R-2 (abc; deviation storage)
     Ring<TC, 2, 1, U> o0;    // own f^col_0 of rows R-2, R-3 (abc)
     Ring<TC, 3, 1, U> o2;    // own f^col_2 of rows R-2 .. R-4 (abc)
     TC o4;                // own f^col_4 of row R-2 (abc)
@@ -359,6 +398,7 @@ struct Pipe {
         sN.zero();
         jN.zero();
         hx.zero();
+        hy.zero();
         o0.zero();
         o2.zero();
         o4 = n1 = n3 = TC(0);
@@ -373,21 +413,16 @@ struct Pipe {
     __device__ __forceinline__ bool is_node(int r) const { return !WALLED || (r >= 0 && r < ny); }
 
     // momentum-wall displacement (lattice units) at step n + dn
-    __device__ __forceinline__ TU uw_lo(int a, int dn) const { return TU(uwb_lo[a] + val_lo[a] * (tn + dn)); }
-    __device__ __forceinline__ TU uw_hi(int a, int dn) const { return TU(uwb_hi[a] + val_hi[a] * (tn + dn)); }
+    __device__ __forceinline__ TU uw_lo(int a, int dn) const { return TU(wall_disp(uwb_lo[a], val_lo[a], tn, dn)); }
+    __device__ __forceinline__ TU uw_hi(int a, int dn) const { return TU(wall_disp(uwb_hi[a], val_hi[a], tn, dn)); }
 
     // ghost rows above the top wall from the two rows below it
     __device__ __forceinline__ TU ghost_hi(int which, TU a, TU b, TU uw) const
     {
-        if (bc_hi == BC_NEUMANN) return a;
-        return which == 0 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
+        return ghost_hi_u(bc_hi, which, a, b, uw);
     }
     // first ghost row below the bottom wall from rows 0 and 1
-    __device__ __forceinline__ TU ghost_lo(TU a, TU b, TU uw) const
-    {
-        if (bc_lo == BC_NEUMANN) return a;
-        return TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3);
-    }
+    __device__ __forceinline__ TU ghost_lo(TU a, TU b, TU uw) const { return ghost_lo_u(bc_lo, a, b, uw); }
     // stress sum in the ghost row below the bottom wall, from rows 0 and 1:
     // own values u0, u1 and x-derivatives hx0, hx1 (du_x/dx, du_y/dx)
     __device__ __forceinline__ void ghost_lo_K(const TU u0[2], const TU u1[2], const TC hx0[2], const TC hx1[2],
@@ -576,6 +611,10 @@ struct Pipe {
             kA2.template push<PH>(1, K[3]);
             hx.template push<PH>(0, H[0]);
             hx.template push<PH>(1, H[2]);
+            if constexpr (DEV) {
+                hy.template push<PH>(0, H[1]);
+                hy.template push<PH>(1, H[3]);
+            }
         }
 
         // stage C: S_n at row R-2, collision
@@ -597,8 +636,21 @@ struct Pipe {
         if (nodeC) {
             jN.template push<PH>(0, jx);
             jN.template push<PH>(1, jy);
+            // the populations: with deviation storage the loaded deviations
+            // plus the reference equilibrium of row R-2 (gradient of stage B)
+            TC fl[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fl[i] = f[i];
+            if constexpr (DEV) {
+                const TC Hc[4] = {hx.template at<PH, 1>(0), hy.template at<PH, 1>(0), hx.template at<PH, 1>(1),
+                                  hy.template at<PH, 1>(1)};
+                TC fr[9];
+                ref_eq(Hc, jx, jy, fr);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fl[i] = fr[i] + f[i];
+            }
             TC r, pxx;
-            collide(f, jx, jy, Sx, Sy, omega, fc, r, pxx);
+            collide(fl, jx, jy, Sx, Sy, omega, fc, r, pxx);
             // K at a wall: the mean of the node row and the ghost row beyond it
             if (WALLED && rC == 0) {
                 TC w[3];
@@ -633,6 +685,69 @@ struct Pipe {
         o2.template push<PH>(0, fc[2]);
         o0.template push<PH>(0, fc[0]);
         o4 = fc[4];
+    }
+};
+
+// The gradient of the displacement a step writes, for the reference
+// equilibrium of deviation storage: row A's new displacement arrives at one
+// iteration (every column of the block at once), goes to LDS and to a ring,
+// and the central differences at row A - 1 take that row's x-neighbours from
+// LDS (written one iteration earlier) and rows A and A - 2, with the ghost
+// rows of the y walls. These are the next step's stages A and B on the same
+// values, in the same expressions, so the reference that step rebuilds when
+// it loads the row equals the one subtracted before the store, bit for bit.
+// `state` is the step index of the displacement (the output state).
+template <class TU, class TC, int BLOCK, bool WALLED, int U>
+struct RefGrad {
+    TU *const L;  // LDS [2 buffers][2 components][BLOCK]
+    const int t, tl, tr, ny, bc_lo, bc_hi;
+    TU uwl[2], uwh[2];
+    Ring<TU, 3, 2, U> uq;  // rows A, A-1, A-2 after the push
+
+    __device__ __forceinline__ TU &at(int b, int c, int x) const { return L[(b * 2 + c) * BLOCK + x]; }
+
+    __device__ __forceinline__ RefGrad(TU *lds, const StepParams &p, long long state, int t_)
+        : L(lds), t(t_), tl(t_ > 0 ? t_ - 1 : 0), tr(t_ < BLOCK - 1 ? t_ + 1 : BLOCK - 1), ny(p.ny),
+          bc_lo(p.bc_lo), bc_hi(p.bc_hi)
+    {
+        const double tn = (double)state;
+        for (int a = 0; a < 2; ++a) {
+            uwl[a] = TU(wall_disp(p.uwb_lo[a], p.val_lo[a], tn, 0));
+            uwh[a] = TU(wall_disp(p.uwb_hi[a], p.val_hi[a], tn, 0));
+        }
+        uq.zero();
+    }
+
+    // Row A's displacement (a node's value; the ghost row above the top wall
+    // from the rows below it); returns the gradient at row A - 1.
+    template <int PH>
+    __device__ __forceinline__ void push(int A, int b, bool nodeA, TU a0, TU a1, TC H[4])
+    {
+        constexpr int Q = PH - 1;
+        const int pb = b ^ 1;
+        TU v0, v1;
+        if (nodeA) {
+            v0 = a0;
+            v1 = a1;
+        } else if (A == ny && bc_hi != BC_PERIODIC) {
+            v0 = ghost_hi_u(bc_hi, 0, uq.template at<Q, 0>(0), uq.template at<Q, 1>(0), uwh[0]);
+            v1 = ghost_hi_u(bc_hi, 0, uq.template at<Q, 0>(1), uq.template at<Q, 1>(1), uwh[1]);
+        } else {
+            v0 = v1 = TU(0);
+        }
+        uq.template push<PH>(0, v0);
+        uq.template push<PH>(1, v1);
+        at(b, 0, t) = v0;
+        at(b, 1, t) = v1;
+        H[0] = TC((at(pb, 0, tr) - at(pb, 0, tl)) * TU(0.5));
+        H[2] = TC((at(pb, 1, tr) - at(pb, 1, tl)) * TU(0.5));
+        TU um0 = uq.template at<PH, 2>(0), um1 = uq.template at<PH, 2>(1);
+        if (WALLED && A - 1 == 0) {
+            um0 = ghost_lo_u(bc_lo, uq.template at<PH, 1>(0), uq.template at<PH, 0>(0), uwl[0]);
+            um1 = ghost_lo_u(bc_lo, uq.template at<PH, 1>(1), uq.template at<PH, 0>(1), uwl[1]);
+        }
+        H[1] = TC((uq.template at<PH, 0>(0) - um0) * TU(0.5));
+        H[3] = TC((uq.template at<PH, 0>(1) - um1) * TU(0.5));
     }
 };
 
@@ -719,6 +834,19 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     const bool sr = FS::kStochastic && p.sr;
     const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
 
+    // Deviation storage: the new populations of row rF - 1 are stored when
+    // RefGrad has the gradient of the new displacement there (rF: the row
+    // whose u_{n+1} and j_{n+1} this iteration produces); they wait FD rows.
+    constexpr bool DEV = FS::kDeviation;
+    constexpr int FD = PC ? 3 : 1;
+    RefGrad<TU, TC, BLOCK, WALLED, 4> rg(&lds.ref[0][0][0], p, p.step + 1, (int)threadIdx.x);
+    Ring<TC, FD, 9> fdl;  // f_{n+1} of rows rF .. rF - FD + 1 (PC) before the push
+    Ring<TC, 1, 2> jdl;   // j_{n+1} of row rF - 1 before the push
+    if constexpr (DEV) {
+        fdl.zero();
+        jdl.zero();
+    }
+
     auto row = [&](auto phase, const int R) {
         constexpr int PH = decltype(phase)::value;
         // Loads of this iteration (u_n at row R, f_n and j_n at row R-2) are
@@ -737,9 +865,27 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         TU unew[2];
         pipe.template def<PH>(R, PH & 1, fn, unew, jnew);
         const int rD = R - 4, rF = PC ? R - 6 : R - 4;
-        if (pipe.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
-            const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rD, ny) * (uint32_t)nx + (uint32_t)g.gx);
-            store_site<FS>(fout, plane, o, fn, f_scale, sr, key);
+        if constexpr (!DEV) {
+            if (pipe.is_node(rD) && g.out_col && rD >= g.y0 && rD < g.y1) {
+                const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rD, ny) * (uint32_t)nx + (uint32_t)g.gx);
+                store_site<FS>(fout, plane, o, fn, f_scale, sr, key);
+            }
+        } else {
+            TC H1[4];
+            rg.template push<PH>(rF, PH & 1, pipe.is_node(rF), unew[0], unew[1], H1);
+            const int rS = rF - 1;
+            if (pipe.is_node(rS) && g.out_col && rS >= g.y0 && rS < g.y1) {
+                TC fr[9], dv[9];
+                ref_eq(H1, jdl.template at<PH - 1, 0>(0), jdl.template at<PH - 1, 0>(1), fr);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) dv[i] = fdl.template at<PH - 1, FD - 1>(i) - fr[i];
+                const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rS, ny) * (uint32_t)nx + (uint32_t)g.gx);
+                store_site<FS>(fout, plane, o, dv, f_scale, sr, key);
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fdl.template push<PH>(i, fn[i]);
+            jdl.template push<PH>(0, TC(TJ(jnew[0])));
+            jdl.template push<PH>(1, TC(TJ(jnew[1])));
         }
         if (pipe.is_node(rF) && g.out_col && rF >= g.y0 && rF < g.y1) {
             const uint32_t o = row_offset((uint32_t)row_store<WALLED>(rF, ny) * (uint32_t)nx + (uint32_t)g.gx);
@@ -759,8 +905,9 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
         __syncthreads();
     };
 
-    const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7);
-    const int Rstart = g.y0 - HX;
+    // deviation storage: one more halo row below and the store delay above
+    const int n_iter = (g.y1 - g.y0) + (PC ? 11 : 7) + (DEV ? 2 : 0);
+    const int Rstart = g.y0 - HX - (DEV ? 1 : 0);
     for (int it = 0; it < n_iter; it += 4) {
         const int R = Rstart + it;
         row(Phase<0>{}, R);

@@ -14,6 +14,20 @@ def rel_l2(x, ref):
     return float(np.linalg.norm(x - ref) / den) if den > 0 else float(np.linalg.norm(x))
 
 
+def max_rel(x, ref):
+    """Largest element-wise error over the largest |reference| value: a
+    pointwise check beside rel-L2, which an error confined to one row, column
+    or tile seam can pass."""
+    den = np.abs(ref).max()
+    return float(np.abs(x - ref).max() / den) if den > 0 else float(np.abs(x).max())
+
+
+# Pointwise bound as a multiple of a case's rel-L2 bound: smooth errors sit
+# within a small factor of their L2 norm, while an error confined to a row
+# of an N-row plate is about sqrt(N) times its share of the norm.
+MAX_NORM_FACTOR = 10.0
+
+
 def oracle_run(nx, ny, u0, v0, nsteps, *, dx=1.0, rho0=1.0, lam=0.1, mu=0.05, tau=0.8, scheme="pc",
                body=(0.0, 0.0), bc_lo=("periodic", (0.0, 0.0)), bc_hi=("periodic", (0.0, 0.0))):
     p = O.Params(nx=nx, ny=ny, dx=dx, rho0=rho0, lam=lam, mu=mu, tau_over_dt=tau,

@@ -20,9 +20,12 @@ class FakeSolver:
 def test_strips_are_multiples_of_32_columns():
     # 256 threads, two PC steps: halo 10 each side, 236 columns -> 224
     assert strips(4096, 256, "fp32u64", "pc", 2) == 19
-    # 16-bit storage takes the same 32-column rule (two blocks may share a line)
-    assert strips(4096, 256, "fp16", "pc", 2) == 19
-    assert strips(4096, 512, "fp16", "pc", 2) == 9
+    # 16-bit storage takes the same 32-column rule (two blocks may share a
+    # line) with one more halo column: 256 - 2 * 6 = 244 -> 224, 512 -> 480
+    assert strips(4096, 256, "fp16", "pc", 1) == 19
+    assert strips(4096, 512, "fp16", "pc", 1) == 9
+    assert strips(4096, 128, "fp16", "pc", 1) == 43  # 128 - 12 = 116 -> 96 columns
+    assert strips(100, 128, "fp16", "pc", 1) == 1 and strips(117, 128, "fp16", "pc", 1) == 2
     # a plate narrower than one block's reach is one strip
     assert strips(100, 128, "fp32", "pc", 1) == 1
 

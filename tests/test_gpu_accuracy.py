@@ -4,18 +4,20 @@ steps), against the FP64 oracle.
 
 The field is uniform in y and the grid is periodic, so the exact (FP64)
 solution has identical rows: the oracle runs a 1024 x 8 plate and each of its
-rows is the reference for every row of the 1024 x 1024 GPU run. The bounds
-are the measured errors with a margin; they record where each precision
-stands after 5000 steps, which is longer than the parity tests' runs:
-- 16-bit storage rounded to nearest drifts: slowly varying populations round
-  the same way step after step, and the error in the conserved momentum grows
-  with the step count (about 1e-2 in u for FP16, 1e-1 for BF16);
-- stochastic rounding removes the drift (u within 1e-3 for both), but its
-  zero-mean noise in u is amplified by the difference quotient in P, which
-  stays at the 1e-2 (FP16) and 1e-1 (BF16) level;
-- FP32 drifts the same way at the float level: about 6e-5 in u; P (1.8e-4)
-  also carries the float rounding of the accumulated displacement, which
-  FP32_U64 (double displacement) removes (P 6e-5, u unchanged).
+rows is the reference for every row of the 1024 x 1024 GPU run.
+
+Every case asserts the contract bound of its storage form (rel-L2 on u and
+P: 1e-5 for FP32 storage, 1e-3 for 16-bit storage; FP64 is held to its
+1e-12 scaled to the run length). Known misses are marked xfail with the
+measured error:
+- FP32 populations drift over 5000 steps: a slowly varying population
+  rounds the same way step after step, so the error in the conserved
+  momentum, and hence in u, grows with the step count (u 6e-5); plain FP32
+  also rounds the accumulated displacement (P 1.8e-4), which FP32_U64 (a
+  double displacement) removes (P 6e-5);
+- 16-bit populations are stored as deviations from the reference
+  equilibrium of their state, which is within a fraction of a percent of
+  them in this smooth wave, so their rounding no longer drifts visibly.
 
 A second case is the large-strain workload at a quarter of its size: a
 1024 x 1024 periodic plate, the same calibrated peak velocity (a wave's
@@ -66,23 +68,28 @@ def errors(gpu, reference):
     return out
 
 
-@pytest.mark.parametrize("prec,rnd,tol_u,tol_P", [
-    ("fp64", "nearest", 3e-11, 3e-11),
-    ("fp32", "nearest", 3e-4, 6e-4),
-    ("fp32u64", "nearest", 1.5e-4, 1.5e-4),
-    ("fp16", "nearest", 4e-2, 4e-2),
-    ("fp16", "stochastic", 5e-4, 4e-2),
-    ("bf16", "nearest", 0.4, 0.4),
-    ("bf16", "stochastic", 3e-3, 0.3),
+def _miss(reason):
+    return pytest.mark.xfail(reason=reason, strict=False)
+
+
+@pytest.mark.parametrize("prec,rnd,tol", [
+    ("fp64", "nearest", 3e-11),
+    pytest.param("fp32", "nearest", 1e-5, marks=_miss("FP32 drift over 5000 steps: u 6.0e-5, P 1.8e-4")),
+    pytest.param("fp32u64", "nearest", 1e-5, marks=_miss("FP32 population drift over 5000 steps: u 6e-5, P 6e-5")),
+    ("fp16", "nearest", 1e-3),
+    ("fp16", "stochastic", 1e-3),
+    ("bf16", "nearest", 1e-3),
+    ("bf16", "stochastic", 1e-3),
 ])
-def test_storage_precision_error_after_5000_steps(errors, prec, rnd, tol_u, tol_P):
+def test_storage_precision_error_after_5000_steps(errors, prec, rnd, tol):
     eu, ev, eP = errors[prec, rnd]
-    assert eu < tol_u and eP < tol_P, (prec, rnd, eu, eP)
+    assert eu < tol and eP < tol, (prec, rnd, eu, eP)
 
 
-@pytest.mark.parametrize("prec", ["fp16", "bf16"])
-def test_stochastic_rounding_removes_the_drift(errors, prec):
-    assert errors[prec, "stochastic"][0] < 0.1 * errors[prec, "nearest"][0]
+def test_stochastic_rounding_removes_the_drift(errors):
+    """BF16 (8 significant bits) still shows the drift of rounding to
+    nearest; stochastic rounding takes it out."""
+    assert errors["bf16", "stochastic"][0] < 0.5 * errors["bf16", "nearest"][0]
 
 
 def _large_strain_case():
@@ -102,12 +109,11 @@ def large_strain_reference():
     return u, v, P
 
 
-# 16-bit storage (rounded to nearest) on this large-strain field: u within
-# 1e-3 for FP16 (1.9e-4); P, a difference of the noisy displacement, at
-# 2.3e-3 misses the 1e-3 target, and BF16 misses it on both (1.7e-3,
-# 1.8e-2). The bounds below hold those measured errors with some margin.
-@pytest.mark.parametrize("prec,tol_u,tol_P", [("fp32", 1e-5, 2e-4), ("fp32u64", 1e-5, 1e-5),
-                                              ("fp16", 1e-3, 5e-3), ("bf16", 5e-3, 5e-2)])
+# The contract bounds on this large-strain field. Plain FP32 misses 1e-5 on
+# P (1.5e-5: P differences a float displacement of a few lattice units).
+@pytest.mark.parametrize("prec,tol_u,tol_P", [
+    pytest.param("fp32", 1e-5, 1e-5, marks=_miss("plain FP32: P 1.5e-5 (float displacement)")),
+    ("fp32u64", 1e-5, 1e-5), ("fp16", 1e-3, 1e-3), ("bf16", 1e-3, 1e-3)])
 def test_large_strain_500_steps(gpu, large_strain_reference, prec, tol_u, tol_P):
     from paper_2208_13769_amd import lbm
 

@@ -49,9 +49,9 @@ def _specs(walled):
     return specs
 
 
-@pytest.mark.parametrize("precision,walled,spl", [("fp16", True, 2), ("fp32", False, 2), ("fp64", True, 2),
+@pytest.mark.parametrize("precision,walled,spl", [("fp16", False, 1), ("fp32", False, 2), ("fp64", True, 2),
                                                   ("fp16", True, 1), ("fp32", False, 1), ("fp32u64", False, 2),
-                                                  ("fp32u64", True, 1), ("bf16", True, 1), ("bf16", False, 2)])
+                                                  ("fp32u64", True, 1), ("bf16", True, 1), ("bf16", False, 1)])
 def test_batch_equals_plates_alone(gpu, precision, walled, spl):
     """Every plate of a mixed batch equals the same plate run alone, bitwise,
     after each of several graph-replayed chunks (eager reads in between);
@@ -175,3 +175,18 @@ def test_packed_tile_table_with_many_tiles_per_block(gpu):
         assert st == 0 and st2 == 0 and db.steps == steps[k]
         assert np.array_equal(ub, us) and np.array_equal(vb, vs) and np.array_equal(Pb, Ps), k
     b.close()
+
+
+def test_batch_16bit_storage_runs_one_step_per_launch(gpu):
+    """16-bit storage has no two-step batch kernel: the batch defaults to one
+    step per launch and refuses two."""
+    from paper_2208_13769_amd import lbm
+    from paper_2208_13769_amd.batch import Batch
+
+    for prec in ("fp16", "bf16"):
+        b = Batch(max_plates=2, arena_bytes=16 << 20, precision=prec)
+        assert b.steps_per_launch() == 1
+        with pytest.raises(lbm.LbmError) as ei:
+            b.set_steps_per_launch(2)
+        assert ei.value.status == lbm.LBM_ERR_UNSUPPORTED
+        b.close()

@@ -18,7 +18,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2208_13769_amd import inputs
-from tests.helpers import rel_l2
+from tests.helpers import MAX_NORM_FACTOR, max_rel, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -43,12 +43,11 @@ def _patch(a, x0, y0):
     return np.ascontiguousarray(a[:, ys][:, :, xs])
 
 
-# The 16-bit forms run in their own benchmark's launch shape (512-thread
-# two-step blocks, 28 segments) on the same large-strain start. FP16 meets
-# the 1e-3 target (worst region P 9.9e-4); BF16 does not (P up to 1.0e-2),
-# and its bound only holds that measured error.
+# The 16-bit forms (deviation storage, one step per launch) run on the same
+# large-strain start in a 256-thread, 28-segment launch, against the 1e-3
+# bound.
 @pytest.mark.parametrize("precision,tiling,tol", [("fp32u64", (256, 26, 2), 1e-5), ("fp64", None, 1e-12),
-                                                  ("fp16", (512, 28, 2), 1e-3), ("bf16", (512, 28, 2), 2e-2)])
+                                                  ("fp16", (256, 28, 1), 1e-3), ("bf16", (256, 28, 1), 1e-3)])
 def test_full_size_sampled_regions(gpu, start_fields, precision, tiling, tol):
     from paper_2208_13769_amd import lbm
 
@@ -61,7 +60,7 @@ def test_full_size_sampled_regions(gpu, start_fields, precision, tiling, tol):
     s.set_fields(u0, v0)
     s.step(K)
     gx, gy = np.meshgrid(np.arange(REGION), np.arange(REGION))
-    worst = 0.0
+    worst = worst_max = 0.0
     for x0, y0 in CENTRES:
         smp = s.sample((gx + x0).ravel(), (gy + y0).ravel())  # [n][17]: u (2), v (2), P (4), ...
         p = O.Params(nx=PATCH, ny=PATCH, lam=0.1, mu=0.05, tau_over_dt=0.8)
@@ -72,10 +71,14 @@ def test_full_size_sampled_regions(gpu, start_fields, precision, tiling, tol):
         ref_u = np.stack([uo[a][sl].ravel() for a in range(2)], axis=1)
         ref_P = np.stack([Po[a, b][sl].ravel() for a in range(2) for b in range(2)], axis=1)
         eu, eP = rel_l2(smp[:, 0:2], ref_u), rel_l2(smp[:, 4:8], ref_P)
-        print(f"{precision} region at ({x0}, {y0}): rel-L2 u {eu:.3e} P {eP:.3e}", flush=True)
+        mu_, mP = max_rel(smp[:, 0:2], ref_u), max_rel(smp[:, 4:8], ref_P)
+        print(f"{precision} region at ({x0}, {y0}): rel-L2 u {eu:.3e} P {eP:.3e}; "
+              f"max-norm u {mu_:.3e} P {mP:.3e}", flush=True)
         worst = max(worst, eu, eP)
+        worst_max = max(worst_max, mu_, mP)
     s.close()
     assert worst < tol
+    assert worst_max < MAX_NORM_FACTOR * tol
 
 
 def test_plates_256_fp64_batch_against_oracle_on_sampled_plates(gpu):
@@ -115,3 +118,45 @@ def test_plates_256_fp64_batch_against_oracle_on_sampled_plates(gpu):
         print(f"plate {i}: n {sp.nx}, lam/mu {sp.lam / sp.mu:.2f}: rel-L2 u {eu:.2e} P {ep:.2e}", flush=True)
         assert eu < 2e-12 and ep < 2e-12, (i, eu, ep)
     b.close()
+
+
+def _golden_500():
+    path = os.path.join(os.path.dirname(__file__), "golden", "large_strain_4096_500.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+# The whole workload: the 4096 x 4096 large-strain plate for its 500 steps,
+# against the FP64 oracle's values at 512 seeded nodes
+# (golden/large_strain_4096_500.py, the oracle alone). FP32 with an FP64
+# displacement runs in the benchmark's launch shape; plain FP32 misses 1e-5
+# on P (it differences a float displacement of a few lattice units).
+@pytest.mark.parametrize("precision,tiling,tol", [
+    ("fp32u64", (256, 26, 2), 1e-5), ("fp64", None, 1e-11),
+    pytest.param("fp32", (256, 26, 2), 1e-5, marks=pytest.mark.xfail(reason="plain FP32: P about 4e-5 after 500 "
+                                                                            "steps", strict=False)),
+    ("fp16", (256, 28, 1), 1e-3), ("bf16", (256, 28, 1), 1e-3)])
+def test_full_size_500_steps_against_oracle(gpu, start_fields, precision, tiling, tol):
+    from paper_2208_13769_amd import lbm
+
+    g = _golden_500()
+    u0, v0 = start_fields
+    s = lbm.Solver(N, N, 1.0, precision, "pc")
+    s.set_material(1.0, g["lam"], g["mu"], g["tau_over_dt"])
+    if tiling:
+        s.set_steps_per_launch(tiling[2])
+        s.set_tiling(tiling[0], tiling[1])
+    s.set_fields(u0, v0)
+    s.step(g["steps"])
+    smp = s.sample(np.array(g["x"]), np.array(g["y"]))
+    *_, d, st = s.read(want_fields=False)
+    s.close()
+    assert st == 0 and d.steps == g["steps"]
+    ref_u, ref_v, ref_P = np.array(g["u"]), np.array(g["v"]), np.array(g["P"])
+    eu, ev, eP = rel_l2(smp[:, 0:2], ref_u), rel_l2(smp[:, 2:4], ref_v), rel_l2(smp[:, 4:8], ref_P)
+    mu_, mP = max_rel(smp[:, 0:2], ref_u), max_rel(smp[:, 4:8], ref_P)
+    print(f"{precision} 4096^2 after {g['steps']} steps, 512 nodes: rel-L2 u {eu:.3e} v {ev:.3e} P {eP:.3e}; "
+          f"max-norm u {mu_:.3e} P {mP:.3e}; max strain {d.max_strain:.3f}", flush=True)
+    assert d.max_strain > 0.15
+    assert eu < tol and eP < tol
+    assert mu_ < MAX_NORM_FACTOR * tol and mP < MAX_NORM_FACTOR * tol
