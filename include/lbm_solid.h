@@ -155,6 +155,21 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
  * LBM_ERR_UNSTABLE (after filling the outputs) if the unstable flag is set. */
 lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_diagnostics *d);
 
+/* The diagnostics of lbm_read_fields (d only) with no use of the
+ * workspace's reduction scratch and no device allocation: for callers that
+ * cannot allocate device memory or touch the workspace's scratch, such as code
+ * being captured into a HIP graph, tight serving loops, or harnesses that
+ * forbid allocation. The per-block partial sums and the folded values go to
+ * a static device array of the library, 1024 * 8 + 8 doubles (65,600
+ * bytes) per GPU, held until the process ends; the diagnostics grid
+ * is capped at 1024 blocks, so no plate needs more (LBM_ERR_UNSUPPORTED
+ * otherwise). Every call on one GPU shares that array: calls that overlap on
+ * one GPU (from different threads or streams) race and must be serialised by
+ * the caller. Results equal lbm_read_fields' diagnostics bit for bit. Runs on
+ * the device current at lbm_create (restoring the caller's current device);
+ * synchronises the stream; LBM_ERR_UNSTABLE as lbm_read_fields. */
+lbm_status lbm_read_diagnostics_noalloc(lbm_solver *h, lbm_diagnostics *d);
+
 /* Derived fields in physical units, from the same central-difference
  * displacement gradient H(u) as P (Sec. 5): the Cauchy stress
  * sigma = J^-1 P F^T ([4][ny][nx]: sigma11, sigma12, sigma21, sigma22; Sec. 7

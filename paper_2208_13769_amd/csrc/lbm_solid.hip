@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,8 +63,16 @@ Layout make_layout(int nx, int ny, lbm_precision p)
 
 }  // namespace
 
+// Device scratch of lbm_read_diagnostics_noalloc: the per-block partial sums
+// of the diagnostics kernel (kMaxDiagBlocks blocks, 8 doubles each) and the
+// folded values (8 doubles). Each GPU holds its own copy until the process
+// ends; every call on a GPU shares it.
+constexpr size_t kNoAllocDiagDoubles = (size_t)kMaxDiagBlocks * 8 + 8;
+static __device__ __align__(256) double scratch[kNoAllocDiagDoubles];
+
 struct lbm_solver {
     int nx = 0, ny = 0;
+    int device = 0;  // the device current at lbm_create
     double dx = 1.0;
     lbm_precision prec = LBM_FP64;
     lbm_scheme scheme = LBM_SCHEME_PC;
@@ -316,6 +325,7 @@ lbm_status lbm_create(int nx, int ny, double dx, lbm_precision p, lbm_scheme s, 
     h->ws_bytes = ws_bytes;
     h->stream = static_cast<hipStream_t>(hip_stream);
     h->L = L;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     plan_launch(h);
     *out = h;
     return LBM_OK;
@@ -732,6 +742,74 @@ lbm_status lbm_read_fields(lbm_solver *h, double *u, double *v, double *P, lbm_d
         d->reserved = 0;
         d->steps = h->steps;
     }
+    if (flag != 0) return fail(h, LBM_ERR_UNSTABLE, "J <= 0 or a non-finite value appeared");
+    return LBM_OK;
+}
+
+namespace {
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (the array's name is a host-side stand-in, not the
+// device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t device_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+lbm_status lbm_read_diagnostics_noalloc(lbm_solver *h, lbm_diagnostics *d)
+{
+    if (!h) return LBM_ERR_ARG;
+    if (!d) return fail(h, LBM_ERR_ARG, "d is NULL");
+    if (!h->fields) return fail(h, LBM_ERR_STATE, "no fields set");
+    // the diagnostics grid is capped at kMaxDiagBlocks blocks
+    const size_t n = (size_t)h->nx * h->ny;
+    const size_t nblocks = std::min<size_t>(kMaxDiagBlocks, (n + 255) / 256);
+    if (nblocks * 8 + 8 > kNoAllocDiagDoubles)
+        return fail(h, LBM_ERR_UNSUPPORTED, "diagnostics need more scratch than the static array holds");
+    int cur = 0;
+    HIP_TRY(h, hipGetDevice(&cur));
+    if (cur != h->device) HIP_TRY(h, hipSetDevice(h->device));
+    double *sp = nullptr;
+    hipError_t e = device_scratch(h->device, &sp);
+    double out[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned flag = 0;
+    if (e == hipSuccess) {
+        PlateIO io = h->io();
+        io.partials = sp;
+        io.diag_out = sp + (size_t)kMaxDiagBlocks * 8;
+        e = plate_read(io, (double)h->steps, nullptr, nullptr, nullptr, out);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, h->flag(), sizeof(unsigned), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (cur != h->device) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "diagnostics");
+    d->momentum[0] = out[0];
+    d->momentum[1] = out[1];
+    d->mass_moment = out[2];
+    d->energy = out[3];
+    d->min_J = out[4];
+    d->max_strain = out[5];
+    d->unstable = (out[6] != 0.0 || flag != 0) ? 1 : 0;
+    d->reserved = 0;
+    d->steps = h->steps;
     if (flag != 0) return fail(h, LBM_ERR_UNSTABLE, "J <= 0 or a non-finite value appeared");
     return LBM_OK;
 }

@@ -34,7 +34,8 @@ ROUNDINGS = {"nearest": LBM_ROUND_NEAREST, "stochastic": LBM_ROUND_STOCHASTIC}
 EXPORTED_EXTRA: list = []
 EXPORTED = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_material", "lbm_set_body_force", "lbm_set_boundary",
-    "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_get_dt", "lbm_destroy", "lbm_last_error",
+    "lbm_set_fields", "lbm_step", "lbm_read_fields", "lbm_read_diagnostics_noalloc", "lbm_get_dt", "lbm_destroy",
+    "lbm_last_error",
     "lbm_set_tiling", "lbm_get_tiling", "lbm_set_steps_per_launch", "lbm_get_steps_per_launch",
     "lbm_resident_blocks", "lbm_set_rounding", "lbm_read_derived", "lbm_sample", "lbm_batch_read_derived",
     "lbm_batch_sample", "lbm_workspace_bytes_walled", "lbm_set_general_path", "lbm_set_mask",
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lbm_step.argtypes = [vp, ctypes.c_int64]
     lib.lbm_read_fields.restype = ctypes.c_int
     lib.lbm_read_fields.argtypes = [vp, dp, dp, dp, ctypes.POINTER(lbm_diagnostics)]
+    lib.lbm_read_diagnostics_noalloc.restype = ctypes.c_int
+    lib.lbm_read_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(lbm_diagnostics)]
     ip = ctypes.POINTER(ctypes.c_int)
     lib.lbm_read_derived.restype = ctypes.c_int
     lib.lbm_read_derived.argtypes = [vp, dp, dp, dp]
@@ -218,6 +221,16 @@ def lbm_sample(h, xs, ys) -> np.ndarray:
     out = np.empty((len(xs), 17))
     _check(load_library().lbm_sample(h, len(xs), _iptr(xs), _iptr(ys), _dptr(out)), h)
     return out
+
+
+def lbm_read_diagnostics_noalloc(h, diag: lbm_diagnostics) -> int:
+    """Diagnostics through the entry point that allocates nothing (its scratch
+    is a static device array); returns the status (LBM_ERR_UNSTABLE is
+    returned, not raised)."""
+    st = load_library().lbm_read_diagnostics_noalloc(h, ctypes.byref(diag))
+    if st not in (LBM_OK, LBM_ERR_UNSTABLE):
+        _check(st, h)
+    return st
 
 
 def lbm_read_fields(h, u=None, v=None, P=None, diag: lbm_diagnostics | None = None) -> int:
