@@ -48,18 +48,20 @@ __device__ inline double u_row(const TU *u, const FieldParams &p, int a, int x, 
     if (y >= 0 && y < p.ny) return (double)u[a * pl + (size_t)y * p.nx + x];
     if (y < 0) {
         const double u0 = (double)u[a * pl + x], u1 = (double)u[a * pl + (size_t)p.nx + x];
+        (void)u1;
         if (p.bc_lo == BC_NEUMANN) return u0;
-        return 8.0 / 3.0 * p.uw_lo[a] - 2.0 * u0 + u1 / 3.0;
+        return 2.0 * p.uw_lo[a] - u0;
     }
     const double v0 = (double)u[a * pl + (size_t)(p.ny - 1) * p.nx + x];
     const double v1 = (double)u[a * pl + (size_t)(p.ny - 2) * p.nx + x];
+    (void)v1;
     if (p.bc_hi == BC_NEUMANN) return v0;
-    return 8.0 / 3.0 * p.uw_hi[a] - 2.0 * v0 + v1 / 3.0;
+    return 2.0 * p.uw_hi[a] - v0;
 }
 
 // Displacement at (x, y), -1 <= x <= nx, -1 <= y <= ny: beyond an x wall the
-// ghost column is extrapolated across the wall from the row values of the
-// two nearest columns (ghost rows included), as the y walls do for rows.
+// ghost column is extrapolated across the wall from the row value of the
+// nearest column (ghost rows included), as the y walls do for rows.
 template <class TU>
 __device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, int y)
 {
@@ -69,8 +71,7 @@ __device__ inline double u_at(const TU *u, const FieldParams &p, int a, int x, i
     const int kind = left ? p.bc_left : p.bc_right;
     const double u0 = u_row(u, p, a, left ? 0 : p.nx - 1, y);
     if (kind == BC_NEUMANN) return u0;
-    const double u1 = u_row(u, p, a, left ? 1 : p.nx - 2, y);
-    return 8.0 / 3.0 * (left ? p.uw_left[a] : p.uw_right[a]) - 2.0 * u0 + u1 / 3.0;
+    return 2.0 * (left ? p.uw_left[a] : p.uw_right[a]) - u0;
 }
 
 // Central-difference gradient at (x, y); a hole neighbour takes the node's

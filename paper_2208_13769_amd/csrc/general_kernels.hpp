@@ -84,13 +84,15 @@ __device__ __forceinline__ TC gweight(int i)
 }
 
 // Ghost value k = 1 or 2 spacings beyond a wall from the node next to it
-// (a) and the one after it (b): the quadratic through the wall displacement
-// uw of a momentum wall, the value a at a traction wall.
+// (a): at a momentum wall the straight line through the wall displacement
+// uw and a (2 uw - a, then 4 uw - 3 a), at a traction wall the value a.
+// (b, the node after a, is used by neither rule.)
 template <class TU>
 __device__ __forceinline__ TU gen_ghost(int kind, TU uw, TU a, TU b, int k)
 {
+    (void)b;
     if (kind == BC_NEUMANN) return a;
-    return k == 1 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
+    return k == 1 ? TU(2) * uw - a : TU(4) * uw - TU(3) * a;
 }
 
 // momentum-wall displacement of edge e at step t (lattice units)

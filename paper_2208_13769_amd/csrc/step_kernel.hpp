@@ -41,7 +41,7 @@
 //
 // Walls (y edges only) lie half a spacing outside the node rows 0 and ny-1.
 // Ghost displacement rows for the finite differences: momentum wall -- the
-// quadratic through the wall displacement u_w and the two nearest rows (the
+// straight line through the wall displacement u_w and the nearest row (the
 // wall moves with j* / rho0, so u_w is the integral of the values of j* in
 // effect); traction wall -- the nearest row repeated. Rows above the
 // top wall follow from rows already walked; the ghost row below the bottom
@@ -235,19 +235,23 @@ __device__ __forceinline__ double wall_disp(double base, double jstar, double tn
 // Ghost displacement rows (Sec. 6, reading Q11): rows above the top wall
 // from the two rows below it (which = 0: the first ghost row, 1: the
 // second), and the first ghost row below the bottom wall from rows 0 and 1;
-// a momentum wall takes the quadratic through its displacement uw, a
-// traction wall repeats the nearest row.
+// a momentum wall takes the straight line through its displacement uw and
+// the nearest row a (2 uw - a one spacing beyond, 4 uw - 3 a two spacings
+// beyond), a traction wall repeats the nearest row. (b, the row after a, is
+// used by neither rule.)
 template <class TU>
 __device__ __forceinline__ TU ghost_hi_u(int bc, int which, TU a, TU b, TU uw)
 {
+    (void)b;
     if (bc == BC_NEUMANN) return a;
-    return which == 0 ? TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3) : TU(8) * uw - TU(9) * a + TU(2) * b;
+    return which == 0 ? TU(2) * uw - a : TU(4) * uw - TU(3) * a;
 }
 template <class TU>
 __device__ __forceinline__ TU ghost_lo_u(int bc, TU a, TU b, TU uw)
 {
+    (void)b;
     if (bc == BC_NEUMANN) return a;
-    return TU(8.0 / 3.0) * uw - TU(2) * a + b / TU(3);
+    return TU(2) * uw - a;
 }
 
 // LDS of one pipeline (one time step in flight): double-buffered rows of the
@@ -310,6 +314,51 @@ struct Ring {
     {
         if constexpr (TL > 0) tail[PMod<P, TS>::v][c] = h[PMod<P, H>::v][c];
         h[PMod<P, H>::v][c] = v;
+    }
+};
+
+// Unrolled by two (U = 2): the rows form pairs of registers, each pair
+// rotating with the phase, so a push moves one value from each pair into the
+// next (ceil(L / 2) - 1 moves, against L - 1 for a shifting ring). After the
+// push of phase P, row k = 2 g + q sits in pair g at slot (P - q) mod 2; an
+// odd ring's last row is a single register.
+template <class T, int L, int N>
+struct Ring<T, L, N, 2> {
+    static constexpr int G = L / 2;     // full pairs
+    static constexpr bool ODD = L & 1;  // one more single row
+    T p[G > 0 ? G : 1][2][N];
+    T last[ODD ? 1 : 1][N];
+
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int c = 0; c < N; ++c) p[g][0][c] = p[g][1][c] = T(0);
+#pragma unroll
+        for (int c = 0; c < N; ++c) last[0][c] = T(0);
+    }
+    template <int P, int K>
+    __device__ __forceinline__ T &at(int c)
+    {
+        static_assert(K >= 0 && K < L, "ring row out of range");
+        if constexpr (ODD && K == L - 1)
+            return last[0][c];
+        else
+            return p[K / 2][PMod<P - (K % 2), 2>::v][c];
+    }
+    template <int P>
+    __device__ __forceinline__ void push(int c, T v)
+    {
+        constexpr int s = PMod<P, 2>::v;
+        // the oldest row of the last full pair moves on to the single row
+        if constexpr (ODD && G > 0) last[0][c] = p[G - 1][s][c];
+#pragma unroll
+        for (int g = G - 1; g > 0; --g) p[g][s][c] = p[g - 1][s][c];
+        if constexpr (G > 0)
+            p[0][s][c] = v;
+        else
+            last[0][c] = v;
     }
 };
 
@@ -435,10 +484,14 @@ struct Pipe {
             H[1] = TC(0);
             H[3] = TC(0);
         } else {
-            H[0] = TC(-2) * hx0[0] + hx1[0] / TC(3);
-            H[2] = TC(-2) * hx0[1] + hx1[1] / TC(3);
-            H[1] = TC(TU(5) * u0[0] - u1[0] - TU(4) * uw[0]);
-            H[3] = TC(TU(5) * u0[1] - u1[1] - TU(4) * uw[1]);
+            // ghost rows 2 uw - u0 and 4 uw - 3 u0: the x-derivatives change
+            // sign, and the central y-difference at row -1 is 2 (u0 - uw)
+            (void)u1;
+            (void)hx1;
+            H[0] = -hx0[0];
+            H[2] = -hx0[1];
+            H[1] = TC(TU(2) * (u0[0] - uw[0]));
+            H[3] = TC(TU(2) * (u0[1] - uw[1]));
         }
         stress_sum(H, lam, mu, K);
         k12 = K[1];
@@ -981,13 +1034,14 @@ struct FDelay<FS, TC, U, true> {
 // step is recomputed, never exchanged. The values handed over pass through
 // the storage precision, so the result equals two single steps bitwise.
 // Row-loop unroll of the two-step tile: 4, except with float arithmetic on a
-// double-precision displacement (16-bit storage, FP32_U64), whose double
-// rings leave no registers for the values the unrolled schedule keeps live
-// (it would drop to one wave per SIMD).
+// double-precision displacement (FP32_U64), whose double rings leave no
+// registers for the values the four-way schedule keeps live (it would drop
+// to one wave per SIMD); those take the two-way unroll, whose rings rotate
+// in register pairs.
 template <class PR>
 constexpr int step2_unroll()
 {
-    return (sizeof(typename PR::TU) == 8 && sizeof(typename PR::TC) == 4) ? 1 : 4;
+    return (sizeof(typename PR::TU) == 8 && sizeof(typename PR::TC) == 4) ? 2 : 4;
 }
 
 template <class PR, int BLOCK, bool WALLED>
@@ -1089,6 +1143,12 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
             row(Phase<1>{}, R + 1, 1);
             row(Phase<2>{}, R + 2, 0);
             row(Phase<3>{}, R + 3, 1);
+        }
+    } else if constexpr (U == 2) {
+        for (int it = 0; it < n_iter; it += 2) {
+            const int R = Rstart + it;
+            row(Phase<0>{}, R, 0);
+            row(Phase<1>{}, R + 1, 1);
         }
     } else {
         for (int it = 0; it < n_iter; ++it) row(Phase<0>{}, Rstart + it, it & 1);
