@@ -317,51 +317,6 @@ struct Ring {
     }
 };
 
-// Unrolled by two (U = 2): the rows form pairs of registers, each pair
-// rotating with the phase, so a push moves one value from each pair into the
-// next (ceil(L / 2) - 1 moves, against L - 1 for a shifting ring). After the
-// push of phase P, row k = 2 g + q sits in pair g at slot (P - q) mod 2; an
-// odd ring's last row is a single register.
-template <class T, int L, int N>
-struct Ring<T, L, N, 2> {
-    static constexpr int G = L / 2;     // full pairs
-    static constexpr bool ODD = L & 1;  // one more single row
-    T p[G > 0 ? G : 1][2][N];
-    T last[ODD ? 1 : 1][N];
-
-    __device__ __forceinline__ void zero()
-    {
-#pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int c = 0; c < N; ++c) p[g][0][c] = p[g][1][c] = T(0);
-#pragma unroll
-        for (int c = 0; c < N; ++c) last[0][c] = T(0);
-    }
-    template <int P, int K>
-    __device__ __forceinline__ T &at(int c)
-    {
-        static_assert(K >= 0 && K < L, "ring row out of range");
-        if constexpr (ODD && K == L - 1)
-            return last[0][c];
-        else
-            return p[K / 2][PMod<P - (K % 2), 2>::v][c];
-    }
-    template <int P>
-    __device__ __forceinline__ void push(int c, T v)
-    {
-        constexpr int s = PMod<P, 2>::v;
-        // the oldest row of the last full pair moves on to the single row
-        if constexpr (ODD && G > 0) last[0][c] = p[G - 1][s][c];
-#pragma unroll
-        for (int g = G - 1; g > 0; --g) p[g][s][c] = p[g - 1][s][c];
-        if constexpr (G > 0)
-            p[0][s][c] = v;
-        else
-            last[0][c] = v;
-    }
-};
-
 // Without unrolling (U = 1) a push shifts the ring by one row and the phase
 // is ignored: row k is always register k.
 template <class T, int L, int N>
@@ -1035,13 +990,15 @@ struct FDelay<FS, TC, U, true> {
 // the storage precision, so the result equals two single steps bitwise.
 // Row-loop unroll of the two-step tile: 4, except with float arithmetic on a
 // double-precision displacement (FP32_U64), whose double rings leave no
-// registers for the values the four-way schedule keeps live (it would drop
-// to one wave per SIMD); those take the two-way unroll, whose rings rotate
-// in register pairs.
+// registers for the values an unrolled schedule keeps live: unrolled by four
+// or by two (rings rotating in register pairs) it needs 283-290 registers,
+// one wave per SIMD, and runs 0.307 ms per step on the 4096^2 plate (0.409
+// with two waves forced, spilling 26 registers) against 0.250 for the
+// shifting loop at two waves.
 template <class PR>
 constexpr int step2_unroll()
 {
-    return (sizeof(typename PR::TU) == 8 && sizeof(typename PR::TC) == 4) ? 2 : 4;
+    return (sizeof(typename PR::TU) == 8 && sizeof(typename PR::TC) == 4) ? 1 : 4;
 }
 
 template <class PR, int BLOCK, bool WALLED>
@@ -1143,12 +1100,6 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
             row(Phase<1>{}, R + 1, 1);
             row(Phase<2>{}, R + 2, 0);
             row(Phase<3>{}, R + 3, 1);
-        }
-    } else if constexpr (U == 2) {
-        for (int it = 0; it < n_iter; it += 2) {
-            const int R = Rstart + it;
-            row(Phase<0>{}, R, 0);
-            row(Phase<1>{}, R + 1, 1);
         }
     } else {
         for (int it = 0; it < n_iter; ++it) row(Phase<0>{}, Rstart + it, it & 1);
