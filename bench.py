@@ -357,6 +357,7 @@ def bench_plates(args):
         ms = e0.elapsed_time(e1)
         return b, slots, ms
 
+    copy_probe(args.copy_probe_mib, torch.device("cuda:0"))
     b16, s16, ms16 = run_batch("fp16")
     b16_spl = b16.steps_per_launch()
     flagged = [i for i, s_ in enumerate(s16) if b16.query(s_)[2]]
