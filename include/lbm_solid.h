@@ -81,7 +81,7 @@ typedef enum { LBM_ROUND_NEAREST = 0, LBM_ROUND_STOCHASTIC = 1 } lbm_rounding;
  * predictor displacement from the trapezoidal rule with j(t + dt) replaced
  * by 2 j(t) - j(t - dt) (j(t - dt) = j(0) at the first step). It grows for
  * lambda > mu (about 9 % per step at lambda = 2 mu) and always runs the
- * general per-site passes, so it needs lbm_workspace_bytes_walled(). */
+ * general step, so it needs lbm_workspace_bytes_walled(). */
 typedef enum { LBM_SCHEME_PC = 0, LBM_SCHEME_EXPLICIT = 1, LBM_SCHEME_EXTRAP = 2 } lbm_scheme;
 
 typedef enum { LBM_EDGE_XMIN = 0, LBM_EDGE_XMAX = 1, LBM_EDGE_YMIN = 2, LBM_EDGE_YMAX = 3 } lbm_edge;
@@ -109,9 +109,9 @@ typedef struct {
 size_t lbm_workspace_bytes(int nx, int ny, lbm_precision p);
 
 /* Device bytes a plate needs when it may have walls on its x edges, holes
- * or the extrapolation scheme (the general per-site passes):
- * lbm_workspace_bytes plus the scratch fields of the passes (about 19
- * values per site) and one mask byte per site. */
+ * or the extrapolation scheme (the general step): lbm_workspace_bytes plus
+ * a copy of j for the extrapolation scheme, one mask byte per site and a
+ * byte per tile of the general step. */
 size_t lbm_workspace_bytes_walled(int nx, int ny, lbm_precision p);
 
 /* Create a handle. nx, ny >= 5; dx > 0. dev_workspace: device memory of
@@ -132,8 +132,9 @@ lbm_status lbm_set_body_force(lbm_solver *h, const double b[2]);
  * of a periodic pair a wall turns the other into a momentum wall at rest
  * until it is set). value may be NULL for LBM_BC_PERIODIC. Takes effect from
  * the next lbm_step, so a load history can be applied step by step.
- * Walls on the x edges run the general passes (walls and corners on every
- * edge) and need a workspace of lbm_workspace_bytes_walled() bytes
+ * Walls on the x edges run the general step (one launch of 2D tiles with
+ * walls and corners on every edge) and need a workspace of
+ * lbm_workspace_bytes_walled() bytes
  * (LBM_ERR_NOMEM otherwise). At a corner of two walls the diagonal link takes
  * the momentum wall's rule if either wall is one (the mean j* if both are);
  * between two traction walls it is anti-bounced with both walls' transformed
@@ -215,10 +216,12 @@ lbm_status lbm_get_steps_per_launch(const lbm_solver *h, int *k);
  * chosen with it. Writes 0 for a shape the handle cannot launch. */
 lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_launch, int *blocks);
 
-/* Run every step as the general per-site passes (1) or, when no x edge is a
- * wall, as the fused step kernel (0, the default). The passes give the same
- * results up to rounding; they exist for walls on the x edges and are
- * slower. Needs a workspace of lbm_workspace_bytes_walled() bytes. */
+/* Run every step as the general step (1: one launch of 2D tiles, each
+ * holding its whole neighbourhood in LDS) or, when no x edge is a wall, as
+ * the fused step kernel (0, the default). Both give the same results up to
+ * rounding; the general step exists for walls on the x edges, holes and the
+ * extrapolation scheme. Needs a workspace of lbm_workspace_bytes_walled()
+ * bytes. */
 lbm_status lbm_set_general_path(lbm_solver *h, int on);
 
 /* Holes in the plate (the plate with a hole of Sec. 7.2). solid: host array
@@ -233,13 +236,14 @@ lbm_status lbm_set_general_path(lbm_solver *h, int on);
  * edge (they may cross periodic edges), and no material node may have hole
  * nodes on both sides along one axis (material at least two nodes thick;
  * LBM_ERR_ARG otherwise; the method gives such a node no gradient). A hole
- * one node wide is valid for the method but not implemented here
- * (LBM_ERR_UNSUPPORTED): holes must be at least two nodes wide. Once a mask
+ * may be one node wide: each material node beside it takes the stress sum
+ * of its own gradient there (the derivatives across the hole set to zero),
+ * so the nodes on its two sides see different values. Once a mask
  * is set, lbm_set_boundary may change boundary values and kinds but may not
  * make an edge periodic or not (LBM_ERR_STATE). Set
  * the boundaries first, then the mask, then the fields (LBM_ERR_STATE
  * after lbm_set_fields). Needs lbm_workspace_bytes_walled() (LBM_ERR_NOMEM
- * otherwise); runs the general passes. Copies the array; synchronises. */
+ * otherwise); runs the general step. Copies the array; synchronises. */
 lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid);
 
 /* Rounding of the populations written by later steps (the start state of

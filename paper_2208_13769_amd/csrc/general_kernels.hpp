@@ -1,42 +1,34 @@
-// general_kernels.hpp -- the time step as plain per-site passes, for plates
-// with walls on the x edges and corners (Sec. 6), holes (Sec. 7.2) and the
-// j-extrapolation variant (end of Sec. 5).
+// general_kernels.hpp -- one time step of a plate with walls on any edge, holes
+// (Sec. 6, Sec. 7.2) or the j-extrapolation variant (end of Sec. 5), as one
+// launch of 2D tiles.
 //
-// The fused step kernel marches rows with a register/LDS pipeline whose x
-// halo is periodic; walls on the x edges need ghost columns and wall rules
-// in every stage, which that pipeline cannot hold without extra barriers.
-// These kernels do one time step as per-site passes over full fields
-// instead (one thread per site; the stress and streaming passes in two
-// launches each, interior nodes and a list of edge nodes):
-//   1. K = P + Pbar on the lattice and one ring of ghost nodes, from u_n and
-//      its ghost values (stress_pass);
-//   2. source S_n (central divergence of K), moments, equilibrium and BGK
-//      collision into f_col (collide_pass);
-//   3. pull streaming; a link whose source lies beyond a wall takes the
-//      wall's rule instead; moments jf of the new populations and the
-//      predictor u^p (stream_pass);
-//   4. K of u^p at t + dt (stress_pass again), then S^p, j_{n+1} and
-//      u_{n+1} (update_pass). The explicit scheme stops after pass 3.
-// With deviation storage (16-bit populations) pass 3 keeps the new
-// populations in scratch and a last pass (store_pass) stores their
-// deviation from the reference equilibrium of the new state; the passes that
-// load populations add the reference of the input state back.
-// In the extrapolation variant (end of Sec. 5) u^p takes 2 j_n - j_{n-1}
-// for j at t + dt; j_{n-1} is still in the output buffer of j, which pass 3
-// reads at its own site before pass 4b overwrites it.
-// Holes (Sec. 7.2): a mask marks nodes outside the material. A link from a
-// material node into a hole crosses a traction-free wall half-way; the wall
-// is the one its axis step enters, both for the diagonal that meets a hole
-// corner. In the differences a hole neighbour takes the node's own
-// displacement, and K there is K of the node's gradient with the
-// derivatives along that axis set to zero. Holes are at least two nodes
-// wide, so a hole node has at most one material neighbour per axis: the
-// stress pass stores that K in the hole node's own slot (columns of the x
-// neighbour's K in entries 0 and 2, of the y neighbour's in 1 and 3, the
-// entries the divergence reads), and the source needs no special case.
-// Hole nodes carry no state: no pass reads it (the read-outs report zeros
-// there), so only the hole nodes on a border are visited at all.
-// Same lattice units, arithmetic and storage rounding as the fused kernel.
+// A block owns a TW x TH tile of output sites and works on a window around
+// it in LDS. The stages of the step shrink the window one ring at a time,
+// each reading only what the previous stage left in LDS:
+//   u_n (ring RU, loaded with the ghost values beyond walls)
+//   -> K = P + Pbar of u_n (ring RK)
+//   -> source S_n, populations f_n, BGK collision f_col (ring RF)
+//   -> pull streaming with the wall and hole rules, moments, predictor
+//      u^p (ring RS)
+//   -> K of u^p (ring RP) -> corrector j_{n+1}, u_{n+1} (ring RC).
+// With 16-bit storage the new populations are stored as deviations from the
+// reference equilibrium of the new state, whose gradient needs u_{n+1} one
+// ring beyond the tile (RC = 1). The explicit scheme ends at the streaming
+// ring. Every ring beyond the tile is recomputed by the neighbouring blocks
+// as well: no stage waits for another block, so one launch is one step.
+//
+// The rules are those of the per-site formulation of the method:
+// - a ghost node beyond a wall takes the value of the node next to the wall
+//   (traction wall) or the straight line through the wall displacement (a
+//   momentum wall: 2 uw - a, then 4 uw - 3 a); beyond two walls (a corner)
+//   the x wall's rule applies to the y wall's ghost;
+// - in a central difference a hole neighbour takes the node's own value;
+// - the stress sum at a hole neighbour across axis n, as a material node
+//   sees it, is K of that node's gradient with the derivatives along n set
+//   to zero (reading Q23). Each node computes it from its own gradient, so a
+//   hole one node wide, seen from both sides, needs nothing stored;
+// - a link whose source lies beyond a wall or in a hole takes the wall's
+//   bounce-back (eq. (25)) or anti-bounce-back (eq. (26)) rule.
 #pragma once
 
 #include "step_kernel.hpp"
@@ -48,6 +40,7 @@ enum : int { EDGE_XMIN = 0, EDGE_XMAX = 1, EDGE_YMIN = 2, EDGE_YMAX = 3 };
 struct GenParams {
     const void *f_in, *u_in, *j_in;  // state n
     void *f_out, *u_out, *j_out;     // state n + 1
+    const void *j_prev;              // j_{n-1} (j-extrapolation only)
     int nx, ny;
     long long plane;
     double omega, lam, mu, bx, by;  // lattice units
@@ -59,17 +52,9 @@ struct GenParams {
     int sr;
     unsigned long long seed;
     int pc;  // explicit (0), predictor-corrector (1), j extrapolated for the predictor (2)
-    void *K;     // scratch [4][ny + 2][k_pitch(nx)] TC: stress sum with one ghost ring
-    void *fcol;  // scratch [9][ny][nx] TC: post-collision populations
-    void *S;     // scratch [2][ny][nx] TC: source S_n
-    void *jf;    // scratch [2][ny][nx] TC: first moment of the new populations
-    void *up;    // scratch [2][ny][nx] TU: predictor displacement
-    void *fnew;  // scratch [9][ny][nx] TC: new populations (deviation storage only)
     unsigned *flag;
-    const unsigned char *mask;  // [ny][nx] bit 0: material (1) or hole (0); bit 1: interior; nullptr: no holes
-    const int *edge_k;          // ring indices (y + 1)(nx + 2) + x + 1 of the stress pass's edge nodes
-    const int *edge_f;          // lattice indices of the stream pass's edge nodes
-    int n_edge_k, n_edge_f;
+    const unsigned char *mask;   // [ny][nx]: 1 material, 0 hole; nullptr: no holes
+    const unsigned char *tiles;  // TILE_* bits of each tile (row-major); nullptr: no holes
 };
 
 // D2Q9 of this implementation (see lattice.hpp)
@@ -86,11 +71,9 @@ __device__ __forceinline__ TC gweight(int i)
 // Ghost value k = 1 or 2 spacings beyond a wall from the node next to it
 // (a): at a momentum wall the straight line through the wall displacement
 // uw and a (2 uw - a, then 4 uw - 3 a), at a traction wall the value a.
-// (b, the node after a, is used by neither rule.)
 template <class TU>
-__device__ __forceinline__ TU gen_ghost(int kind, TU uw, TU a, TU b, int k)
+__device__ __forceinline__ TU gen_ghost(int kind, TU uw, TU a, int k)
 {
-    (void)b;
     if (kind == BC_NEUMANN) return a;
     return k == 1 ? TU(2) * uw - a : TU(4) * uw - TU(3) * a;
 }
@@ -102,529 +85,772 @@ __device__ __forceinline__ TU gen_uw(const GenParams &p, int e, int a, double t)
     return TU(p.uwb[e][a] + p.val[e][a] * t);
 }
 
-// u of column x (0 <= x < nx) at row y (-2 <= y <= ny + 1): ghost rows of
-// the y walls, or the periodic image
-template <class TU>
-__device__ __forceinline__ TU gen_u_row(const TU *u, const GenParams &p, int a, int x, int y, double t)
-{
-    const size_t pl = (size_t)p.plane;
-    if (y >= 0 && y < p.ny) return u[a * pl + (size_t)y * p.nx + x];
-    if (p.bc[EDGE_YMIN] == BC_PERIODIC) {
-        y = (y % p.ny + p.ny) % p.ny;
-        return u[a * pl + (size_t)y * p.nx + x];
-    }
-    const bool lo = y < 0;
-    const int e = lo ? EDGE_YMIN : EDGE_YMAX;
-    const int k = lo ? -y : y - (p.ny - 1);
-    const TU u0 = u[a * pl + (size_t)(lo ? 0 : p.ny - 1) * p.nx + x];
-    const TU u1 = u[a * pl + (size_t)(lo ? 1 : p.ny - 2) * p.nx + x];
-    return gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, a, t), u0, u1, k);
-}
+// Threads of a tile's block.
+constexpr int kTileBlock = 512;
 
-// u at (x, y) within two spacings of the lattice: ghost columns of the x
-// walls are extrapolated across the wall from the rows' values (ghost rows
-// included), so corner ghosts come from the ghost rows
-template <class TU>
-__device__ __forceinline__ TU gen_u(const TU *u, const GenParams &p, int a, int x, int y, double t)
-{
-    if (x >= 0 && x < p.nx) return gen_u_row(u, p, a, x, y, t);
-    if (p.bc[EDGE_XMIN] == BC_PERIODIC) return gen_u_row(u, p, a, (x % p.nx + p.nx) % p.nx, y, t);
-    const bool lo = x < 0;
-    const int e = lo ? EDGE_XMIN : EDGE_XMAX;
-    const int k = lo ? -x : x - (p.nx - 1);
-    const TU u0 = gen_u_row(u, p, a, lo ? 0 : p.nx - 1, y, t);
-    const TU u1 = gen_u_row(u, p, a, lo ? 1 : p.nx - 2, y, t);
-    return gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, a, t), u0, u1, k);
-}
-
-// node (x, y) lies in a hole; coordinates beyond a periodic edge wrap,
-// beyond a wall they are in no hole
-__device__ __forceinline__ bool g_hole(const GenParams &p, int x, int y)
-{
-    if (!p.mask) return false;
-    if (y < 0 || y >= p.ny) {
-        if (p.bc[EDGE_YMIN] != BC_PERIODIC) return false;
-        y = (y % p.ny + p.ny) % p.ny;
-    }
-    if (x < 0 || x >= p.nx) {
-        if (p.bc[EDGE_XMIN] != BC_PERIODIC) return false;
-        x = (x % p.nx + p.nx) % p.nx;
-    }
-    return (p.mask[(size_t)y * p.nx + x] & 1) == 0;
-}
-
-// central-difference gradient of u at (x, y) (lattice or ghost ring); a hole
-// neighbour takes the node's own value
-template <class PR>
-__device__ __forceinline__ void gen_grad(const GenParams &p, const typename PR::TU *u, int x, int y, double t,
-                                         typename PR::TC H[4])
-{
+// Tile shape and the rings (distance from the tile) of the stages.
+// MODE 0: explicit; 1: predictor-corrector (also with j extrapolated).
+template <class PR, int MODE>
+struct TileCfg {
     using TU = typename PR::TU;
     using TC = typename PR::TC;
-    const bool hxp = g_hole(p, x + 1, y), hxm = g_hole(p, x - 1, y);
-    const bool hyp = g_hole(p, x, y + 1), hym = g_hole(p, x, y - 1);
-    for (int a = 0; a < 2; ++a) {
-        const TU c = (hxp || hxm || hyp || hym) ? gen_u(u, p, a, x, y, t) : TU(0);
-        const TU xp = hxp ? c : gen_u(u, p, a, x + 1, y, t), xm = hxm ? c : gen_u(u, p, a, x - 1, y, t);
-        const TU yp = hyp ? c : gen_u(u, p, a, x, y + 1, t), ym = hym ? c : gen_u(u, p, a, x, y - 1, t);
-        H[2 * a + 0] = TC((xp - xm) * TU(0.5));
-        H[2 * a + 1] = TC((yp - ym) * TU(0.5));
-    }
-}
+    static constexpr bool DEV = FStore<typename PR::TF>::kDeviation;
+    static constexpr int BLOCK = kTileBlock;
+    static constexpr int TW = 32;
+    // Rows per tile: LDS within 80 KB, so two blocks share a CU, and few
+    // enough sites per thread on the streaming ring (at most two) and, with
+    // deviation storage, on the collision ring (at most two) that the
+    // registers holding them are not spilled.
+    static constexpr int TH = DEV ? 4 : (sizeof(TC) == 8 ? 6 : 8);
+    static constexpr int RC = DEV ? 1 : 0;          // corrector (PC) or update (explicit)
+    static constexpr int RS = MODE ? RC + 2 : RC;   // streaming, predictor
+    static constexpr int RP = MODE ? RC + 1 : 0;    // K of u^p
+    static constexpr int RF = RS + 1;               // collision
+    static constexpr int RK = RS + 2;               // K of u_n
+    static constexpr int RU = RS + 3;               // u_n
+    static constexpr int W(int r) { return TW + 2 * r; }
+    static constexpr int H(int r) { return TH + 2 * r; }
+    static constexpr int N(int r) { return W(r) * H(r); }
+};
 
-// The populations of state n at node (x, y), site s: the stored values or,
-// with deviation storage, the stored deviations plus the reference
-// equilibrium of the stored state (gradient at step n, stored momentum).
-template <class PR>
-__device__ __forceinline__ void gen_load_f(const GenParams &p, int x, int y, size_t s, typename PR::TC f[9])
-{
+template <class PR, int MODE>
+struct TileLdsG {
+    static_assert(TileCfg<PR, MODE>::N(TileCfg<PR, MODE>::RS) <= 2 * TileCfg<PR, MODE>::BLOCK &&
+                      TileCfg<PR, MODE>::N(TileCfg<PR, MODE>::RC) <= 2 * TileCfg<PR, MODE>::BLOCK,
+                  "two sites per thread at most on the streaming and corrector rings");
+    using C = TileCfg<PR, MODE>;
+    using TU = typename PR::TU;
+    using TC = typename PR::TC;
+    TU u[2][C::N(C::RU)];
+    TC k[4][C::N(C::RK)];
+    TC fc[9][C::N(C::RF)];
+    TC jc[2][MODE || C::DEV ? C::N(C::RC) : 1];  // jf, then j_{n+1}, at the corrector ring
+    TC jn[2][C::N(C::RF)];                       // j_n on the collision ring
+    TU un[2][MODE ? C::N(C::RC) : 1];            // u_n at the corrector ring
+    TC fn[9][C::DEV ? C::TW * C::TH : 1];        // new populations of the tile (deviation storage)
+    unsigned char kind[C::N(C::RU)];
+};
+
+enum : unsigned char { SITE_NODE = 1, SITE_HOLE = 2, SITE_GHOST = 4 };
+
+// Bits of a tile's entry in the tile table (built on the host with the mask).
+enum : unsigned char { TILE_HOLES = 1, TILE_MATERIAL = 2 };
+
+template <class PR, int MODE>
+struct TileStep {
+    using C = TileCfg<PR, MODE>;
     using TF = typename PR::TF;
     using TU = typename PR::TU;
     using TJ = typename PR::TJ;
     using TC = typename PR::TC;
     using FS = FStore<TF>;
-    const size_t pl = (size_t)p.plane;
-    const TF *fin = static_cast<const TF *>(p.f_in);
-    for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
-    if constexpr (FS::kDeviation) {
-        TC H[4], fr[9];
-        gen_grad<PR>(p, static_cast<const TU *>(p.u_in), x, y, (double)p.step, H);
-        const TJ *jin = static_cast<const TJ *>(p.j_in);
-        ref_eq(H, TC(jin[s]), TC(jin[pl + s]), fr);
-        for (int i = 0; i < 9; ++i) f[i] = fr[i] + f[i];
+    using Lds = TileLdsG<PR, MODE>;
+
+    const GenParams &p;
+    Lds &L;
+    const int x0, y0;
+    const bool perx, pery;
+    const TC lam, mu, omega;
+    // From the tile table (all set without a mask): the window holds a hole
+    // node, so the hole rules are tested; the tile holds a material node (a
+    // tile wholly inside a hole computes nothing: its sites only get the
+    // zero state of hole nodes).
+    const bool holes, active;
+
+    __device__ TileStep(const GenParams &p_, Lds &l, int x0_, int y0_, unsigned char tf)
+        : p(p_), L(l), x0(x0_), y0(y0_), perx(p_.bc[EDGE_XMIN] == BC_PERIODIC),
+          pery(p_.bc[EDGE_YMIN] == BC_PERIODIC), lam(TC(p_.lam)), mu(TC(p_.mu)), omega(TC(p_.omega)),
+          holes((tf & TILE_HOLES) != 0), active((tf & TILE_MATERIAL) != 0)
+    {
     }
-}
 
-// (x, y) and its eight neighbours are lattice nodes of the material (no
-// ghost value, no wall, no hole): the common case, taken without branches
-__device__ __forceinline__ bool g_inner(const GenParams &p, int x, int y)
-{
-    if (x < 1 || x > p.nx - 2 || y < 1 || y > p.ny - 2) return false;
-    // bit 1 of the mask: the host marked the node interior
-    return !p.mask || (p.mask[(size_t)y * p.nx + x] & 2) != 0;
-}
+    // index of tile-relative (dx, dy) in an array over ring r
+    template <int R>
+    __device__ __forceinline__ static int at(int dx, int dy)
+    {
+        return (dy + R) * C::W(R) + (dx + R);
+    }
 
-// Row pitch of K: column x sits at x + 32, so the lattice columns of every
-// row start on a 128-byte line and a wave's store covers whole lines.
-__host__ __device__ __forceinline__ size_t k_pitch(int nx) { return ((size_t)nx + 33 + 31) / 32 * 32; }
+    // Plate coordinates of tile-relative (dx, dy): wrapped across periodic
+    // edges; bx, by: spacings beyond a wall (0 inside the plate).
+    __device__ __forceinline__ void coords(int dx, int dy, int &x, int &y, int &bx, int &by) const
+    {
+        x = x0 + dx;
+        y = y0 + dy;
+        bx = by = 0;
+        if (x < 0 || x >= p.nx) {
+            if (perx) {
+                x %= p.nx;
+                if (x < 0) x += p.nx;
+            } else {
+                bx = x < 0 ? -x : x - (p.nx - 1);
+            }
+        }
+        if (y < 0 || y >= p.ny) {
+            if (pery) {
+                y %= p.ny;
+                if (y < 0) y += p.ny;
+            } else {
+                by = y < 0 ? -y : y - (p.ny - 1);
+            }
+        }
+    }
 
-__device__ __forceinline__ size_t k_index(const GenParams &p, int c, int x, int y)
-{
-    return ((size_t)c * (p.ny + 2) + (size_t)(y + 1)) * k_pitch(p.nx) + (size_t)(x + 32);
-}
+    __device__ __forceinline__ unsigned char kind(int dx, int dy) const { return L.kind[at<C::RU>(dx, dy)]; }
+    __device__ __forceinline__ bool hole(int dx, int dy) const { return kind(dx, dy) & SITE_HOLE; }
+    __device__ __forceinline__ TU uval(int a, int dx, int dy) const { return L.u[a][at<C::RU>(dx, dy)]; }
+    __device__ __forceinline__ TC kval(int c, int dx, int dy) const { return L.k[c][at<C::RK>(dx, dy)]; }
 
-// K at the hole neighbour of (x, y) across axis n: K of the node's gradient
-// with the derivatives along n set to zero
-template <class PR>
-__device__ __forceinline__ void gen_k_hole(const GenParams &p, int x, int y, int which, int n,
-                                           typename PR::TC K[4])
-{
-    using TU = typename PR::TU;
-    using TC = typename PR::TC;
-    TC H[4];
-    gen_grad<PR>(p, static_cast<const TU *>(which ? p.up : p.u_in), x, y, (double)(p.step + which), H);
-    H[n] = TC(0);
-    H[2 + n] = TC(0);
-    stress_sum(H, TC(p.lam), TC(p.mu), K);
-}
+    // Ghost value at (dx, dy), bx and by spacings beyond the walls, from the
+    // value a of the node next to the wall(s); step t.
+    __device__ __forceinline__ TU ghost(int aidx, int dx, int dy, int bx, int by, TU a, double t) const
+    {
+        if (by) {
+            const int e = y0 + dy < 0 ? EDGE_YMIN : EDGE_YMAX;
+            a = gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, aidx, t), a, by);
+        }
+        if (bx) {
+            const int e = x0 + dx < 0 ? EDGE_XMIN : EDGE_XMAX;
+            a = gen_ghost<TU>(p.bc[e], gen_uw<TU>(p, e, aidx, t), a, bx);
+        }
+        return a;
+    }
 
-// Pass 1 / 4a: K = P + Pbar from central differences of u (eqs. (10), (15),
-// (27)) on the lattice and its ring of ghost nodes. `which`: 0 = u_n at step
-// n, 1 = the predictor u^p at step n + 1. Sets the flag where J <= 0.
-// EDGE: the launch over the listed nodes with a ghost, wall or hole in
-// their stencil; the other launch takes the interior nodes (no branches), so
-// neither carries the registers of the other's path.
-template <class PR, bool EDGE>
-__global__ void __launch_bounds__(256) stress_pass(const GenParams p, const int which)
-{
-    using TU = typename PR::TU;
-    using TC = typename PR::TC;
-    const TU *u = static_cast<const TU *>(which ? p.up : p.u_in);
-    TC *Kp = static_cast<TC *>(p.K);
-    if (!EDGE) {
-        // lattice rows of ceil(nx / 256) blocks each: the row index is the
-        // same for the whole block (no per-thread division)
-        const int nbx = (p.nx + 255) / 256;
-        const int y = (int)blockIdx.x / nbx;
-        const int x = ((int)blockIdx.x - y * nbx) * 256 + (int)threadIdx.x;
-        if (x < 1 || x > p.nx - 2 || y < 1 || y > p.ny - 2) return;
-        // the four neighbours lie in the lattice: load them before the mask
-        // test so that both loads are in flight together (a hole node's u is
-        // read for nothing; measured faster all the same)
-        const size_t pl = (size_t)p.plane, o = (size_t)y * p.nx + x;
-        TU v[2][4];
+    // tile-relative position of the node next to the wall(s) for a ghost
+    __device__ __forceinline__ void edge_of(int dx, int dy, int bx, int by, int &ex, int &ey) const
+    {
+        ex = dx + (bx ? (x0 + dx < 0 ? bx : -bx) : 0);
+        ey = dy + (by ? (y0 + dy < 0 ? by : -by) : 0);
+    }
+
+    // central-difference gradient of the displacement in LDS at (dx, dy); a
+    // hole neighbour takes the node's own value
+    __device__ __forceinline__ void grad(int dx, int dy, TC H[4]) const
+    {
+        const bool m = holes;
+        const bool hxp = m && hole(dx + 1, dy), hxm = m && hole(dx - 1, dy);
+        const bool hyp = m && hole(dx, dy + 1), hym = m && hole(dx, dy - 1);
+#pragma unroll
         for (int a = 0; a < 2; ++a) {
-            const TU *ua = u + a * pl + o;
-            v[a][0] = ua[1];
-            v[a][1] = ua[-1];
-            v[a][2] = ua[p.nx];
-            v[a][3] = ua[-(ptrdiff_t)p.nx];
+            const TU c = uval(a, dx, dy);
+            const TU xp = hxp ? c : uval(a, dx + 1, dy), xm = hxm ? c : uval(a, dx - 1, dy);
+            const TU yp = hyp ? c : uval(a, dx, dy + 1), ym = hym ? c : uval(a, dx, dy - 1);
+            H[2 * a + 0] = TC((xp - xm) * TU(0.5));
+            H[2 * a + 1] = TC((yp - ym) * TU(0.5));
         }
-        if (!g_inner(p, x, y)) return;
-        TC H[4], K[4];
-        for (int a = 0; a < 2; ++a) {
-            H[2 * a + 0] = TC((v[a][0] - v[a][1]) * TU(0.5));
-            H[2 * a + 1] = TC((v[a][2] - v[a][3]) * TU(0.5));
+    }
+
+    // K at the hole neighbour across axis n as node (dx, dy) sees it
+    __device__ __forceinline__ void k_hole(const TC H[4], int n, TC K[4]) const
+    {
+        TC Hn[4] = {H[0], H[1], H[2], H[3]};
+        Hn[n] = TC(0);
+        Hn[2 + n] = TC(0);
+        stress_sum(Hn, lam, mu, K);
+    }
+
+    // Source S = rho0 b + div K at node (dx, dy) (eq. (23)) from the K in
+    // LDS; across a hole the node's own hole K.
+    __device__ __forceinline__ void source(int dx, int dy, TC S[2]) const
+    {
+        TC kxp[4], kxm[4], kyp[4], kym[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            kxp[c] = kval(c, dx + 1, dy);
+            kxm[c] = kval(c, dx - 1, dy);
+            kyp[c] = kval(c, dx, dy + 1);
+            kym[c] = kval(c, dx, dy - 1);
         }
-        const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
-        for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
-        if (which == 0 && !(J > TC(0))) p.flag[0] = 1u;
-        return;
+        if (holes) {
+            const bool hxp = hole(dx + 1, dy), hxm = hole(dx - 1, dy);
+            const bool hyp = hole(dx, dy + 1), hym = hole(dx, dy - 1);
+            if (hxp || hxm || hyp || hym) {
+                TC H[4], kh[4];
+                grad(dx, dy, H);
+                if (hxp || hxm) {
+                    k_hole(H, 0, kh);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (hxp) kxp[c] = kh[c];
+                        if (hxm) kxm[c] = kh[c];
+                    }
+                }
+                if (hyp || hym) {
+                    k_hole(H, 1, kh);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (hyp) kyp[c] = kh[c];
+                        if (hym) kym[c] = kh[c];
+                    }
+                }
+            }
+        }
+        S[0] = TC(p.bx) + TC(0.5) * (kxp[0] - kxm[0]) + TC(0.5) * (kyp[1] - kym[1]);
+        S[1] = TC(p.by) + TC(0.5) * (kxp[2] - kxm[2]) + TC(0.5) * (kyp[3] - kym[3]);
     }
-    const int w = p.nx + 2;
-    const int tid = blockIdx.x * 256 + threadIdx.x;
-    if (tid >= p.n_edge_k) return;
-    const int s = p.edge_k[tid];
-    const int y = s / w - 1, x = s % w - 1;
-    const double t = (double)(p.step + which);
-    if (g_hole(p, x, y)) {
-        // K seen from the material neighbour across each axis (zero if none)
-        TC kx[4] = {TC(0), TC(0), TC(0), TC(0)}, ky[4] = {TC(0), TC(0), TC(0), TC(0)};
-        const int sx = !g_hole(p, x - 1, y) ? -1 : (!g_hole(p, x + 1, y) ? 1 : 0);
-        const int sy = !g_hole(p, x, y - 1) ? -1 : (!g_hole(p, x, y + 1) ? 1 : 0);
-        if (sx) gen_k_hole<PR>(p, x + sx, y, which, 0, kx);
-        if (sy) gen_k_hole<PR>(p, x, y + sy, which, 1, ky);
-        Kp[k_index(p, 0, x, y)] = kx[0];
-        Kp[k_index(p, 2, x, y)] = kx[2];
-        Kp[k_index(p, 1, x, y)] = ky[1];
-        Kp[k_index(p, 3, x, y)] = ky[3];
-        return;
+
+    // populations of state n at node (dx, dy), site s (with deviation
+    // storage plus the reference equilibrium of the stored state)
+    __device__ __forceinline__ void load_f(int dx, int dy, size_t s, TC jn0, TC jn1, TC f[9]) const
+    {
+        const size_t pl = (size_t)p.plane;
+        const TF *fin = static_cast<const TF *>(p.f_in);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = FS::load(fin, i * pl + s, TC(p.f_inv_scale));
+        if constexpr (FS::kDeviation) {
+            TC H[4], fr[9];
+            grad(dx, dy, H);
+            ref_eq(H, jn0, jn1, fr);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = fr[i] + f[i];
+        }
     }
-    TC H[4], K[4];
-    gen_grad<PR>(p, u, x, y, t, H);
-    const TC J = stress_sum(H, TC(p.lam), TC(p.mu), K);
-    for (int c = 0; c < 4; ++c) Kp[k_index(p, c, x, y)] = K[c];
-    if (which == 0 && x >= 0 && x < p.nx && y >= 0 && y < p.ny && !(J > TC(0))) p.flag[0] = 1u;
-}
 
-// central divergence of K at node (x, y) plus the body force (eq. (23))
-template <class PR>
-__device__ __forceinline__ void gen_source(const GenParams &p, int x, int y, typename PR::TC S[2])
-{
-    using TC = typename PR::TC;
-    const TC *K = static_cast<const TC *>(p.K);
-    TC kxp[4], kxm[4], kyp[4], kym[4];
-    for (int c = 0; c < 4; ++c) {
-        kxp[c] = K[k_index(p, c, x + 1, y)];
-        kxm[c] = K[k_index(p, c, x - 1, y)];
-        kyp[c] = K[k_index(p, c, x, y + 1)];
-        kym[c] = K[k_index(p, c, x, y - 1)];
-    }
-    S[0] = TC(p.bx) + TC(0.5) * (kxp[0] - kxm[0]) + TC(0.5) * (kyp[1] - kym[1]);
-    S[1] = TC(p.by) + TC(0.5) * (kxp[2] - kxm[2]) + TC(0.5) * (kyp[3] - kym[3]);
-}
-
-// Pass 2: source, moments, equilibrium (20), forcing (22) and BGK collision (4)
-template <class PR>
-__global__ void __launch_bounds__(256) collide_pass(const GenParams p)
-{
-    using TJ = typename PR::TJ;
-    using TC = typename PR::TC;
-    const int n = p.nx * p.ny;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int y = s / p.nx, x = s - y * p.nx;
-    if (g_hole(p, x, y)) return;
-    const size_t pl = (size_t)p.plane;
-    const TJ *jin = static_cast<const TJ *>(p.j_in);
-    TC S[2], f[9], fc[9], r, pxx;
-    gen_source<PR>(p, x, y, S);
-    gen_load_f<PR>(p, x, y, (size_t)s, f);
-    collide(f, TC(jin[s]), TC(jin[pl + s]), S[0], S[1], TC(p.omega), fc, r, pxx);
-    TC *fcol = static_cast<TC *>(p.fcol);
-    for (int i = 0; i < 9; ++i) fcol[i * pl + s] = fc[i];
-    TC *Sp = static_cast<TC *>(p.S);
-    Sp[s] = S[0];
-    Sp[pl + s] = S[1];
-}
-
-// Value the wall returns into direction opp(o) at node (x, y) for the link o
-// that leaves through the wall(s): sx, sy are the outward signs of the x
-// and y walls it crosses (0 = none). Bounce-back with the wall momentum
-// (eq. (25)) if a crossed wall is a momentum wall (the mean j* if both are);
-// otherwise anti-bounce-back (eq. (26)) with r_bd and Pbar* at the node:
-// each traction wall's transform gives its normal column, -s T* + K N; a
-// tangential entry keeps the populations' second moment; at a corner the
-// off-diagonal entry is the mean of both walls' values.
-// hole: the walls are those of a hole (traction-free), not of the edges.
-template <class PR>
-__device__ __forceinline__ typename PR::TC gen_wall(const GenParams &p, int x, int y, int o, int sx, int sy,
-                                                    typename PR::TC fco, bool hole)
-{
-    using TC = typename PR::TC;
-    const int ex = sx < 0 ? EDGE_XMIN : EDGE_XMAX, ey = sy < 0 ? EDGE_YMIN : EDGE_YMAX;
-    const bool dx = !hole && sx != 0 && p.bc[ex] == BC_DIRICHLET;
-    const bool dy = !hole && sy != 0 && p.bc[ey] == BC_DIRICHLET;
-    const double tx0 = hole ? 0.0 : p.val[ex][0], tx1 = hole ? 0.0 : p.val[ex][1];
-    const double ty0 = hole ? 0.0 : p.val[ey][0], ty1 = hole ? 0.0 : p.val[ey][1];
-    const TC w = gweight<TC>(o);
-    const TC cx = TC(kGx[o]), cy = TC(kGy[o]);
-    if (dx || dy) {
-        TC jx, jy;
-        if (dx && dy) {
-            jx = TC(0.5 * (p.val[ex][0] + p.val[ey][0]));
-            jy = TC(0.5 * (p.val[ex][1] + p.val[ey][1]));
+    // Value the wall returns into direction opp(o) at node (dx, dy) for the
+    // link o that leaves through the wall(s); sx, sy: outward signs of the
+    // walls crossed. Bounce-back with the wall momentum (eq. (25)) if a
+    // crossed wall is a momentum wall (the mean j* if both are); otherwise
+    // anti-bounce-back (eq. (26)) with r_bd and Pbar* at the node: each
+    // traction wall's column of Pbar* is -s T* + K n, K at the wall the mean
+    // of the node's and the one beyond the wall (a ghost node, or the hole K
+    // the node sees); a tangential entry keeps the populations' second
+    // moment, and at a corner the off-diagonal entry is the mean of both
+    // walls' values. m: r, Pxx, Pyy, Pxy of the node's populations.
+    __device__ __forceinline__ TC wall(int dx, int dy, int o, int sx, int sy, TC fco, bool hole_wall, const TC m[4],
+                                       const TC H[4]) const
+    {
+        const int ex = sx < 0 ? EDGE_XMIN : EDGE_XMAX, ey = sy < 0 ? EDGE_YMIN : EDGE_YMAX;
+        const bool ddx = !hole_wall && sx != 0 && p.bc[ex] == BC_DIRICHLET;
+        const bool ddy = !hole_wall && sy != 0 && p.bc[ey] == BC_DIRICHLET;
+        const TC w = gweight<TC>(o);
+        const TC cx = TC(kGx[o]), cy = TC(kGy[o]);
+        if (ddx || ddy) {
+            TC jx, jy;
+            if (ddx && ddy) {
+                jx = TC(0.5 * (p.val[ex][0] + p.val[ey][0]));
+                jy = TC(0.5 * (p.val[ex][1] + p.val[ey][1]));
+            } else {
+                const int e = ddx ? ex : ey;
+                jx = TC(p.val[e][0]);
+                jy = TC(p.val[e][1]);
+            }
+            return fco - TC(6) * w * (cx * jx + cy * jy);
+        }
+        const double tx0 = hole_wall ? 0.0 : p.val[ex][0], tx1 = hole_wall ? 0.0 : p.val[ex][1];
+        const double ty0 = hole_wall ? 0.0 : p.val[ey][0], ty1 = hole_wall ? 0.0 : p.val[ey][1];
+        const TC r = m[0];
+        TC Pxx = m[1], Pyy = m[2], Pxy = m[3];
+        TC qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
+        if (sx) {
+            TC kb0, kb2;
+            if (holes && hole(dx + sx, dy)) {
+                TC kh[4];
+                k_hole(H, 0, kh);
+                kb0 = kh[0];
+                kb2 = kh[2];
+            } else {
+                kb0 = kval(0, dx + sx, dy);
+                kb2 = kval(2, dx + sx, dy);
+            }
+            const TC sg = TC(sx);
+            qx0 = -sg * TC(tx0) + TC(0.5) * (kval(0, dx, dy) + kb0);
+            qx1 = -sg * TC(tx1) + TC(0.5) * (kval(2, dx, dy) + kb2);
+        }
+        if (sy) {
+            TC kb1, kb3;
+            if (holes && hole(dx, dy + sy)) {
+                TC kh[4];
+                k_hole(H, 1, kh);
+                kb1 = kh[1];
+                kb3 = kh[3];
+            } else {
+                kb1 = kval(1, dx, dy + sy);
+                kb3 = kval(3, dx, dy + sy);
+            }
+            const TC sg = TC(sy);
+            qy0 = -sg * TC(ty0) + TC(0.5) * (kval(1, dx, dy) + kb1);
+            qy1 = -sg * TC(ty1) + TC(0.5) * (kval(3, dx, dy) + kb3);
+        }
+        if (sx && sy) {
+            Pxx = qx0;
+            Pyy = qy1;
+            Pxy = TC(0.5) * (qx1 + qy0);
+        } else if (sy) {
+            Pxy = qy0;
+            Pyy = qy1;
         } else {
-            const int e = dx ? ex : ey;
-            jx = TC(p.val[e][0]);
-            jy = TC(p.val[e][1]);
+            Pxx = qx0;
+            Pxy = qx1;
         }
-        return fco - TC(6) * w * (cx * jx + cy * jy);
+        const TC third = TC(1) / TC(3);
+        const TC axx = Pxx - r * third, ayy = Pyy - r * third;
+        const TC q = axx * cx * cx + TC(2) * Pxy * cx * cy + ayy * cy * cy - (axx + ayy) * third;
+        return -fco + TC(2) * w * (r + TC(4.5) * q);
     }
-    // populations' moments r and Pi at the node (state n)
-    const size_t s = (size_t)y * p.nx + x;
-    TC f[9];
-    gen_load_f<PR>(p, x, y, s, f);
-    const TC r = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const TC dsum = (f[5] + f[6]) + (f[7] + f[8]);
-    TC Pxx = (f[1] + f[3]) + dsum, Pyy = (f[2] + f[4]) + dsum, Pxy = (f[5] - f[6]) + (f[7] - f[8]);
-    const TC *K = static_cast<const TC *>(p.K);
-    TC qx0 = 0, qx1 = 0, qy0 = 0, qy1 = 0;
-    // K at a wall: the mean of the node and the neighbour beyond the wall (a
-    // ghost node, or a hole node holding the K its material neighbour sees)
-    if (sx) {  // x wall: column x of Pbar*, q_a = -s T_a + K_ax
-        const TC sg = TC(sx);
-        qx0 = -sg * TC(tx0) + TC(0.5) * (K[k_index(p, 0, x, y)] + K[k_index(p, 0, x + sx, y)]);
-        qx1 = -sg * TC(tx1) + TC(0.5) * (K[k_index(p, 2, x, y)] + K[k_index(p, 2, x + sx, y)]);
-    }
-    if (sy) {  // y wall: column y, q_a = -s T_a + K_ay
-        const TC sg = TC(sy);
-        qy0 = -sg * TC(ty0) + TC(0.5) * (K[k_index(p, 1, x, y)] + K[k_index(p, 1, x, y + sy)]);
-        qy1 = -sg * TC(ty1) + TC(0.5) * (K[k_index(p, 3, x, y)] + K[k_index(p, 3, x, y + sy)]);
-    }
-    if (sx && sy) {
-        Pxx = qx0;
-        Pyy = qy1;
-        Pxy = TC(0.5) * (qx1 + qy0);
-    } else if (sy) {
-        Pxy = qy0;
-        Pyy = qy1;
-    } else {
-        Pxx = qx0;
-        Pxy = qx1;
-    }
-    // A = Pbar* - r/3 I; A : (e e - I/3)
-    const TC third = TC(1) / TC(3);
-    const TC axx = Pxx - r * third, ayy = Pyy - r * third;
-    const TC q = axx * cx * cx + TC(2) * Pxy * cx * cy + ayy * cy * cy - (axx + ayy) * third;
-    return -fco + TC(2) * w * (r + TC(4.5) * q);
-}
 
-// Pull of the nine populations of a node next to an edge or a hole: a link
-// whose source lies beyond a wall, or in a hole, takes the wall's rule.
-template <class PR>
-__device__ __forceinline__ void stream_edge(const GenParams &p, int x, int y, int s, bool perx, bool pery,
-                                         typename PR::TC fn[9])
-{
-    using TC = typename PR::TC;
-    const size_t pl = (size_t)p.plane;
-    const TC *fcol = static_cast<const TC *>(p.fcol);
-    for (int i = 0; i < 9; ++i) {
-        int sxp = x - kGx[i], syp = y - kGy[i];
-        if (i && g_hole(p, sxp, syp)) {
-            // the link o = opp(i) enters a hole: the wall its axis step
-            // enters, or both for the diagonal through a hole corner
-            const int o = kGopp[i];
-            const bool hx = kGx[o] && g_hole(p, x + kGx[o], y), hy = kGy[o] && g_hole(p, x, y + kGy[o]);
-            const bool both = !hx && !hy;
-            fn[i] = gen_wall<PR>(p, x, y, o, (hx || both) ? kGx[o] : 0, (hy || both) ? kGy[o] : 0,
-                                 fcol[o * pl + s], true);
-            continue;
+    // Pull streaming (eq. (5)) at node (dx, dy), site s: a link whose source
+    // lies beyond a wall or in a hole takes the wall's rule.
+    __device__ __forceinline__ void stream(int dx, int dy, size_t s, TC jn0, TC jn1, TC fn[9]) const
+    {
+        constexpr int R = C::RF;
+        const int xn = x0 + dx, yn = y0 + dy;  // unwrapped: a source beyond a wall leaves [0, n)
+        bool any = false;
+        int cross[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int sx = dx - kGx[i], sy = dy - kGy[i];
+            int c = 0;
+            if (i && holes && hole(sx, sy)) {
+                c = 4;
+            } else {
+                const bool bx = !perx && (xn - kGx[i] < 0 || xn - kGx[i] >= p.nx);
+                const bool by = !pery && (yn - kGy[i] < 0 || yn - kGy[i] >= p.ny);
+                c = (bx ? 1 : 0) | (by ? 2 : 0);
+            }
+            cross[i] = c;
+            any |= c != 0;
+            fn[i] = L.fc[i][at<R>(sx, sy)];
         }
-        bool cx = sxp < 0 || sxp >= p.nx, cy = syp < 0 || syp >= p.ny;
-        if (cx && perx) {
-            sxp = (sxp + p.nx) % p.nx;
-            cx = false;
-        }
-        if (cy && pery) {
-            syp = (syp + p.ny) % p.ny;
-            cy = false;
-        }
-        if (!cx && !cy) {
-            fn[i] = fcol[i * pl + (size_t)syp * p.nx + sxp];
-        } else {
+        if (!any) return;
+        TC f[9], H[4], m[4];
+        load_f(dx, dy, s, jn0, jn1, f);
+        grad(dx, dy, H);
+        m[0] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const TC dsum = (f[5] + f[6]) + (f[7] + f[8]);
+        m[1] = (f[1] + f[3]) + dsum;
+        m[2] = (f[2] + f[4]) + dsum;
+        m[3] = (f[5] - f[6]) + (f[7] - f[8]);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (!cross[i]) continue;
             const int o = kGopp[i];  // the link that left through the wall
-            fn[i] = gen_wall<PR>(p, x, y, o, cx ? kGx[o] : 0, cy ? kGy[o] : 0, fcol[o * pl + s], false);
+            const TC fco = L.fc[o][at<R>(dx, dy)];
+            if (cross[i] == 4) {
+                // the wall its axis step enters, or both for the diagonal
+                // through a hole corner
+                const bool hx = kGx[o] && hole(dx + kGx[o], dy), hy = kGy[o] && hole(dx, dy + kGy[o]);
+                const bool both = !hx && !hy;
+                fn[i] = wall(dx, dy, o, (hx || both) ? kGx[o] : 0, (hy || both) ? kGy[o] : 0, fco, true, m, H);
+            } else {
+                fn[i] = wall(dx, dy, o, (cross[i] & 1) ? kGx[o] : 0, (cross[i] & 2) ? kGy[o] : 0, fco, false, m, H);
+            }
         }
     }
-}
 
-// Pass 3: pull streaming (5) with the wall rules (Sec. 6), storage of the
-// new populations, their first moment jf and the predictor u^p (PC), or the
-// new j and u directly (explicit).
-template <class PR, bool EDGE>
-__global__ void __launch_bounds__(256) stream_pass(const GenParams p)
-{
-    using TF = typename PR::TF;
-    using TU = typename PR::TU;
-    using TJ = typename PR::TJ;
-    using TC = typename PR::TC;
-    using FS = FStore<TF>;
-    const int tid = blockIdx.x * 256 + threadIdx.x;
-    if (tid >= (EDGE ? p.n_edge_f : p.nx * p.ny)) return;
-    const int s = EDGE ? p.edge_f[tid] : tid;
-    const int y = s / p.nx, x = s - y * p.nx;
-    const size_t pl = (size_t)p.plane;
-    if (!EDGE && !g_inner(p, x, y)) return;  // (hole nodes are in no launch: their state is never read)
-    const TC *fcol = static_cast<const TC *>(p.fcol);
-    const bool perx = p.bc[EDGE_XMIN] == BC_PERIODIC, pery = p.bc[EDGE_YMIN] == BC_PERIODIC;
-    TC fn[9];
-    if (!EDGE) {
-        for (int i = 0; i < 9; ++i) fn[i] = fcol[i * pl + (size_t)(s - kGy[i] * p.nx - kGx[i])];
-    } else {
-        stream_edge<PR>(p, x, y, s, perx, pery, fn);
+    // Fill the ghost nodes of ring R in L.u from the nodes next to the walls
+    // (step t). The caller has written the plate's nodes and synchronised.
+    template <int R>
+    __device__ __forceinline__ void ghost_fill(double t)
+    {
+        if ((perx && pery) || !active) return;
+        constexpr int NR = C::N(R), PR_ = (NR + C::BLOCK - 1) / C::BLOCK;
+#pragma unroll
+        for (int q = 0; q < PR_; ++q) {
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NR) continue;
+            const int dy = w / C::W(R) - R, dx = w % C::W(R) - R;
+            int x, y, bx, by;
+            coords(dx, dy, x, y, bx, by);
+            if (!(bx | by) || bx > 2 || by > 2) continue;
+            int ex, ey;
+            edge_of(dx, dy, bx, by, ex, ey);
+#pragma unroll
+            for (int a = 0; a < 2; ++a) L.u[a][at<C::RU>(dx, dy)] = ghost(a, dx, dy, bx, by, uval(a, ex, ey), t);
+        }
     }
-    if constexpr (FS::kDeviation) {
-        // stored by store_pass once the new state's gradient is known
-        TC *fnw = static_cast<TC *>(p.fnew);
-        for (int i = 0; i < 9; ++i) fnw[i * pl + s] = fn[i];
-    } else {
+
+    // K = P + Pbar (eqs. (15), (27)) of the displacement in LDS on ring R;
+    // flag: J <= 0 at a node of the tile (u_n only)
+    template <int R>
+    __device__ __forceinline__ void stress(bool flag)
+    {
+        constexpr int NR = C::N(R), PR_ = (NR + C::BLOCK - 1) / C::BLOCK;
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < PR_; ++q) {
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NR || !active) continue;
+            const int dy = w / C::W(R) - R, dx = w % C::W(R) - R;
+            const unsigned char kd = kind(dx, dy);
+            if (kd & SITE_HOLE) continue;
+            TC H[4], K[4];
+            grad(dx, dy, H);
+            const TC J = stress_sum(H, lam, mu, K);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) L.k[c][at<C::RK>(dx, dy)] = K[c];
+            if (flag && (kd & SITE_NODE) && dx >= 0 && dx < C::TW && dy >= 0 && dy < C::TH &&
+                x0 + dx < p.nx && y0 + dy < p.ny && !(J > TC(0)))
+                bad = true;
+        }
+        if (bad) p.flag[0] = 1u;
+    }
+
+    __device__ __forceinline__ bool in_tile(int dx, int dy) const
+    {
+        return dx >= 0 && dx < C::TW && dy >= 0 && dy < C::TH && x0 + dx < p.nx && y0 + dy < p.ny;
+    }
+
+    __device__ __forceinline__ void run()
+    {
+        const size_t pl = (size_t)p.plane;
+        const double tn = (double)p.step, tn1 = (double)(p.step + 1);
+        const TF *fin = static_cast<const TF *>(p.f_in);
+        const TU *uin = static_cast<const TU *>(p.u_in);
+        const TJ *jin = static_cast<const TJ *>(p.j_in);
+        TU *uout = static_cast<TU *>(p.u_out);
+        TJ *jout = static_cast<TJ *>(p.j_out);
         const bool sr = FS::kStochastic && p.sr;
         const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
-        store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, fn, TC(p.f_scale), sr, key);
-    }
-    const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
-    const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
-    const TC *S = static_cast<const TC *>(p.S);
-    const TU *u = static_cast<const TU *>(p.u_in);
-    const TJ *jin = static_cast<const TJ *>(p.j_in);
-    const TC jn0 = TC(jin[s]), jn1 = TC(jin[pl + s]);
-    if (p.pc) {
-        TC *jf = static_cast<TC *>(p.jf);
-        jf[s] = jfx;
-        jf[pl + s] = jfy;
-        TC jpx = jfx + TC(0.5) * S[s], jpy = jfy + TC(0.5) * S[pl + s];
-        if (p.pc == 2) {
-            const TJ *jold = static_cast<const TJ *>(p.j_out);
-            jpx = TC(2) * jn0 - TC(jold[s]);
-            jpy = TC(2) * jn1 - TC(jold[pl + s]);
+        const TC inv = TC(p.f_inv_scale);
+        bool bad = false;
+
+        // Every load of the state is issued here, before the first barrier
+        // waits for all of them at once: f_n and j_n of the collision ring
+        // into registers, u_n (or the edge value a ghost is made from) and
+        // the mask on the u ring.
+        constexpr int NF = C::N(C::RF), PF = (NF + C::BLOCK - 1) / C::BLOCK;
+        constexpr int NU = C::N(C::RU), PU = (NU + C::BLOCK - 1) / C::BLOCK;
+        TF fr[PF][9];
+        TJ jr[PF][2];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fr[q][i] = TF(0);
+            jr[q][0] = jr[q][1] = TJ(0);
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NF) continue;
+            const int dy = w / C::W(C::RF) - C::RF, dx = w % C::W(C::RF) - C::RF;
+            int x, y, bx, by;
+            coords(dx, dy, x, y, bx, by);
+            if (bx | by) continue;
+            const size_t s = (size_t)y * p.nx + x;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fr[q][i] = fin[i * pl + s];
+            jr[q][0] = jin[s];
+            jr[q][1] = jin[pl + s];
         }
-        TU *up = static_cast<TU *>(p.up);
-        up[s] = u[s] + TU(TC(0.5) * (jpx + jn0));
-        up[pl + s] = u[pl + s] + TU(TC(0.5) * (jpy + jn1));
+        TU ur[PU][2];
+        unsigned char mr[PU];
+#pragma unroll
+        for (int q = 0; q < PU; ++q) {
+            ur[q][0] = ur[q][1] = TU(0);
+            mr[q] = 1;
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NU) continue;
+            const int dy = w / C::W(C::RU) - C::RU, dx = w % C::W(C::RU) - C::RU;
+            int x, y, bx, by;
+            coords(dx, dy, x, y, bx, by);
+            if (bx > 2 || by > 2) continue;
+            const int xe = x < 0 ? 0 : (x >= p.nx ? p.nx - 1 : x);
+            const int ye = y < 0 ? 0 : (y >= p.ny ? p.ny - 1 : y);
+            const size_t s = (size_t)ye * p.nx + xe;
+            ur[q][0] = uin[s];
+            ur[q][1] = uin[pl + s];
+            if (p.mask && !(bx | by)) mr[q] = p.mask[s];
+        }
+#pragma unroll
+        for (int q = 0; q < PU; ++q) {
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NU) continue;
+            const int dy = w / C::W(C::RU) - C::RU, dx = w % C::W(C::RU) - C::RU;
+            int x, y, bx, by;
+            coords(dx, dy, x, y, bx, by);
+            unsigned char kd = SITE_GHOST;
+            TU v0 = ur[q][0], v1 = ur[q][1];
+            if (!(bx | by)) {
+                kd = (mr[q] & 1) ? SITE_NODE : SITE_HOLE;
+            } else if (bx <= 2 && by <= 2) {
+                v0 = ghost(0, dx, dy, bx, by, v0, tn);
+                v1 = ghost(1, dx, dy, bx, by, v1, tn);
+            }
+            L.kind[w] = kd;
+            L.u[0][w] = v0;
+            L.u[1][w] = v1;
+        }
+        __syncthreads();
+
+        stress<C::RK>(true);
+        __syncthreads();
+
+        // source, populations and collision on the collision ring
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NF) continue;
+            const int dy = w / C::W(C::RF) - C::RF, dx = w % C::W(C::RF) - C::RF;
+            if (!active || !(kind(dx, dy) & SITE_NODE)) continue;
+            const TC jn0 = TC(jr[q][0]), jn1 = TC(jr[q][1]);
+            TC S[2], f[9], fc[9], r, pxx;
+            source(dx, dy, S);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = FS::cvt(fr[q][i], inv);
+            if constexpr (FS::kDeviation) {
+                TC H[4], fq[9];
+                grad(dx, dy, H);
+                ref_eq(H, jn0, jn1, fq);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) f[i] = fq[i] + f[i];
+            }
+            collide(f, jn0, jn1, S[0], S[1], omega, fc, r, pxx);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) L.fc[i][w] = fc[i];
+            L.jn[0][w] = jn0;
+            L.jn[1][w] = jn1;
+        }
+        __syncthreads();
+
+        // streaming and moments on the streaming ring: the predictor u^p
+        // (PC) or the new state (explicit), held in registers until the
+        // ring's reads of L.u are over
+        constexpr int NS = C::N(C::RS), PS = (NS + C::BLOCK - 1) / C::BLOCK;
+        TU un[PS][2];
+#pragma unroll
+        for (int q = 0; q < PS; ++q) {
+            un[q][0] = un[q][1] = TU(0);
+            const int w = threadIdx.x + q * C::BLOCK;
+            if (w >= NS) continue;
+            const int dy = w / C::W(C::RS) - C::RS, dx = w % C::W(C::RS) - C::RS;
+            const unsigned char kd = kind(dx, dy);
+            int x, y, bx, by;
+            coords(dx, dy, x, y, bx, by);
+            const size_t s = (size_t)y * p.nx + x;
+            if (!active || !(kd & SITE_NODE)) {
+                if ((kd & SITE_HOLE) && MODE == 0 && in_tile(dx, dy)) {
+                    uout[s] = uout[pl + s] = TU(0);
+                    jout[s] = jout[pl + s] = TJ(0);
+                }
+                continue;
+            }
+            const TC jn0 = L.jn[0][at<C::RF>(dx, dy)], jn1 = L.jn[1][at<C::RF>(dx, dy)];
+            TC fn[9], S[2];
+            stream(dx, dy, s, jn0, jn1, fn);
+            if (in_tile(dx, dy)) {
+                if constexpr (C::DEV) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) L.fn[i][dy * C::TW + dx] = fn[i];
+                } else {
+                    store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, fn, TC(p.f_scale), sr, key);
+                }
+            }
+            const TC jfx = ((fn[1] - fn[3]) + (fn[5] - fn[6])) + (fn[8] - fn[7]);
+            const TC jfy = ((fn[2] - fn[4]) + (fn[5] + fn[6])) - (fn[7] + fn[8]);
+            source(dx, dy, S);
+            const TU u0 = uval(0, dx, dy), u1 = uval(1, dx, dy);
+            if constexpr (MODE) {
+                if (dx >= -C::RC && dx < C::TW + C::RC && dy >= -C::RC && dy < C::TH + C::RC) {
+                    const int c = at<C::RC>(dx, dy);
+                    L.jc[0][c] = jfx;
+                    L.jc[1][c] = jfy;
+                    L.un[0][c] = u0;
+                    L.un[1][c] = u1;
+                }
+                TC jpx = jfx + TC(0.5) * S[0], jpy = jfy + TC(0.5) * S[1];
+                if (p.pc == 2) {
+                    const TJ *jold = static_cast<const TJ *>(p.j_prev);
+                    jpx = TC(2) * jn0 - TC(jold[s]);
+                    jpy = TC(2) * jn1 - TC(jold[pl + s]);
+                }
+                un[q][0] = u0 + TU(TC(0.5) * (jpx + jn0));
+                un[q][1] = u1 + TU(TC(0.5) * (jpy + jn1));
+            } else {
+                const TC j0 = jfx + TC(0.5) * S[0], j1 = jfy + TC(0.5) * S[1];
+                un[q][0] = u0 + TU(TC(0.5) * (j0 + jn0));
+                un[q][1] = u1 + TU(TC(0.5) * (j1 + jn1));
+                if constexpr (C::DEV) {
+                    L.jc[0][at<C::RC>(dx, dy)] = j0;
+                    L.jc[1][at<C::RC>(dx, dy)] = j1;
+                }
+                if (in_tile(dx, dy)) {
+                    uout[s] = un[q][0];
+                    uout[pl + s] = un[q][1];
+                    jout[s] = TJ(j0);
+                    jout[pl + s] = TJ(j1);
+                    if (!isfinite((double)un[q][0]) || !isfinite((double)un[q][1]) || !isfinite((double)j0) ||
+                        !isfinite((double)j1))
+                        bad = true;
+                }
+            }
+        }
+        __syncthreads();
+
+        if constexpr (MODE) {
+            // K of u^p on its ring, then the corrector
+#pragma unroll
+            for (int q = 0; q < PS; ++q) {
+                const int w = threadIdx.x + q * C::BLOCK;
+                if (w < NS) {
+                    const int dy = w / C::W(C::RS) - C::RS, dx = w % C::W(C::RS) - C::RS;
+                    L.u[0][at<C::RU>(dx, dy)] = un[q][0];
+                    L.u[1][at<C::RU>(dx, dy)] = un[q][1];
+                }
+            }
+            __syncthreads();
+            ghost_fill<C::RS>(tn1);
+            __syncthreads();
+            stress<C::RP>(false);
+            __syncthreads();
+
+            constexpr int NC = C::N(C::RC), PC_ = (NC + C::BLOCK - 1) / C::BLOCK;
+#pragma unroll
+            for (int q = 0; q < PC_; ++q) {
+                const int w = threadIdx.x + q * C::BLOCK;
+                if (w >= NC) continue;
+                const int dy = w / C::W(C::RC) - C::RC, dx = w % C::W(C::RC) - C::RC;
+                const unsigned char kd = kind(dx, dy);
+                int x, y, bx, by;
+                coords(dx, dy, x, y, bx, by);
+                const size_t s = (size_t)y * p.nx + x;
+                if (!active || !(kd & SITE_NODE)) {
+                    if ((kd & SITE_HOLE) && in_tile(dx, dy)) {
+                        uout[s] = uout[pl + s] = TU(0);
+                        jout[s] = jout[pl + s] = TJ(0);
+                    }
+                    continue;
+                }
+                TC Sp[2];
+                source(dx, dy, Sp);
+                const int f = at<C::RF>(dx, dy);
+                const TC jn0 = L.jn[0][f], jn1 = L.jn[1][f];
+                const TC j0 = L.jc[0][w] + TC(0.5) * Sp[0], j1 = L.jc[1][w] + TC(0.5) * Sp[1];
+                const TU u0 = L.un[0][w] + TU(TC(0.5) * (j0 + jn0));
+                const TU u1 = L.un[1][w] + TU(TC(0.5) * (j1 + jn1));
+                if constexpr (C::DEV) {
+                    // u_{n+1} and j_{n+1} in place of this site's u_n and jf
+                    L.un[0][w] = u0;
+                    L.un[1][w] = u1;
+                    L.jc[0][w] = j0;
+                    L.jc[1][w] = j1;
+                }
+                if (in_tile(dx, dy)) {
+                    uout[s] = u0;
+                    uout[pl + s] = u1;
+                    jout[s] = TJ(j0);
+                    jout[pl + s] = TJ(j1);
+                    if (!isfinite((double)u0) || !isfinite((double)u1) || !isfinite((double)j0) ||
+                        !isfinite((double)j1))
+                        bad = true;
+                }
+            }
+            if constexpr (C::DEV) {
+                __syncthreads();
+                for (int w = threadIdx.x; w < NC; w += C::BLOCK) {
+                    const int dy = w / C::W(C::RC) - C::RC, dx = w % C::W(C::RC) - C::RC;
+                    if (kind(dx, dy) & SITE_NODE) {
+                        L.u[0][at<C::RU>(dx, dy)] = L.un[0][w];
+                        L.u[1][at<C::RU>(dx, dy)] = L.un[1][w];
+                    }
+                }
+            }
+        } else if constexpr (C::DEV) {
+            // explicit: the new state of the update ring is in registers
+#pragma unroll
+            for (int q = 0; q < PS; ++q) {
+                const int w = threadIdx.x + q * C::BLOCK;
+                if (w < NS) {
+                    const int dy = w / C::W(C::RS) - C::RS, dx = w % C::W(C::RS) - C::RS;
+                    L.u[0][at<C::RU>(dx, dy)] = un[q][0];
+                    L.u[1][at<C::RU>(dx, dy)] = un[q][1];
+                }
+            }
+        }
+
+        if constexpr (C::DEV) {
+            // store the new populations' deviation from the reference
+            // equilibrium of the new state (the gradient of u_{n+1} and
+            // j_{n+1}), as the next step's loads rebuild it
+            __syncthreads();
+            ghost_fill<C::RC>(tn1);
+            __syncthreads();
+            for (int w = threadIdx.x; w < C::TW * C::TH; w += C::BLOCK) {
+                const int dy = w / C::TW, dx = w % C::TW;
+                if (!in_tile(dx, dy) || !(kind(dx, dy) & SITE_NODE)) continue;
+                int x, y, bx, by;
+                coords(dx, dy, x, y, bx, by);
+                const size_t s = (size_t)y * p.nx + x;
+                TC H[4], fq[9], dv[9];
+                grad(dx, dy, H);
+                const int c = at<C::RC>(dx, dy);
+                ref_eq(H, TC(TJ(L.jc[0][c])), TC(TJ(L.jc[1][c])), fq);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) dv[i] = L.fn[i][w] - fq[i];
+                store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, dv, TC(p.f_scale), sr, key);
+            }
+        }
+        if (bad) p.flag[0] = 1u;
+    }
+};
+
+// One block per tile. Blocks are dealt round-robin to the 8 XCDs; the remap
+// gives each XCD a run of consecutive tiles, row by row of tiles, so the
+// windows of horizontal neighbours overlap in one L2. (Column by column,
+// which puts vertical neighbours one after another, measured 10 % slower.)
+template <class PR, int MODE>
+__global__ void __launch_bounds__(kTileBlock) tile_step_kernel(const GenParams p, const int nbx, const int nb)
+{
+    using C = TileCfg<PR, MODE>;
+    __shared__ TileLdsG<PR, MODE> lds;
+    const int bid = blockIdx.x;
+    const int xq = nb >> 3, xr = nb & 7;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int logical = xcd * xq + min(xcd, xr) + loc;
+    const int ty = logical / nbx, tx = logical - ty * nbx;
+    const unsigned char tf = p.tiles ? p.tiles[logical] : (unsigned char)TILE_MATERIAL;
+    TileStep<PR, MODE> t(p, lds, tx * C::TW, ty * C::TH, tf);
+    t.run();
+}
+
+// Tile width, height and the u ring (the window's margin) of the general
+// step of a precision and scheme (pc: predictor-corrector or extrapolation),
+// for the host's tile table.
+template <class PR>
+inline void tile_shape(bool pc, int &tw, int &th, int &ru)
+{
+    if (pc) {
+        using C = TileCfg<PR, 1>;
+        tw = C::TW, th = C::TH, ru = C::RU;
     } else {
-        const TC j0 = jfx + TC(0.5) * S[s], j1 = jfy + TC(0.5) * S[pl + s];
-        const TU u0 = u[s] + TU(TC(0.5) * (j0 + jn0)), u1 = u[pl + s] + TU(TC(0.5) * (j1 + jn1));
-        static_cast<TU *>(p.u_out)[s] = u0;
-        static_cast<TU *>(p.u_out)[pl + s] = u1;
-        static_cast<TJ *>(p.j_out)[s] = TJ(j0);
-        static_cast<TJ *>(p.j_out)[pl + s] = TJ(j1);
-        if (!isfinite((double)u0) || !isfinite((double)u1) || !isfinite((double)j0) || !isfinite((double)j1))
-            p.flag[0] = 1u;
+        using C = TileCfg<PR, 0>;
+        tw = C::TW, th = C::TH, ru = C::RU;
     }
 }
 
-// Pass 4b (PC): S^p from K(u^p), j_{n+1} = jf + S^p / 2 and the trapezoidal
-// displacement update (eq. (24)).
-template <class PR>
-__global__ void __launch_bounds__(256) update_pass(const GenParams p)
-{
-    using TU = typename PR::TU;
-    using TJ = typename PR::TJ;
-    using TC = typename PR::TC;
-    const int n = p.nx * p.ny;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int y = s / p.nx, x = s - y * p.nx;
-    const size_t pl = (size_t)p.plane;
-    if (g_hole(p, x, y)) {
-        static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
-        static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
-        return;
-    }
-    TC Sp[2];
-    gen_source<PR>(p, x, y, Sp);
-    const TC *jf = static_cast<const TC *>(p.jf);
-    const TU *u = static_cast<const TU *>(p.u_in);
-    const TJ *jin = static_cast<const TJ *>(p.j_in);
-    const TC j0 = jf[s] + TC(0.5) * Sp[0], j1 = jf[pl + s] + TC(0.5) * Sp[1];
-    const TU u0 = u[s] + TU(TC(0.5) * (j0 + TC(jin[s]))), u1 = u[pl + s] + TU(TC(0.5) * (j1 + TC(jin[pl + s])));
-    static_cast<TU *>(p.u_out)[s] = u0;
-    static_cast<TU *>(p.u_out)[pl + s] = u1;
-    static_cast<TJ *>(p.j_out)[s] = TJ(j0);
-    static_cast<TJ *>(p.j_out)[pl + s] = TJ(j1);
-    if (!isfinite((double)u0) || !isfinite((double)u1) || !isfinite((double)j0) || !isfinite((double)j1))
-        p.flag[0] = 1u;
-}
+// Upper bound of the tile table's entries for an nx x ny plate.
+inline size_t max_tiles(int nx, int ny) { return (size_t)((nx + 31) / 32) * (size_t)((ny + 3) / 4); }
 
-// Last pass with deviation storage: the new populations minus the reference
-// equilibrium of the new state (the gradient of u_{n+1} at step n + 1 and
-// j_{n+1}, as the next step's loads rebuild it), rounded to the storage type.
-template <class PR>
-__global__ void __launch_bounds__(256) store_pass(const GenParams p)
-{
-    using TF = typename PR::TF;
-    using TU = typename PR::TU;
-    using TJ = typename PR::TJ;
-    using TC = typename PR::TC;
-    using FS = FStore<TF>;
-    const int n = p.nx * p.ny;
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int y = s / p.nx, x = s - y * p.nx;
-    if (g_hole(p, x, y)) return;
-    const size_t pl = (size_t)p.plane;
-    TC H[4], fr[9], dv[9];
-    gen_grad<PR>(p, static_cast<const TU *>(p.u_out), x, y, (double)(p.step + 1), H);
-    const TJ *jo = static_cast<const TJ *>(p.j_out);
-    ref_eq(H, TC(jo[s]), TC(jo[pl + s]), fr);
-    const TC *fnw = static_cast<const TC *>(p.fnew);
-    for (int i = 0; i < 9; ++i) dv[i] = fnw[i * pl + s] - fr[i];
-    const bool sr = FS::kStochastic && p.sr;
-    const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
-    store_site<FS>(static_cast<TF *>(p.f_out), pl, (uint32_t)s, dv, TC(p.f_scale), sr, key);
-}
-
-// Scratch bytes of the passes for an nx x ny plate.
+// Scratch bytes of the general step for an nx x ny plate: j_{n-1} of the
+// extrapolation variant.
 template <class PR>
 inline size_t general_scratch_bytes(int nx, int ny)
 {
-    using TU = typename PR::TU;
-    using TC = typename PR::TC;
-    const size_t n = (size_t)nx * ny, ne = k_pitch(nx) * (ny + 2);
-    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    const size_t fnew = FStore<typename PR::TF>::kDeviation ? al(9 * n * sizeof(TC)) : 0;
-    return al(4 * ne * sizeof(TC)) + al(9 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) + al(2 * n * sizeof(TC)) +
-           al(2 * n * sizeof(TU)) + fnew;
+    return ((size_t)2 * nx * ny * sizeof(typename PR::TJ) + 255) / 256 * 256;
 }
 
-// Enqueue one time step of the passes on the stream; scratch is
-// general_scratch_bytes<PR>(nx, ny) bytes, 256-byte aligned.
+// Enqueue one time step on the stream; scratch is general_scratch_bytes<PR>
+// bytes, 256-byte aligned.
 template <class PR>
 hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
 {
-    using TC = typename PR::TC;
-    const size_t n = (size_t)p.nx * p.ny, ne = k_pitch(p.nx) * (p.ny + 2);
-    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
-    size_t off = 0;
-    p.K = scratch + off;
-    off += al(4 * ne * sizeof(TC));
-    p.fcol = scratch + off;
-    off += al(9 * n * sizeof(TC));
-    p.S = scratch + off;
-    off += al(2 * n * sizeof(TC));
-    p.jf = scratch + off;
-    off += al(2 * n * sizeof(TC));
-    p.up = scratch + off;
-    off += al(2 * n * sizeof(typename PR::TU));
-    p.fnew = scratch + off;
-    const int nb = (int)((n + 255) / 256), nbi = (p.nx + 255) / 256 * p.ny;
-    const int nbk = (p.n_edge_k + 255) / 256, nbf = (p.n_edge_f + 255) / 256;
-    hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbi), dim3(256), 0, st, p, 0);
-    if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 0);
-    hipLaunchKernelGGL((collide_pass<PR>), dim3(nb), dim3(256), 0, st, p);
-    hipLaunchKernelGGL((stream_pass<PR, false>), dim3(nb), dim3(256), 0, st, p);
-    if (nbf) hipLaunchKernelGGL((stream_pass<PR, true>), dim3(nbf), dim3(256), 0, st, p);
-    if (p.pc) {
-        hipLaunchKernelGGL((stress_pass<PR, false>), dim3(nbi), dim3(256), 0, st, p, 1);
-        if (nbk) hipLaunchKernelGGL((stress_pass<PR, true>), dim3(nbk), dim3(256), 0, st, p, 1);
-        hipLaunchKernelGGL((update_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    if (p.pc == 2) {
+        // j_{n-1} sits in the output buffer of j, which the tiles overwrite
+        // while their neighbours still read it: keep a copy
+        const size_t bytes = (size_t)2 * p.nx * p.ny * sizeof(typename PR::TJ);
+        const hipError_t e = hipMemcpyAsync(scratch, p.j_out, bytes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        p.j_prev = scratch;
     }
-    if constexpr (FStore<typename PR::TF>::kDeviation) hipLaunchKernelGGL((store_pass<PR>), dim3(nb), dim3(256), 0, st, p);
+    if (p.pc) {
+        using C = TileCfg<PR, 1>;
+        const int nbx = (p.nx + C::TW - 1) / C::TW, nb = nbx * ((p.ny + C::TH - 1) / C::TH);
+        hipLaunchKernelGGL((tile_step_kernel<PR, 1>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
+    } else {
+        using C = TileCfg<PR, 0>;
+        const int nbx = (p.nx + C::TW - 1) / C::TW, nb = nbx * ((p.ny + C::TH - 1) / C::TH);
+        hipLaunchKernelGGL((tile_step_kernel<PR, 0>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
+    }
     return hipGetLastError();
 }
 
-// Each precision's passes are compiled in an object of their own
+// Each precision's kernels are compiled in an object of their own
 // (instantiate.hip).
 extern template hipError_t general_step<PrecF64>(GenParams, char *, hipStream_t);
 extern template hipError_t general_step<PrecF32>(GenParams, char *, hipStream_t);

@@ -24,9 +24,9 @@ struct Layout {
     StateLayout state;
     size_t staging, staging_bytes;
     size_t partials, small, total;
-    size_t scratch, total_walled;  // scratch of the general passes (walls on the x edges)
+    size_t scratch, total_walled;  // scratch of the general step (walls on the x edges)
     size_t mask;                   // material mask [ny][nx] bytes, after the scratch
-    size_t edge_k, edge_f;         // node lists of the edge launches (int32), after the mask
+    size_t tiles;                  // tile table of the general step (TILE_* bytes), after the mask
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -55,9 +55,8 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.total = off;
     L.scratch = off;
     L.mask = align_up(off + general_scratch(nx, ny, p));
-    L.edge_k = align_up(L.mask + (size_t)nx * ny);
-    L.edge_f = align_up(L.edge_k + sizeof(int) * (size_t)(nx + 2) * (ny + 2));
-    L.total_walled = align_up(L.edge_f + sizeof(int) * (size_t)nx * ny);
+    L.tiles = align_up(L.mask + (size_t)nx * ny);
+    L.total_walled = align_up(L.tiles + max_tiles(nx, ny));
     return L;
 }
 
@@ -96,11 +95,8 @@ struct lbm_solver {
     int spl = 1;  // time steps per launch (1, or 2 with the predictor-corrector)
     int sr = 0;   // stochastic rounding of 16-bit populations
     unsigned long long seed = 0;
-    bool force_general = false;  // run the general passes even without x walls
+    bool force_general = false;  // run the general step even without x walls
     bool has_mask = false;       // holes (lbm_set_mask)
-    std::vector<unsigned char> mask_host;  // copy of the mask, for the edge lists
-    bool edges_dirty = true;     // the edge lists need rebuilding (edges or mask changed)
-    int n_edge_k = 0, n_edge_f = 0;
 
     bool general() const
     {
@@ -109,6 +105,10 @@ struct lbm_solver {
     const unsigned char *mask_ptr() const
     {
         return has_mask ? reinterpret_cast<const unsigned char *>(ws + L.mask) : nullptr;
+    }
+    const unsigned char *tiles_ptr() const
+    {
+        return has_mask ? reinterpret_cast<const unsigned char *>(ws + L.tiles) : nullptr;
     }
     std::string err;
 
@@ -381,9 +381,6 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
         // the opposite edge stops being periodic: it becomes a wall at rest until set
         h->set_edge(other, LBM_BC_DIRICHLET_J, 0.0, 0.0);
     }
-    const bool was_periodic = h->bc[e] == LBM_BC_PERIODIC;
-    // the edge lists depend only on which edges are periodic (and the mask)
-    if (was_periodic != (bc == LBM_BC_PERIODIC)) h->edges_dirty = true;
     h->set_edge(e, bc, bc == LBM_BC_PERIODIC ? 0.0 : value[0], bc == LBM_BC_PERIODIC ? 0.0 : value[1]);
     refit_two_step(h);
     HIP_TRY(h, h->refit_scale());
@@ -434,8 +431,6 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
     if (h->fields) return fail(h, LBM_ERR_STATE, "set the mask before the fields");
     if (!solid) {
         h->has_mask = false;
-        h->mask_host.clear();
-        h->edges_dirty = true;
         return LBM_OK;
     }
     if (h->ws_bytes < h->L.total_walled)
@@ -453,14 +448,12 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
         }
         return solid[(size_t)y * nx + x] == 0;
     };
-    bool any_material = false, thin_hole = false;
+    bool any_material = false;
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
             if (hole(x, y)) {
                 if (((y == 0 || y == ny - 1) && !pery) || ((x == 0 || x == nx - 1) && !perx))
                     return fail(h, LBM_ERR_ARG, "a hole touches a wall edge");
-                if ((!hole(x - 1, y) && !hole(x + 1, y)) || (!hole(x, y - 1) && !hole(x, y + 1)))
-                    thin_hole = true;
                 continue;
             }
             any_material = true;
@@ -468,32 +461,43 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
                 return fail(h, LBM_ERR_ARG, "material one node thick between holes");
         }
     if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
-    // The method allows a hole one node wide; the stress pass keeps the K a
-    // border node needs in its hole neighbour's slot, which the two material
-    // nodes on either side of such a hole would both claim.
-    if (thin_hole) return fail(h, LBM_ERR_UNSUPPORTED, "a hole one node wide (the library needs holes two nodes wide)");
-    h->mask_host.assign(solid, solid + (size_t)nx * ny);
-    for (auto &m : h->mask_host) m = m ? 1 : 0;
-    // The device copy also marks interior nodes in bit 1: the node and its
-    // eight neighbours are material nodes of the lattice, so the interior
-    // launches of the general passes read one byte instead of nine.
-    std::vector<unsigned char> dev(h->mask_host);
-    const unsigned char *mh = h->mask_host.data();
-    for (int y = 1; y < ny - 1; ++y)
-        for (int x = 1; x < nx - 1; ++x) {
-            bool in = true;
-            for (int dy = -1; dy <= 1 && in; ++dy)
-                for (int dx = -1; dx <= 1; ++dx)
-                    if (!mh[(size_t)(y + dy) * nx + (x + dx)]) {
-                        in = false;
+    std::vector<unsigned char> dev(solid, solid + (size_t)nx * ny);
+    for (auto &m : dev) m = m ? 1 : 0;
+    // Tile table of the general step: a tile holds a material node; its
+    // window (the tile and ru nodes around it, across periodic edges) holds a
+    // hole node.
+    int tw = 0, th = 0, ru = 0;
+    switch (h->prec) {
+    case LBM_FP64: tile_shape<PrecF64>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
+    case LBM_FP32: tile_shape<PrecF32>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
+    case LBM_FP16_STORE: tile_shape<PrecF16>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
+    case LBM_FP32_U64: tile_shape<PrecF32U64>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
+    default: tile_shape<PrecBF16>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
+    }
+    const int nbx = (nx + tw - 1) / tw, nby = (ny + th - 1) / th;
+    std::vector<unsigned char> tiles((size_t)nbx * nby, 0);
+    for (int ty = 0; ty < nby; ++ty)
+        for (int tx = 0; tx < nbx; ++tx) {
+            unsigned char f = 0;
+            for (int y = ty * th; y < std::min(ny, (ty + 1) * th) && !f; ++y)
+                for (int x = tx * tw; x < std::min(nx, (tx + 1) * tw); ++x)
+                    if (!hole(x, y)) {
+                        f = TILE_MATERIAL;
                         break;
                     }
-            if (in) dev[(size_t)y * nx + x] |= 2;
+            bool any = false;
+            for (int y = ty * th - ru; y < (ty + 1) * th + ru && !any; ++y)
+                for (int x = tx * tw - ru; x < (tx + 1) * tw + ru; ++x)
+                    if (hole(x, y)) {
+                        any = true;
+                        break;
+                    }
+            tiles[(size_t)ty * nbx + tx] = f | (any ? TILE_HOLES : 0);
         }
     HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, dev.data(), (size_t)nx * ny, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.tiles, tiles.data(), tiles.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->has_mask = true;
-    h->edges_dirty = true;
     return LBM_OK;
 }
 
@@ -501,7 +505,7 @@ lbm_status lbm_set_general_path(lbm_solver *h, int on)
 {
     if (!h) return LBM_ERR_ARG;
     if (on && h->ws_bytes < h->L.total_walled)
-        return fail(h, LBM_ERR_NOMEM, "the general passes need a workspace of lbm_workspace_bytes_walled() bytes");
+        return fail(h, LBM_ERR_NOMEM, "the general step needs a workspace of lbm_workspace_bytes_walled() bytes");
     h->force_general = on != 0;
     return LBM_OK;
 }
@@ -563,63 +567,6 @@ lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0)
     return LBM_OK;
 }
 
-namespace {
-
-// Node lists of the edge launches of the general passes: the stress pass's
-// ring nodes and lattice nodes whose stencil meets a ghost, wall or hole
-// (hole nodes only where a material node borders them), and the stream
-// pass's material nodes not in the interior. Built on the host when the
-// edges or the mask change; hole nodes off the borders are never read, so
-// no launch visits them.
-hipError_t build_edge_lists(lbm_solver *h)
-{
-    const int nx = h->nx, ny = h->ny;
-    const bool perx = h->bc[LBM_EDGE_XMIN] == LBM_BC_PERIODIC, pery = h->bc[LBM_EDGE_YMIN] == LBM_BC_PERIODIC;
-    const unsigned char *m = h->has_mask ? h->mask_host.data() : nullptr;
-    auto hole = [&](int x, int y) {
-        if (!m) return false;
-        if (y < 0 || y >= ny) {
-            if (!pery) return false;
-            y = (y % ny + ny) % ny;
-        }
-        if (x < 0 || x >= nx) {
-            if (!perx) return false;
-            x = (x % nx + nx) % nx;
-        }
-        return m[(size_t)y * nx + x] == 0;
-    };
-    auto inner = [&](int x, int y) {
-        if (x < 1 || x > nx - 2 || y < 1 || y > ny - 2) return false;
-        if (!m) return true;
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx)
-                if (!m[(size_t)(y + dy) * nx + (x + dx)]) return false;
-        return true;
-    };
-    std::vector<int> ek, ef;
-    for (int y = -1; y <= ny; ++y)
-        for (int x = -1; x <= nx; ++x) {
-            if (inner(x, y)) continue;
-            if (hole(x, y) && hole(x - 1, y) && hole(x + 1, y) && hole(x, y - 1) && hole(x, y + 1)) continue;
-            ek.push_back((y + 1) * (nx + 2) + (x + 1));
-            if (x >= 0 && x < nx && y >= 0 && y < ny && !hole(x, y)) ef.push_back(y * nx + x);
-        }
-    h->n_edge_k = (int)ek.size();
-    h->n_edge_f = (int)ef.size();
-    hipError_t e = hipSuccess;
-    if (!ek.empty())
-        e = hipMemcpyAsync(h->ws + h->L.edge_k, ek.data(), sizeof(int) * ek.size(), hipMemcpyHostToDevice,
-                           h->stream);
-    if (!e && !ef.empty())
-        e = hipMemcpyAsync(h->ws + h->L.edge_f, ef.data(), sizeof(int) * ef.size(), hipMemcpyHostToDevice,
-                           h->stream);
-    if (!e) e = hipStreamSynchronize(h->stream);
-    if (!e) h->edges_dirty = false;
-    return e;
-}
-
-}  // namespace
-
 lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
 {
     if (!h) return LBM_ERR_ARG;
@@ -672,11 +619,7 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.pc = h->scheme == LBM_SCHEME_EXTRAP ? 2 : (pc ? 1 : 0);
         gp.flag = sp.flag;
         gp.mask = h->mask_ptr();
-        if (h->edges_dirty) HIP_TRY(h, build_edge_lists(h));
-        gp.edge_k = reinterpret_cast<const int *>(h->ws + h->L.edge_k);
-        gp.edge_f = reinterpret_cast<const int *>(h->ws + h->L.edge_f);
-        gp.n_edge_k = h->n_edge_k;
-        gp.n_edge_f = h->n_edge_f;
+        gp.tiles = h->tiles_ptr();
         for (int64_t k = 0; k < nsteps; ++k) {
             gp.f_in = h->fptr(h->cur);
             gp.u_in = h->uptr(h->cur);

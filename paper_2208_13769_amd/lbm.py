@@ -306,7 +306,7 @@ class Solver:
     def __init__(self, nx: int, ny: int, dx: float = 1.0, precision: str = "fp64", scheme: str = "pc",
                  device: str = "cuda:0", stream=None, walled: bool = False):
         """walled: size the workspace for walls on the x edges (the general
-        passes); always so for the "extrap" scheme."""
+        step); always so for the "extrap" scheme."""
         import torch
 
         self.nx, self.ny, self.dx = nx, ny, dx

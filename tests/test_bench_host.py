@@ -20,9 +20,10 @@ def test_bytes_per_site_of_one_pass_over_the_state():
     assert bench.BYTES_PER_SITE_PASS["fp16"] == bench.BYTES_PER_SITE_PASS["bf16"] == 84
 
 
-def test_general_pass_bytes_per_site_and_step():
-    assert sum(bench.general_bytes_per_site("fp32u64").values()) == 368
-    assert sum(bench.general_bytes_per_site("fp64").values()) == 640
+def test_general_step_bytes_per_material_site():
+    # the state read and written once, and the mask byte
+    assert bench.general_bytes_per_site("fp32u64") == 121
+    assert bench.general_bytes_per_site("fp64") == 209
 
 
 def test_counter_record_only_for_its_kernel_and_shape():

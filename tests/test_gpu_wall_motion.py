@@ -6,8 +6,8 @@ values in effect and stays continuous when j* changes. The strip runs a
 history of tangential and normal wall momenta on both y walls (every value
 change lands between lbm_step calls), then both walls stop; the GPU must
 follow the oracle through the history and the settling, in the fused
-kernel with one and with two steps per launch and in the general per-site
-passes, and with momentum walls on the x edges (general passes).
+kernel with one and with two steps per launch and in the general step,
+and with momentum walls on the x edges (general step).
 """
 import numpy as np
 import pytest

@@ -1,5 +1,5 @@
-"""Walls on the x edges and at corners (the general per-site passes)
-against the oracle, and the passes against the fused kernel where both run."""
+"""Walls on the x edges and at corners (the general step)
+against the oracle, and the general step against the fused kernel where both run."""
 import numpy as np
 import pytest
 
@@ -135,7 +135,7 @@ def test_loaded_block_40x40_matches_oracle(gpu, name, kinds, load, amp, steps, t
 
 
 @pytest.mark.parametrize("kinds", [(P_, P_, P_, P_), (P_, P_, D_, N_)])
-def test_general_passes_equal_fused_kernel(gpu, kinds):
+def test_general_step_equals_fused_kernel(gpu, kinds):
     nx, ny, n = 130, 70, 40
     u0, v0 = _case(nx, ny, 82)
     vals = [(0.0, 0.0), (0.0, 0.0), VALS[D_][2] if kinds[2] else (0.0, 0.0), VALS[N_][3] if kinds[3] else (0.0, 0.0)]
@@ -197,8 +197,8 @@ def test_paper_tension_probe_series(gpu):
 @pytest.mark.parametrize("precision,tol", [
     ("fp16", 1e-3),
     pytest.param("bf16", 1e-3, marks=pytest.mark.xfail(reason="BF16 on four walls: P 2.6e-3 (u 2.2e-4)", strict=False))])
-def test_general_passes_16bit_storage(gpu, precision, tol):
-    """The per-site passes with 16-bit populations (deviations from the
+def test_general_step_16bit_storage(gpu, precision, tol):
+    """The general step with 16-bit populations (deviations from the
     reference equilibrium, rounded to nearest) on four walls, against the
     FP64 oracle within the 1e-3 bound."""
     nx, ny, n = 50, 40, 100
