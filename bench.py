@@ -141,7 +141,7 @@ def timed_windows(solver, stream, steps: int, repeats: int):
     return out, time.perf_counter() - wall0
 
 
-def step_roofline(prec: str, sites: int, spl: int, ms_step: float, traffic):
+def step_roofline(prec: str, sites: int, spl: int, ms_step: float, traffic, kernel=None):
     """Roofline object of the step kernel: algorithmic bytes per launch are
     BYTES_PER_UPDATE x the updates one launch processes (sites x spl), over
     the launch's duration (spl time steps)."""
@@ -151,7 +151,7 @@ def step_roofline(prec: str, sites: int, spl: int, ms_step: float, traffic):
     achieved = bytes_launch / (ms_launch / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "step2_kernel" if spl == 2 else "step_kernel", "steps_per_launch": spl,
+            "kernel": kernel or ("step2_kernel" if spl == 2 else "step_kernel"), "steps_per_launch": spl,
             "launch_us": round(ms_launch * 1e3, 2), "bytes_per_update": BYTES_PER_UPDATE[prec],
             "updates_per_launch": updates_launch, "algorithmic_bytes_per_launch": bytes_launch,
             # the launch's own minimum traffic: the state read and written once
@@ -454,7 +454,8 @@ def main():
                     help="override the workload's precision (fp64, fp32, fp32u64, fp16, bf16)")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiling", default="auto", help="auto | default | BLOCK,NSEGS,STEPS_PER_LAUNCH")
+    ap.add_argument("--tiling", default="auto",
+                    help="auto | default | BLOCK,NSEGS,STEPS_PER_LAUNCH (0,0,1: the general step)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run a plain elementwise copy of this many MiB (float32 read + "
                          "write) three times: its HBM counter readings calibrate the step kernel's")
@@ -472,7 +473,7 @@ def main():
     import torch
 
     from paper_2208_13769_amd import lbm
-    from paper_2208_13769_amd.autotune import best_tiling
+    from paper_2208_13769_amd.autotune import GENERAL, apply_tiling, best_tiling
 
     if args.workload == "hole":
         bench_hole(args)
@@ -488,20 +489,18 @@ def main():
     s = lbm.Solver(nx, ny, 1.0, prec, "pc")
     s.set_material(1.0, wl["lam"], wl["mu"], wl["tau"])
     s.set_fields(wl["u0"], wl["v0"])
-    tiling_source = "default"
+    tiling_source, general = "default", False
     if args.tiling == "auto":
-        block, segs, spl = best_tiling(s, nx, ny, prec, "pc")
-        s.set_steps_per_launch(spl)
-        s.set_tiling(block, segs)
+        t = best_tiling(s, nx, ny, prec, "pc")
+        apply_tiling(s, t)
         s.set_fields(wl["u0"], wl["v0"])
-        tiling_source = "autotuned"
+        tiling_source, general = "autotuned", tuple(t) == GENERAL
     elif args.tiling != "default":
-        block, segs, spl = map(int, args.tiling.split(","))
-        s.set_steps_per_launch(spl)
-        s.set_tiling(block, segs)
-        tiling_source = "given"
+        t = tuple(map(int, args.tiling.split(",")))
+        apply_tiling(s, t)
+        tiling_source, general = "given", t == GENERAL
     block, segs = s.tiling()
-    spl = s.steps_per_launch()
+    spl = 1 if general else s.steps_per_launch()
 
     stream = s.stream
     copy_probe(args.copy_probe_mib, s.device)
@@ -514,14 +513,17 @@ def main():
     sites = nx * ny
     ms_step = ms / args.steps
     mlups = sites * args.steps / (ms / 1e3) / 1e6
-    roofline = step_roofline(prec, sites, spl, ms_step, traffic_for(prec, sites, block, segs, spl))
+    roofline = step_roofline(prec, sites, spl, ms_step,
+                             None if general else traffic_for(prec, sites, block, segs, spl),
+                             "tile_step_kernel" if general else None)
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [nx, ny], "sites": sites, "precision": prec, "scheme": "pc",
-                   "tiling": {"block": block, "n_segs": segs, "steps_per_launch": spl, "source": tiling_source},
+                   "tiling": ({"path": "general step (2D tiles, 512 threads)", "source": tiling_source} if general else
+                              {"block": block, "n_segs": segs, "steps_per_launch": spl, "source": tiling_source}),
                    "repeats": args.repeats, "window_ms": [round(w, 4) for w in windows_ms],
                    "wall_s": round(wall, 4)},
         "roofline": roofline,

@@ -219,9 +219,11 @@ lbm_status lbm_resident_blocks(const lbm_solver *h, int block, int steps_per_lau
 /* Run every step as the general step (1: one launch of 2D tiles, each
  * holding its whole neighbourhood in LDS) or, when no x edge is a wall, as
  * the fused step kernel (0, the default). Both give the same results up to
- * rounding; the general step exists for walls on the x edges, holes and the
- * extrapolation scheme. Needs a workspace of lbm_workspace_bytes_walled()
- * bytes. */
+ * rounding. The general step runs walls on the x edges, holes and the
+ * extrapolation scheme; on small plates it is also the faster one (its
+ * tiles' stages run in parallel where the fused kernel marches rows one
+ * after another). Needs no workspace beyond what the plate's edges, mask
+ * and scheme already need. */
 lbm_status lbm_set_general_path(lbm_solver *h, int on);
 
 /* Holes in the plate (the plate with a hole of Sec. 7.2). solid: host array

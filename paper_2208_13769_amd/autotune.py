@@ -1,14 +1,18 @@
-"""Launch-shape autotuner for the fused step kernel.
+"""Launch-shape autotuner of a plate's time step.
 
-The step kernel's results do not depend on its launch shape (threads per
-block = columns per strip + halo, and row segments per strip), only its speed
-does. For a plate size, precision and scheme the tuner times a short run of
-each candidate shape with HIP events on the solver's stream and keeps the
-fastest. Results are cached in a JSON file (``$LBM_AUTOTUNE_CACHE``, default
+The step's results do not depend on how it is launched, only its speed does:
+the fused step kernel's shape (threads per block = columns per strip + halo,
+row segments per strip, one or two steps per launch), or the general step
+(2D tiles whose stages run in parallel, the faster one on small plates). For
+a plate size, precision and scheme the tuner times a short run of each
+candidate with HIP events on the solver's stream and keeps the fastest.
+Results are cached in a JSON file (``$LBM_AUTOTUNE_CACHE``, default
 ``~/.cache/lbm_solid/autotune.json``) keyed by device name and problem.
 
 Tuning advances the solver's state: call ``set_fields`` again afterwards.
-``best_tiling`` returns (block, segments, steps per launch).
+``best_tiling`` returns (block, segments, steps per launch), with
+``GENERAL`` = (0, 0, 1) standing for the general step; ``apply_tiling`` sets
+either on a solver.
 """
 from __future__ import annotations
 
@@ -16,6 +20,7 @@ import json
 import os
 
 HALO = {"pc": 5, "explicit": 3}
+GENERAL = (0, 0, 1)  # the general step in place of a fused-kernel shape
 
 
 def _cache_path() -> str:
@@ -91,7 +96,19 @@ def candidates(solver, nx: int, ny: int, precision: str, scheme: str):
                 if n_str * segs <= resident and segs not in seen:
                     seen.add(segs)
                     out.append((block, segs, spl))
+    out.append(GENERAL)
     return out
+
+
+def apply_tiling(solver, tiling) -> None:
+    """Run the solver's steps with a candidate of ``candidates``."""
+    block, segs, spl = tiling
+    if tuple(tiling) == GENERAL:
+        solver.set_general_path(True)
+        return
+    solver.set_general_path(False)
+    solver.set_steps_per_launch(spl)
+    solver.set_tiling(block, segs)
 
 
 def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
@@ -101,8 +118,7 @@ def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
     stream = solver.stream
     best, best_ms, table = None, float("inf"), []
     for block, segs, spl in candidates(solver, nx, ny, precision, scheme):
-        solver.set_steps_per_launch(spl)
-        solver.set_tiling(block, segs)
+        apply_tiling(solver, (block, segs, spl))
         solver.step(2)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -120,7 +136,7 @@ def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
 def best_tiling(solver, nx: int, ny: int, precision: str, scheme: str):
     import torch
 
-    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v5"
+    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v6"
     cache = _load_cache()
     if key in cache:
         return tuple(cache[key]["tiling"])

@@ -504,8 +504,8 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
 lbm_status lbm_set_general_path(lbm_solver *h, int on)
 {
     if (!h) return LBM_ERR_ARG;
-    if (on && h->ws_bytes < h->L.total_walled)
-        return fail(h, LBM_ERR_NOMEM, "the general step needs a workspace of lbm_workspace_bytes_walled() bytes");
+    // (holes, x walls and the extrapolation scheme already hold the walled
+    // workspace; the general step of any other plate needs no more)
     h->force_general = on != 0;
     return LBM_OK;
 }

@@ -41,10 +41,14 @@ def oracle_run(nx, ny, u0, v0, nsteps, *, dx=1.0, rho0=1.0, lam=0.1, mu=0.05, ta
 
 
 def gpu_run(nx, ny, u0, v0, nsteps, *, precision="fp64", dx=1.0, rho0=1.0, lam=0.1, mu=0.05, tau=0.8,
-            scheme="pc", body=(0.0, 0.0), bc_lo=("periodic", (0.0, 0.0)), bc_hi=("periodic", (0.0, 0.0))):
+            scheme="pc", body=(0.0, 0.0), bc_lo=("periodic", (0.0, 0.0)), bc_hi=("periodic", (0.0, 0.0)),
+            general=False):
+    """general: run the general step (2D tiles) in place of the fused kernel."""
     from paper_2208_13769_amd import lbm
 
     s = lbm.Solver(nx, ny, dx, precision, scheme)
+    if general:
+        s.set_general_path(True)
     s.set_material(rho0, lam, mu, tau)
     if any(body):
         s.set_body_force(np.array(body, dtype=np.float64))

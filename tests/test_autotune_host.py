@@ -1,7 +1,7 @@
 """Host logic of the autotuner (no GPU): the launch shapes it tries."""
 import pytest
 
-from paper_2208_13769_amd.autotune import candidates, strips
+from paper_2208_13769_amd.autotune import GENERAL, candidates, strips
 
 
 class FakeSolver:
@@ -33,6 +33,8 @@ def test_strips_are_multiples_of_32_columns():
 def test_large_plate_segments_fill_whole_waves():
     s = FakeSolver()
     c = candidates(s, 4096, 4096, "fp32u64", "pc")
+    assert c[-1] == GENERAL  # the general step is always a candidate
+    c = c[:-1]
     assert c and all(spl in (1, 2) for _, _, spl in c)
     assert not any(b == 512 and spl == 2 for b, _, spl in c)  # not launchable here
     for block, segs, spl in c:
@@ -52,5 +54,5 @@ def test_small_plate_tries_short_segments():
 @pytest.mark.parametrize("scheme", ["pc", "explicit"])
 def test_explicit_scheme_has_one_step_per_launch(scheme):
     c = candidates(FakeSolver(), 300, 90, "fp32", scheme)
-    spls = {spl for _, _, spl in c}
+    spls = {spl for b, _, spl in c if b}
     assert spls == ({1, 2} if scheme == "pc" else {1})

@@ -13,10 +13,10 @@ pytestmark = pytest.mark.gpu
 MAT = dict(lam=0.1, mu=0.05, tau=0.8)
 
 
-def _compare(case, nsteps, tol_u, tol_P, tol_v=None, precision="fp64", **kw):
+def _compare(case, nsteps, tol_u, tol_P, tol_v=None, precision="fp64", general=False, **kw):
     u0, v0, nx, ny = case
     uo, vo, Po, do = oracle_run(nx, ny, u0, v0, nsteps, **kw)
-    ug, vg, Pg, dg, st = gpu_run(nx, ny, u0, v0, nsteps, precision=precision, **kw)
+    ug, vg, Pg, dg, st = gpu_run(nx, ny, u0, v0, nsteps, precision=precision, general=general, **kw)
     assert st == 0
     eu, eP, ev = rel_l2(ug, uo), rel_l2(Pg, Po), rel_l2(vg, vo)
     mu_, mP = max_rel(ug, uo), max_rel(Pg, Po)
@@ -55,6 +55,21 @@ def test_ragged_nonlinear_fp64(gpu, scheme):
 @pytest.mark.parametrize("precision", ["fp32", "fp32u64"])
 def test_ragged_nonlinear_fp32(gpu, precision):
     _compare(random_case(517, 77, 8, 0.05), 60, 1e-5, 1e-5, precision=precision, lam=0.1, mu=0.05)
+
+
+@pytest.mark.parametrize("scheme", ["pc", "explicit"])
+def test_general_step_on_periodic_and_y_walled_plates(gpu, scheme):
+    """The general step (2D tiles), which the autotuner picks for small
+    plates, in the plain workspace: the 64 x 64 shear wave for 1000 steps
+    (lam = mu for the explicit scheme, which grows for lam > mu), and the
+    ragged 517 x 77 field with y walls, against the oracle."""
+    mat = dict(lam=0.05, mu=0.05) if scheme == "explicit" else {}
+    o, g = _compare(shear_wave_64_case(), 1000, 1e-12, 1e-12, 1e-12, scheme=scheme, general=True, **mat)
+    assert np.allclose(g[3].momentum, o[3]["momentum"], rtol=0, atol=1e-14)
+    kw = dict(lam=0.1, mu=0.05, bc_lo=("dirichlet", (0.0, 0.0)), bc_hi=("neumann", (0.0, 2e-4)))
+    _compare(random_case(517, 77, 7, 0.05), 60, 1e-12, 1e-12, 1e-12, scheme=scheme, general=True, **kw)
+    _compare(random_case(517, 77, 8, 0.05), 60, 1e-5, 1e-5, precision="fp32u64", scheme=scheme, general=True,
+             **kw)
 
 
 def test_small_block_widths(gpu):
