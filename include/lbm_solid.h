@@ -148,7 +148,11 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
  * Synchronises the stream. Needs the material to be set first. */
 lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0);
 
-/* Enqueue nsteps time steps on the stream and return at once. */
+/* Enqueue nsteps time steps on the stream and return at once. On a plate
+ * with x walls or holes large enough that part of it lies clear of both,
+ * each step forks that part onto a stream the library creates (default
+ * priority) and joins it back with events: work enqueued on the handle's
+ * stream after lbm_step still sees the whole step. */
 lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
 
 /* Read u, v = j / rho0, the first Piola-Kirchhoff stress P(H(u)) and the
@@ -256,7 +260,8 @@ lbm_status lbm_set_rounding(lbm_solver *h, lbm_rounding r, uint64_t seed);
 /* Time step dt of the handle's material. */
 lbm_status lbm_get_dt(const lbm_solver *h, double *dt);
 
-/* Destroy the handle. Never frees the workspace or the stream. */
+/* Destroy the handle (and the stream the library may have created for it).
+ * Never frees the workspace or the caller's stream. */
 void lbm_destroy(lbm_solver *h);
 
 /* Message of the last failing call on h (or of the last failing

@@ -133,8 +133,10 @@ struct TileLdsG {
 
 enum : unsigned char { SITE_NODE = 1, SITE_HOLE = 2, SITE_GHOST = 4 };
 
-// Bits of a tile's entry in the tile table (built on the host with the mask).
-enum : unsigned char { TILE_HOLES = 1, TILE_MATERIAL = 2 };
+// Bits of a tile's entry in the tile table (built on the host): the window
+// holds a hole node; the tile holds a material node; the fused step kernel
+// computes the tile (it lies clear of x walls and holes).
+enum : unsigned char { TILE_HOLES = 1, TILE_MATERIAL = 2, TILE_FUSED = 4 };
 
 template <class PR, int MODE>
 struct TileStep {
@@ -795,6 +797,21 @@ __global__ void __launch_bounds__(kTileBlock) tile_step_kernel(const GenParams p
     const int logical = xcd * xq + min(xcd, xr) + loc;
     const int ty = logical / nbx, tx = logical - ty * nbx;
     const unsigned char tf = p.tiles ? p.tiles[logical] : (unsigned char)TILE_MATERIAL;
+    if (tf & TILE_FUSED) return;
+    if (!(tf & TILE_MATERIAL)) {
+        // wholly inside a hole: the hole nodes' zero state, nothing else
+        using TU = typename PR::TU;
+        using TJ = typename PR::TJ;
+        const size_t pl = (size_t)p.plane;
+        for (int w = threadIdx.x; w < C::TW * C::TH; w += C::BLOCK) {
+            const int x = tx * C::TW + w % C::TW, y = ty * C::TH + w / C::TW;
+            if (x >= p.nx || y >= p.ny) continue;
+            const size_t s = (size_t)y * p.nx + x;
+            static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
+            static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
+        }
+        return;
+    }
     TileStep<PR, MODE> t(p, lds, tx * C::TW, ty * C::TH, tf);
     t.run();
 }

@@ -213,6 +213,9 @@ struct Kernels {
     // The entry points below are defined out of the class (not inline), so
     // that each precision is instantiated in one object only.
     static hipError_t step(const StepParams &sp, int block, int nblocks, bool pc, hipStream_t st);
+    // one step over a tile list (256 threads per block; sp's shape is the
+    // 256-thread shape)
+    static hipError_t step_list(const StepParams &sp, const int *list, int n, bool pc, hipStream_t st);
     // whether a two-step block of this many threads fits the LDS
     static bool step2_ok(int block, bool walled);
     // two predictor-corrector steps per launch
@@ -232,6 +235,25 @@ hipError_t Kernels<PR>::step(const StepParams &sp, int block, int nblocks, bool 
     case 512: return step_b<512>(sp, nblocks, pc, st);
     default: return step_b<256>(sp, nblocks, pc, st);
     }
+}
+
+template <class PR>
+hipError_t Kernels<PR>::step_list(const StepParams &sp, const int *list, int n, bool pc, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const bool w = sp.bc_lo != BC_PERIODIC;
+    if (pc) {
+        if (w)
+            hipLaunchKernelGGL((step_list_kernel<PR, 256, true, true>), dim3(n), dim3(256), 0, st, sp, list, n);
+        else
+            hipLaunchKernelGGL((step_list_kernel<PR, 256, true, false>), dim3(n), dim3(256), 0, st, sp, list, n);
+    } else {
+        if (w)
+            hipLaunchKernelGGL((step_list_kernel<PR, 256, false, true>), dim3(n), dim3(256), 0, st, sp, list, n);
+        else
+            hipLaunchKernelGGL((step_list_kernel<PR, 256, false, false>), dim3(n), dim3(256), 0, st, sp, list, n);
+    }
+    return hipGetLastError();
 }
 
 template <class PR>

@@ -27,6 +27,7 @@ struct Layout {
     size_t scratch, total_walled;  // scratch of the general step (walls on the x edges)
     size_t mask;                   // material mask [ny][nx] bytes, after the scratch
     size_t tiles;                  // tile table of the general step (TILE_* bytes), after the mask
+    size_t flist;                  // fused-kernel tiles of the general step (3 ints each), after the tiles
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -56,7 +57,8 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.scratch = off;
     L.mask = align_up(off + general_scratch(nx, ny, p));
     L.tiles = align_up(L.mask + (size_t)nx * ny);
-    L.total_walled = align_up(L.tiles + max_tiles(nx, ny));
+    L.flist = align_up(L.tiles + max_tiles(nx, ny));
+    L.total_walled = align_up(L.flist + 3 * sizeof(int) * max_tiles(nx, ny));
     return L;
 }
 
@@ -97,6 +99,23 @@ struct lbm_solver {
     unsigned long long seed = 0;
     bool force_general = false;  // run the general step even without x walls
     bool has_mask = false;       // holes (lbm_set_mask)
+    std::vector<unsigned char> mask_host;  // host copy of the mask (1 material, 0 hole)
+    bool tables_dirty = true;    // the general step's tile table and fused list need rebuilding
+    bool tables_built = false;   // the tile table in the workspace is valid
+    int n_flist = 0;             // entries of the fused list
+    Shape fshape{};              // the fused list's launch shape (256 threads, one step)
+    // The fused share runs on a second stream beside the 2D tiles (forked
+    // from and joined back into the handle's stream each step); created on
+    // first use, default priority.
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    ~lbm_solver()
+    {
+        if (aux) (void)hipStreamSynchronize(aux);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
 
     bool general() const
     {
@@ -108,7 +127,7 @@ struct lbm_solver {
     }
     const unsigned char *tiles_ptr() const
     {
-        return has_mask ? reinterpret_cast<const unsigned char *>(ws + L.tiles) : nullptr;
+        return tables_built ? reinterpret_cast<const unsigned char *>(ws + L.tiles) : nullptr;
     }
     std::string err;
 
@@ -381,6 +400,7 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
         // the opposite edge stops being periodic: it becomes a wall at rest until set
         h->set_edge(other, LBM_BC_DIRICHLET_J, 0.0, 0.0);
     }
+    if ((h->bc[e] == LBM_BC_PERIODIC) != (bc == LBM_BC_PERIODIC)) h->tables_dirty = true;
     h->set_edge(e, bc, bc == LBM_BC_PERIODIC ? 0.0 : value[0], bc == LBM_BC_PERIODIC ? 0.0 : value[1]);
     refit_two_step(h);
     HIP_TRY(h, h->refit_scale());
@@ -431,6 +451,8 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
     if (h->fields) return fail(h, LBM_ERR_STATE, "set the mask before the fields");
     if (!solid) {
         h->has_mask = false;
+        h->mask_host.clear();
+        h->tables_dirty = true;
         return LBM_OK;
     }
     if (h->ws_bytes < h->L.total_walled)
@@ -463,41 +485,11 @@ lbm_status lbm_set_mask(lbm_solver *h, const unsigned char *solid)
     if (!any_material) return fail(h, LBM_ERR_ARG, "no material node");
     std::vector<unsigned char> dev(solid, solid + (size_t)nx * ny);
     for (auto &m : dev) m = m ? 1 : 0;
-    // Tile table of the general step: a tile holds a material node; its
-    // window (the tile and ru nodes around it, across periodic edges) holds a
-    // hole node.
-    int tw = 0, th = 0, ru = 0;
-    switch (h->prec) {
-    case LBM_FP64: tile_shape<PrecF64>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
-    case LBM_FP32: tile_shape<PrecF32>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
-    case LBM_FP16_STORE: tile_shape<PrecF16>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
-    case LBM_FP32_U64: tile_shape<PrecF32U64>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
-    default: tile_shape<PrecBF16>(h->scheme != LBM_SCHEME_EXPLICIT, tw, th, ru); break;
-    }
-    const int nbx = (nx + tw - 1) / tw, nby = (ny + th - 1) / th;
-    std::vector<unsigned char> tiles((size_t)nbx * nby, 0);
-    for (int ty = 0; ty < nby; ++ty)
-        for (int tx = 0; tx < nbx; ++tx) {
-            unsigned char f = 0;
-            for (int y = ty * th; y < std::min(ny, (ty + 1) * th) && !f; ++y)
-                for (int x = tx * tw; x < std::min(nx, (tx + 1) * tw); ++x)
-                    if (!hole(x, y)) {
-                        f = TILE_MATERIAL;
-                        break;
-                    }
-            bool any = false;
-            for (int y = ty * th - ru; y < (ty + 1) * th + ru && !any; ++y)
-                for (int x = tx * tw - ru; x < (tx + 1) * tw + ru; ++x)
-                    if (hole(x, y)) {
-                        any = true;
-                        break;
-                    }
-            tiles[(size_t)ty * nbx + tx] = f | (any ? TILE_HOLES : 0);
-        }
     HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.mask, dev.data(), (size_t)nx * ny, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.tiles, tiles.data(), tiles.size(), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    h->mask_host.swap(dev);
     h->has_mask = true;
+    h->tables_dirty = true;
     return LBM_OK;
 }
 
@@ -567,6 +559,137 @@ lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0)
     return LBM_OK;
 }
 
+namespace {
+
+// The general step's tables, built on the host when the mask or the edges
+// change. The tile table marks each 2D tile whose window holds a hole node,
+// that holds a material node, and that the fused kernel computes instead.
+// The fused list: on a plate with x walls or holes, the tiles of the fused
+// step kernel (256-thread strips, row runs aligned to the 2D tiles' rows)
+// whose outputs lie farther than the stencil's reach from both. There the
+// fused kernel's periodic-x arithmetic is the general rules' arithmetic, and
+// it runs those sites at the fused kernel's rate.
+hipError_t build_general_tables(lbm_solver *h)
+{
+    const int nx = h->nx, ny = h->ny;
+    const bool perx = h->bc[LBM_EDGE_XMIN] == LBM_BC_PERIODIC, pery = h->bc[LBM_EDGE_YMIN] == LBM_BC_PERIODIC;
+    const bool pc = h->scheme != LBM_SCHEME_EXPLICIT;
+    int tw = 0, th = 0, ru = 0;
+    switch (h->prec) {
+    case LBM_FP64: tile_shape<PrecF64>(pc, tw, th, ru); break;
+    case LBM_FP32: tile_shape<PrecF32>(pc, tw, th, ru); break;
+    case LBM_FP16_STORE: tile_shape<PrecF16>(pc, tw, th, ru); break;
+    case LBM_FP32_U64: tile_shape<PrecF32U64>(pc, tw, th, ru); break;
+    default: tile_shape<PrecBF16>(pc, tw, th, ru); break;
+    }
+    const int mg = stencil_halo(h->prec, h->scheme, 1);
+    // hole counts of boxes: per-row prefix sums over the rows and columns
+    // within max(ru, mg) of the plate (wrapped across periodic edges; beyond
+    // a wall there are no holes)
+    const int e = std::max(ru, mg);
+    const int W = nx + 2 * e, Hh = ny + 2 * e;
+    std::vector<uint32_t> pre;
+    const bool any_mask = h->has_mask;
+    if (any_mask) {
+        pre.assign((size_t)Hh * (W + 1), 0u);
+        const unsigned char *m = h->mask_host.data();
+        for (int r = 0; r < Hh; ++r) {
+            int y = r - e;
+            bool row_in = true;
+            if (y < 0 || y >= ny) {
+                if (pery) y = ((y % ny) + ny) % ny;
+                else row_in = false;
+            }
+            uint32_t *pr = pre.data() + (size_t)r * (W + 1);
+            for (int c = 0; c < W; ++c) {
+                int x = c - e;
+                bool in = row_in;
+                if (x < 0 || x >= nx) {
+                    if (perx) x = ((x % nx) + nx) % nx;
+                    else in = false;
+                }
+                pr[c + 1] = pr[c] + ((in && m[(size_t)y * nx + x] == 0) ? 1u : 0u);
+            }
+        }
+    }
+    // holes in [x0, x1) x [y0, y1), plate coordinates within e of the plate
+    auto holes_in = [&](int x0, int x1, int y0, int y1) -> bool {
+        if (!any_mask) return false;
+        x0 = std::max(x0, -e) + e, x1 = std::min(x1, nx + e) + e;
+        y0 = std::max(y0, -e) + e, y1 = std::min(y1, ny + e) + e;
+        for (int r = y0; r < y1; ++r) {
+            const uint32_t *pr = pre.data() + (size_t)r * (W + 1);
+            if (pr[x1] != pr[x0]) return true;
+        }
+        return false;
+    };
+    const int nbx = (nx + tw - 1) / tw, nby = (ny + th - 1) / th;
+    std::vector<unsigned char> tiles((size_t)nbx * nby, 0);
+    for (int ty = 0; ty < nby; ++ty)
+        for (int tx = 0; tx < nbx; ++tx) {
+            const int x0 = tx * tw, y0 = ty * th;
+            const int x1 = std::min(nx, x0 + tw), y1 = std::min(ny, y0 + th);
+            unsigned char f = 0;
+            // material: fewer hole nodes than nodes in the tile
+            if (!any_mask) {
+                f = TILE_MATERIAL;
+            } else {
+                uint32_t n = 0;
+                for (int r = y0 + e; r < y1 + e; ++r) {
+                    const uint32_t *pr = pre.data() + (size_t)r * (W + 1);
+                    n += pr[x1 + e] - pr[x0 + e];
+                }
+                if (n < (uint32_t)((x1 - x0) * (y1 - y0))) f = TILE_MATERIAL;
+            }
+            if (holes_in(x0 - ru, x0 + tw + ru, y0 - ru, y0 + th + ru)) f |= TILE_HOLES;
+            tiles[(size_t)ty * nbx + tx] = f;
+        }
+    std::vector<int> list;
+    if (h->scheme != LBM_SCHEME_EXTRAP && (any_mask || !perx)) {
+        const Shape fs = make_shape(nx, ny, h->prec, h->scheme, 256, 1, 1);
+        h->fshape = fs;
+        const int seg_rows = std::max(th, (ny / 26) / th * th);
+        // a strip's columns start on a 2D tile's column (strips are a
+        // multiple of 32 columns wide, or the whole plate)
+        if (fs.n_strips == 1 || fs.strip_w % tw == 0)
+            for (int st = 0; st < fs.n_strips; ++st) {
+                const int x0 = st * fs.strip_w, x1 = std::min(nx, x0 + fs.strip_w);
+                if (!perx && (x0 - mg < 0 || x1 + mg > nx)) continue;
+                int run0 = -1;
+                for (int ty = 0; ty <= nby; ++ty) {
+                    const bool clean = ty < nby && !holes_in(x0 - mg, x1 + mg, ty * th - mg,
+                                                             std::min(ny, ty * th + th) + mg);
+                    if (clean && run0 < 0) run0 = ty;
+                    if (!clean && run0 >= 0) {
+                        const int ya = run0 * th, yb = std::min(ny, ty * th);
+                        for (int a = ya; a < yb; a += seg_rows) {
+                            list.push_back(st);
+                            list.push_back(a);
+                            list.push_back(std::min(yb, a + seg_rows));
+                        }
+                        for (int t = run0; t < ty; ++t)
+                            for (int tx = x0 / tw; tx < (x1 + tw - 1) / tw; ++tx)
+                                tiles[(size_t)t * nbx + tx] |= TILE_FUSED;
+                        run0 = -1;
+                    }
+                }
+            }
+    }
+    hipError_t err = hipMemcpyAsync(h->ws + h->L.tiles, tiles.data(), tiles.size(), hipMemcpyHostToDevice,
+                                    h->stream);
+    if (!err && !list.empty())
+        err = hipMemcpyAsync(h->ws + h->L.flist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice,
+                             h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+    if (err) return err;
+    h->n_flist = (int)(list.size() / 3);
+    h->tables_built = true;
+    h->tables_dirty = false;
+    return hipSuccess;
+}
+
+}  // namespace
+
 lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
 {
     if (!h) return LBM_ERR_ARG;
@@ -619,16 +742,37 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.pc = h->scheme == LBM_SCHEME_EXTRAP ? 2 : (pc ? 1 : 0);
         gp.flag = sp.flag;
         gp.mask = h->mask_ptr();
+        if (h->tables_dirty && h->ws_bytes >= h->L.total_walled) HIP_TRY(h, build_general_tables(h));
         gp.tiles = h->tiles_ptr();
+        // the fused kernel's share: the tiles clear of x walls and holes
+        const int nf = gp.tiles ? h->n_flist : 0;
+        if (nf > 0 && !h->aux) {
+            HIP_TRY(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+            HIP_TRY(h, hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
+            HIP_TRY(h, hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
+        }
+        const int *flist = reinterpret_cast<const int *>(h->ws + h->L.flist);
+        StepParams fp = sp;
+        fp.strip_w = h->fshape.strip_w;
+        fp.halo_a = h->fshape.halo_a;
+        fp.n_strips = h->fshape.n_strips;
+        fp.n_segs = 1;
         for (int64_t k = 0; k < nsteps; ++k) {
-            gp.f_in = h->fptr(h->cur);
-            gp.u_in = h->uptr(h->cur);
-            gp.j_in = h->jptr(h->cur);
-            gp.f_out = h->fptr(h->cur ^ 1);
-            gp.u_out = h->uptr(h->cur ^ 1);
-            gp.j_out = h->jptr(h->cur ^ 1);
-            gp.step = h->steps;
+            gp.f_in = fp.f_in = h->fptr(h->cur);
+            gp.u_in = fp.u_in = h->uptr(h->cur);
+            gp.j_in = fp.j_in = h->jptr(h->cur);
+            gp.f_out = fp.f_out = h->fptr(h->cur ^ 1);
+            gp.u_out = fp.u_out = h->uptr(h->cur ^ 1);
+            gp.j_out = fp.j_out = h->jptr(h->cur ^ 1);
+            gp.step = fp.step = h->steps;
+            if (nf > 0) {
+                HIP_TRY(h, hipEventRecord(h->fork, h->stream));
+                HIP_TRY(h, hipStreamWaitEvent(h->aux, h->fork, 0));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step_list(fp, flist, nf, pc, h->aux)));
+                HIP_TRY(h, hipEventRecord(h->join, h->aux));
+            }
             HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gp, h->ws + h->L.scratch, h->stream)));
+            if (nf > 0) HIP_TRY(h, hipStreamWaitEvent(h->stream, h->join, 0));
             h->cur ^= 1;
             h->steps += 1;
         }

@@ -818,7 +818,8 @@ using Phase = std::integral_constant<int, V>;
 // segment's last output row, where nothing is stored or checked.
 template <class PR, int BLOCK, bool PC, bool WALLED>
 __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, const int seg,
-                                          TileLds<PR, BLOCK, PC, WALLED> &lds)
+                                          TileLds<PR, BLOCK, PC, WALLED> &lds, const int yr0 = -1,
+                                          const int yr1 = 0)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
@@ -837,7 +838,11 @@ __device__ __forceinline__ void step_tile(const StepParams &p, const int strip, 
     const int nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)p.plane;
     const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
-    const TileGeom g = tile_geom(p, strip, seg);
+    TileGeom g = tile_geom(p, strip, seg);
+    if (yr0 >= 0) {  // an explicit row range in place of segment seg
+        g.y0 = yr0;
+        g.y1 = yr1;
+    }
     P pipe(lds, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
     const bool sr = FS::kStochastic && p.sr;
     const uint32_t key = sr ? sr_key(p.seed, p.step + 1) : 0u;
@@ -1125,6 +1130,22 @@ __global__ void __launch_bounds__(BLOCK) step_kernel(const StepParams p)
     const int strip = logical - seg * p.n_strips;
     __shared__ TileLds<PR, BLOCK, PC, WALLED> lds;
     step_tile<PR, BLOCK, PC, WALLED>(p, strip, seg, lds);
+}
+
+// One step over a list of tiles (strip, first row, end row), three ints per
+// entry: the parts of a plate with x walls or holes that lie clear of them,
+// next to the general step's 2D tiles for the rest. Blocks map to entries
+// as in step_kernel.
+template <class PR, int BLOCK, bool PC, bool WALLED>
+__global__ void __launch_bounds__(BLOCK) step_list_kernel(const StepParams p, const int *__restrict__ list, const int n)
+{
+    const int bid = blockIdx.x;
+    const int xq = n >> 3, xr = n & 7;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int logical = xcd * xq + min(xcd, xr) + loc;
+    const int *e = list + 3 * logical;
+    __shared__ TileLds<PR, BLOCK, PC, WALLED> lds;
+    step_tile<PR, BLOCK, PC, WALLED>(p, e[0], 0, lds, e[1], e[2]);
 }
 
 // Two steps per launch, one block per tile (same tile order as step_kernel).
