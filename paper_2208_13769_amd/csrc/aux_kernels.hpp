@@ -16,7 +16,7 @@ struct FieldParams {
     int bc_left, bc_right;      // x edges
     double uw_left[2], uw_right[2];
     double lam, mu;             // lattice units
-    const unsigned char *mask;  // [ny][nx] bit 0: material (1) or hole (0), Sec. 7.2; bit 1: interior; nullptr: no holes
+    const unsigned char *mask;  // [ny][nx]: material (1) or hole (0), Sec. 7.2; nullptr: no holes
 };
 
 // Node (x, y) lies in a hole; coordinates beyond a periodic edge wrap,

@@ -55,6 +55,8 @@ struct GenParams {
     unsigned *flag;
     const unsigned char *mask;   // [ny][nx]: 1 material, 0 hole; nullptr: no holes
     const unsigned char *tiles;  // TILE_* bits of each tile (row-major); nullptr: no holes
+    const int *tlist;            // the tiles to launch (row-major indices); nullptr: every tile
+    int n_tlist;
 };
 
 // D2Q9 of this implementation (see lattice.hpp)
@@ -795,23 +797,12 @@ __global__ void __launch_bounds__(kTileBlock) tile_step_kernel(const GenParams p
     const int xq = nb >> 3, xr = nb & 7;
     const int xcd = bid & 7, loc = bid >> 3;
     const int logical = xcd * xq + min(xcd, xr) + loc;
-    const int ty = logical / nbx, tx = logical - ty * nbx;
-    const unsigned char tf = p.tiles ? p.tiles[logical] : (unsigned char)TILE_MATERIAL;
-    if (tf & TILE_FUSED) return;
-    if (!(tf & TILE_MATERIAL)) {
-        // wholly inside a hole: the hole nodes' zero state, nothing else
-        using TU = typename PR::TU;
-        using TJ = typename PR::TJ;
-        const size_t pl = (size_t)p.plane;
-        for (int w = threadIdx.x; w < C::TW * C::TH; w += C::BLOCK) {
-            const int x = tx * C::TW + w % C::TW, y = ty * C::TH + w / C::TW;
-            if (x >= p.nx || y >= p.ny) continue;
-            const size_t s = (size_t)y * p.nx + x;
-            static_cast<TU *>(p.u_out)[s] = static_cast<TU *>(p.u_out)[pl + s] = TU(0);
-            static_cast<TJ *>(p.j_out)[s] = static_cast<TJ *>(p.j_out)[pl + s] = TJ(0);
-        }
-        return;
-    }
+    const int tile = p.tlist ? p.tlist[logical] : logical;
+    const int ty = tile / nbx, tx = tile - ty * nbx;
+    const unsigned char tf = p.tiles ? p.tiles[tile] : (unsigned char)TILE_MATERIAL;
+    // (the fused kernel computes a TILE_FUSED tile; nothing reads the state
+    // of hole nodes, so a tile without material has nothing to do)
+    if ((tf & TILE_FUSED) || !(tf & TILE_MATERIAL)) return;
     TileStep<PR, MODE> t(p, lds, tx * C::TW, ty * C::TH, tf);
     t.run();
 }
@@ -857,12 +848,14 @@ hipError_t general_step(GenParams p, char *scratch, hipStream_t st)
     }
     if (p.pc) {
         using C = TileCfg<PR, 1>;
-        const int nbx = (p.nx + C::TW - 1) / C::TW, nb = nbx * ((p.ny + C::TH - 1) / C::TH);
-        hipLaunchKernelGGL((tile_step_kernel<PR, 1>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
+        const int nbx = (p.nx + C::TW - 1) / C::TW;
+        const int nb = p.tlist ? p.n_tlist : nbx * ((p.ny + C::TH - 1) / C::TH);
+        if (nb > 0) hipLaunchKernelGGL((tile_step_kernel<PR, 1>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
     } else {
         using C = TileCfg<PR, 0>;
-        const int nbx = (p.nx + C::TW - 1) / C::TW, nb = nbx * ((p.ny + C::TH - 1) / C::TH);
-        hipLaunchKernelGGL((tile_step_kernel<PR, 0>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
+        const int nbx = (p.nx + C::TW - 1) / C::TW;
+        const int nb = p.tlist ? p.n_tlist : nbx * ((p.ny + C::TH - 1) / C::TH);
+        if (nb > 0) hipLaunchKernelGGL((tile_step_kernel<PR, 0>), dim3(nb), dim3(C::BLOCK), 0, st, p, nbx, nb);
     }
     return hipGetLastError();
 }

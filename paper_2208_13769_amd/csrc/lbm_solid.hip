@@ -28,6 +28,7 @@ struct Layout {
     size_t mask;                   // material mask [ny][nx] bytes, after the scratch
     size_t tiles;                  // tile table of the general step (TILE_* bytes), after the mask
     size_t flist;                  // fused-kernel tiles of the general step (3 ints each), after the tiles
+    size_t tlist;                  // the 2D tiles the general step launches (int each), after the fused list
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -58,7 +59,8 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.mask = align_up(off + general_scratch(nx, ny, p));
     L.tiles = align_up(L.mask + (size_t)nx * ny);
     L.flist = align_up(L.tiles + max_tiles(nx, ny));
-    L.total_walled = align_up(L.flist + 3 * sizeof(int) * max_tiles(nx, ny));
+    L.tlist = align_up(L.flist + 3 * sizeof(int) * max_tiles(nx, ny));
+    L.total_walled = align_up(L.tlist + sizeof(int) * max_tiles(nx, ny));
     return L;
 }
 
@@ -103,6 +105,7 @@ struct lbm_solver {
     bool tables_dirty = true;    // the general step's tile table and fused list need rebuilding
     bool tables_built = false;   // the tile table in the workspace is valid
     int n_flist = 0;             // entries of the fused list
+    int n_tlist = 0;             // entries of the 2D tile list
     Shape fshape{};              // the fused list's launch shape (256 threads, one step)
     // The fused share runs on a second stream beside the 2D tiles (forked
     // from and joined back into the handle's stream each step); created on
@@ -675,14 +678,24 @@ hipError_t build_general_tables(lbm_solver *h)
                 }
             }
     }
+    // the 2D tiles to launch: those with material that the fused kernel does
+    // not compute, in row-major order (the kernel deals them to the XCDs in
+    // equal runs)
+    std::vector<int> tl;
+    for (size_t t = 0; t < tiles.size(); ++t)
+        if ((tiles[t] & TILE_MATERIAL) && !(tiles[t] & TILE_FUSED)) tl.push_back((int)t);
     hipError_t err = hipMemcpyAsync(h->ws + h->L.tiles, tiles.data(), tiles.size(), hipMemcpyHostToDevice,
                                     h->stream);
     if (!err && !list.empty())
         err = hipMemcpyAsync(h->ws + h->L.flist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice,
                              h->stream);
+    if (!err && !tl.empty())
+        err = hipMemcpyAsync(h->ws + h->L.tlist, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice,
+                             h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
     if (err) return err;
     h->n_flist = (int)(list.size() / 3);
+    h->n_tlist = (int)tl.size();
     h->tables_built = true;
     h->tables_dirty = false;
     return hipSuccess;
@@ -744,6 +757,8 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.mask = h->mask_ptr();
         if (h->tables_dirty && h->ws_bytes >= h->L.total_walled) HIP_TRY(h, build_general_tables(h));
         gp.tiles = h->tiles_ptr();
+        gp.tlist = gp.tiles ? reinterpret_cast<const int *>(h->ws + h->L.tlist) : nullptr;
+        gp.n_tlist = gp.tiles ? h->n_tlist : 0;
         // the fused kernel's share: the tiles clear of x walls and holes
         const int nf = gp.tiles ? h->n_flist : 0;
         if (nf > 0 && !h->aux) {
