@@ -115,26 +115,26 @@ def test_one_node_wide_holes_match_oracle(gpu, scheme):
 
 @pytest.mark.parametrize("precision,scheme,tol", [("fp64", "pc", 1e-12), ("fp64", "explicit", 1e-12),
                                                    ("fp32u64", "pc", 1e-5), ("fp16", "pc", 1e-3)])
-@pytest.mark.parametrize("ykinds", [(D_, N_), (P_, P_)])
-def test_fused_share_of_the_general_step_matches_oracle(gpu, precision, scheme, tol, ykinds):
+@pytest.mark.parametrize("kinds", [(N_, D_, D_, N_), (N_, D_, P_, P_), (P_, P_, D_, N_)])
+def test_fused_share_of_the_general_step_matches_oracle(gpu, precision, scheme, tol, kinds):
     """A plate wide enough that the general step hands the fused kernel the
-    strips clear of the x walls and of the hole (here the runs above and
-    below the hole in the second strip, and all of the third), next to the
-    2D tiles for the rest: against the oracle."""
+    strips clear of the x walls and of the hole (with x walls: the runs above
+    and below the hole in the second strip, and all of the third; periodic
+    in x: also the strips whose halo wraps across the edge), next to the 2D
+    tiles for the rest: against the oracle."""
     nx, ny, n = 700, 160, 40
     m = np.ones((ny, nx), np.uint8)
     m[60:100, 300:400] = 0
     rng = np.random.Generator(np.random.PCG64(35))
     u0 = 0.002 * rng.standard_normal((2, ny, nx)) * m[None]
     v0 = 0.002 * rng.standard_normal((2, ny, nx)) * m[None]
-    kinds = (N_, D_) + ykinds
-    vals = [(0.0001, 0.0), (0.0, 0.0)] + [(0.0, 0.0) if k == P_ else ((0.0, 0.0) if k == D_ else (0.0, 2e-4))
-                                         for k in ykinds]
+    vals = [(0.0, 0.0) if k == P_ else ((0.0001, 0.0) if e == 0 else (0.0, 2e-4) if k == N_ else (0.0, 0.0))
+            for e, k in enumerate(kinds)]
     uo, vo, Po, so, do = _oracle(nx, ny, u0, v0, n, kinds, vals, m, scheme=scheme)
     ug, vg, Pg, sg, dg, st, _ = _gpu(nx, ny, u0, v0, n, kinds, vals, m, precision=precision, scheme=scheme)
     assert st == 0
     e = [rel_l2(ug, uo), rel_l2(vg, vo), rel_l2(Pg, Po)]
-    print(f"fused share {precision} {scheme} {ykinds}: rel-L2 u {e[0]:.3e} v {e[1]:.3e} P {e[2]:.3e}", flush=True)
+    print(f"fused share {precision} {scheme} {kinds}: rel-L2 u {e[0]:.3e} v {e[1]:.3e} P {e[2]:.3e}", flush=True)
     assert max(e[0], e[2]) < tol
     assert np.abs(ug[:, m == 0]).max() == 0.0
 
