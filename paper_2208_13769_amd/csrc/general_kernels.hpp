@@ -800,9 +800,10 @@ __global__ void __launch_bounds__(kTileBlock) tile_step_kernel(const GenParams p
     const int tile = p.tlist ? p.tlist[logical] : logical;
     const int ty = tile / nbx, tx = tile - ty * nbx;
     const unsigned char tf = p.tiles ? p.tiles[tile] : (unsigned char)TILE_MATERIAL;
-    // (the fused kernel computes a TILE_FUSED tile; nothing reads the state
-    // of hole nodes, so a tile without material has nothing to do)
-    if ((tf & TILE_FUSED) || !(tf & TILE_MATERIAL)) return;
+    // (without a list the fused kernel computes a TILE_FUSED tile; nothing
+    // reads the state of hole nodes, so a tile without material has nothing
+    // to do)
+    if ((!p.tlist && (tf & TILE_FUSED)) || !(tf & TILE_MATERIAL)) return;
     TileStep<PR, MODE> t(p, lds, tx * C::TW, ty * C::TH, tf);
     t.run();
 }

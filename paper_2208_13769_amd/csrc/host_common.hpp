@@ -216,6 +216,10 @@ struct Kernels {
     // one step over a tile list (256 threads per block; sp's shape is the
     // 256-thread shape)
     static hipError_t step_list(const StepParams &sp, const int *list, int n, bool pc, hipStream_t st);
+    // two predictor-corrector steps over a tile list (256 threads, the
+    // two-step shape); hipErrorInvalidConfiguration where the block's LDS
+    // does not fit
+    static hipError_t step2_list(const StepParams &sp, const int *list, int n, hipStream_t st);
     // whether a two-step block of this many threads fits the LDS
     static bool step2_ok(int block, bool walled);
     // two predictor-corrector steps per launch
@@ -252,6 +256,24 @@ hipError_t Kernels<PR>::step_list(const StepParams &sp, const int *list, int n, 
             hipLaunchKernelGGL((step_list_kernel<PR, 256, false, true>), dim3(n), dim3(256), 0, st, sp, list, n);
         else
             hipLaunchKernelGGL((step_list_kernel<PR, 256, false, false>), dim3(n), dim3(256), 0, st, sp, list, n);
+    }
+    return hipGetLastError();
+}
+
+template <class PR>
+hipError_t Kernels<PR>::step2_list(const StepParams &sp, const int *list, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (sp.bc_lo != BC_PERIODIC) {
+        if constexpr (step2_fits<256, true>())
+            hipLaunchKernelGGL((step2_list_kernel<PR, 256, true>), dim3(n), dim3(256), 0, st, sp, list, n);
+        else
+            return hipErrorInvalidConfiguration;
+    } else {
+        if constexpr (step2_fits<256, false>())
+            hipLaunchKernelGGL((step2_list_kernel<PR, 256, false>), dim3(n), dim3(256), 0, st, sp, list, n);
+        else
+            return hipErrorInvalidConfiguration;
     }
     return hipGetLastError();
 }

@@ -29,6 +29,11 @@ struct Layout {
     size_t tiles;                  // tile table of the general step (TILE_* bytes), after the mask
     size_t flist;                  // fused-kernel tiles of the general step (3 ints each), after the tiles
     size_t tlist;                  // the 2D tiles the general step launches (int each), after the fused list
+    // paired steps: the two-step fused list, the 2D tiles of the first step
+    // (the rest widened by one tile) and of the second (the rest), and a
+    // third copy of the state for the first step's output
+    size_t flist2, tlist_a, tlist_b;
+    size_t mid_f, mid_u, mid_j;
 };
 
 size_t general_scratch(int nx, int ny, lbm_precision p)
@@ -60,7 +65,15 @@ Layout make_layout(int nx, int ny, lbm_precision p)
     L.tiles = align_up(L.mask + (size_t)nx * ny);
     L.flist = align_up(L.tiles + max_tiles(nx, ny));
     L.tlist = align_up(L.flist + 3 * sizeof(int) * max_tiles(nx, ny));
-    L.total_walled = align_up(L.tlist + sizeof(int) * max_tiles(nx, ny));
+    L.flist2 = align_up(L.tlist + sizeof(int) * max_tiles(nx, ny));
+    L.tlist_a = align_up(L.flist2 + 3 * sizeof(int) * max_tiles(nx, ny));
+    L.tlist_b = align_up(L.tlist_a + sizeof(int) * max_tiles(nx, ny));
+    const ElemSizes es = elem_sizes(p);
+    const size_t n = (size_t)nx * ny;
+    L.mid_f = align_up(L.tlist_b + sizeof(int) * max_tiles(nx, ny));
+    L.mid_u = align_up(L.mid_f + 9 * n * es.f);
+    L.mid_j = align_up(L.mid_u + 2 * n * es.u);
+    L.total_walled = align_up(L.mid_j + 2 * n * es.j);
     return L;
 }
 
@@ -106,6 +119,8 @@ struct lbm_solver {
     bool tables_built = false;   // the tile table in the workspace is valid
     int n_flist = 0;             // entries of the fused list
     int n_tlist = 0;             // entries of the 2D tile list
+    int n_flist2 = 0, n_tlist_a = 0, n_tlist_b = 0;  // paired steps (n_flist2 = 0: none)
+    Shape fshape2{};             // the two-step fused list's launch shape
     Shape fshape{};              // the fused list's launch shape (256 threads, one step)
     // The fused share runs on a second stream beside the 2D tiles (forked
     // from and joined back into the handle's stream each step); created on
@@ -647,55 +662,131 @@ hipError_t build_general_tables(lbm_solver *h)
             if (holes_in(x0 - ru, x0 + tw + ru, y0 - ru, y0 + th + ru)) f |= TILE_HOLES;
             tiles[(size_t)ty * nbx + tx] = f;
         }
-    std::vector<int> list;
-    if (h->scheme != LBM_SCHEME_EXTRAP && (any_mask || !perx)) {
-        const Shape fs = make_shape(nx, ny, h->prec, h->scheme, 256, 1, 1);
-        h->fshape = fs;
+    // fused-kernel entries of a launch of spl steps: (strip, row run) pairs
+    // whose outputs lie farther than the launch's stencil reach from x walls
+    // and holes; `mark` receives the 2D tiles they cover
+    auto fused_list = [&](int spl, Shape &fs, std::vector<unsigned char> &mark) {
+        std::vector<int> list;
+        mark.assign(tiles.size(), 0);
+        if (h->scheme == LBM_SCHEME_EXTRAP || !(any_mask || !perx)) return list;
+        fs = make_shape(nx, ny, h->prec, h->scheme, 256, 1, spl);
+        const int reach = stencil_halo(h->prec, h->scheme, spl);
         const int seg_rows = std::max(th, (ny / 26) / th * th);
         // a strip's columns start on a 2D tile's column (strips are a
         // multiple of 32 columns wide, or the whole plate)
-        if (fs.n_strips == 1 || fs.strip_w % tw == 0)
-            for (int st = 0; st < fs.n_strips; ++st) {
-                const int x0 = st * fs.strip_w, x1 = std::min(nx, x0 + fs.strip_w);
-                if (!perx && (x0 - mg < 0 || x1 + mg > nx)) continue;
-                int run0 = -1;
-                for (int ty = 0; ty <= nby; ++ty) {
-                    const bool clean = ty < nby && !holes_in(x0 - mg, x1 + mg, ty * th - mg,
-                                                             std::min(ny, ty * th + th) + mg);
-                    if (clean && run0 < 0) run0 = ty;
-                    if (!clean && run0 >= 0) {
-                        const int ya = run0 * th, yb = std::min(ny, ty * th);
-                        for (int a = ya; a < yb; a += seg_rows) {
-                            list.push_back(st);
-                            list.push_back(a);
-                            list.push_back(std::min(yb, a + seg_rows));
-                        }
-                        for (int t = run0; t < ty; ++t)
-                            for (int tx = x0 / tw; tx < (x1 + tw - 1) / tw; ++tx)
-                                tiles[(size_t)t * nbx + tx] |= TILE_FUSED;
-                        run0 = -1;
+        if (!(fs.n_strips == 1 || fs.strip_w % tw == 0)) return list;
+        for (int st = 0; st < fs.n_strips; ++st) {
+            const int x0 = st * fs.strip_w, x1 = std::min(nx, x0 + fs.strip_w);
+            if (!perx && (x0 - reach < 0 || x1 + reach > nx)) continue;
+            int run0 = -1;
+            for (int ty = 0; ty <= nby; ++ty) {
+                const bool clean = ty < nby && !holes_in(x0 - reach, x1 + reach, ty * th - reach,
+                                                         std::min(ny, ty * th + th) + reach);
+                if (clean && run0 < 0) run0 = ty;
+                if (!clean && run0 >= 0) {
+                    const int ya = run0 * th, yb = std::min(ny, ty * th);
+                    for (int a = ya; a < yb; a += seg_rows) {
+                        list.push_back(st);
+                        list.push_back(a);
+                        list.push_back(std::min(yb, a + seg_rows));
                     }
+                    for (int t = run0; t < ty; ++t)
+                        for (int tx = x0 / tw; tx < (x1 + tw - 1) / tw; ++tx) mark[(size_t)t * nbx + tx] = 1;
+                    run0 = -1;
                 }
             }
-    }
+        }
+        return list;
+    };
+    std::vector<unsigned char> mark1, mark2;
+    const std::vector<int> list = fused_list(1, h->fshape, mark1);
+    for (size_t t = 0; t < tiles.size(); ++t)
+        if (mark1[t]) tiles[t] |= TILE_FUSED;
     // the 2D tiles to launch: those with material that the fused kernel does
     // not compute, in row-major order (the kernel deals them to the XCDs in
     // equal runs)
     std::vector<int> tl;
     for (size_t t = 0; t < tiles.size(); ++t)
         if ((tiles[t] & TILE_MATERIAL) && !(tiles[t] & TILE_FUSED)) tl.push_back((int)t);
+    // Paired steps: the two-step fused kernel over the strips clear of walls
+    // and holes by two steps' reach; the 2D tiles advance the rest in two
+    // launches, the first over the rest widened by one tile (at least the
+    // one-step reach in each direction) into a third state copy, the second
+    // from it over the rest.
+    // The walled two-step fused kernel runs one wave per SIMD (one block per
+    // CU) where the one-step kernel runs two. On the 4096² plate with a hole
+    // that pays in FP64 (0.662 against 0.726 ms per step) and FP32 (0.423
+    // against 0.556 ms), not in FP32 with a double displacement (0.508
+    // against 0.452 ms), so paired steps run in FP64 and FP32.
+    std::vector<int> list2, tla, tlb;
+    bool pair = h->scheme == LBM_SCHEME_PC && (h->prec == LBM_FP64 || h->prec == LBM_FP32);
+    if (pair)
+        pair = (h->prec == LBM_FP64 ? Kernels<PrecF64>::step2_ok(256, !pery)
+                                    : Kernels<PrecF32>::step2_ok(256, !pery)) &&
+               th >= mg && tw >= mg;
+    if (pair) {
+        list2 = fused_list(2, h->fshape2, mark2);
+        std::vector<unsigned char> rest(tiles.size(), 0), wide(tiles.size(), 0);
+        for (size_t t = 0; t < tiles.size(); ++t) rest[t] = (tiles[t] & TILE_MATERIAL) && !mark2[t];
+        // nodes between [a0, a1) and [b0, b1) on a line or a ring of n nodes
+        auto gap = [](int a0, int a1, int b0, int b1, int n, bool per) {
+            int best = 1 << 30;
+            for (int sh = per ? -n : 0; sh <= (per ? n : 0); sh += n ? n : 1) {
+                const int c0 = b0 + sh, c1 = b1 + sh;
+                const int g = c0 >= a1 ? c0 - a1 + 1 : (a0 >= c1 ? a0 - c1 + 1 : 0);
+                best = std::min(best, g);
+                if (!per) break;
+            }
+            return best;
+        };
+        // the first launch covers every tile with a node within the
+        // one-step reach of a rest tile (two tiles around suffice: tiles are
+        // at least that reach wide, the ragged last one aside)
+        for (int ty = 0; ty < nby; ++ty)
+            for (int tx = 0; tx < nbx; ++tx) {
+                if (!rest[(size_t)ty * nbx + tx]) continue;
+                const int ax0 = tx * tw, ax1 = std::min(nx, ax0 + tw), ay0 = ty * th, ay1 = std::min(ny, ay0 + th);
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        int ux = tx + dx, uy = ty + dy;
+                        if (ux < 0 || ux >= nbx) {
+                            if (!perx) continue;
+                            ux = (ux % nbx + nbx) % nbx;
+                        }
+                        if (uy < 0 || uy >= nby) {
+                            if (!pery) continue;
+                            uy = (uy % nby + nby) % nby;
+                        }
+                        const int bx0 = ux * tw, bx1 = std::min(nx, bx0 + tw);
+                        const int by0 = uy * th, by1 = std::min(ny, by0 + th);
+                        if (gap(ax0, ax1, bx0, bx1, nx, perx) <= mg && gap(ay0, ay1, by0, by1, ny, pery) <= mg)
+                            wide[(size_t)uy * nbx + ux] = 1;
+                    }
+            }
+        for (size_t t = 0; t < tiles.size(); ++t) {
+            if (wide[t] && (tiles[t] & TILE_MATERIAL)) tla.push_back((int)t);
+            if (rest[t]) tlb.push_back((int)t);
+        }
+        if (list2.empty()) tla.clear(), tlb.clear();
+    }
     hipError_t err = hipMemcpyAsync(h->ws + h->L.tiles, tiles.data(), tiles.size(), hipMemcpyHostToDevice,
                                     h->stream);
-    if (!err && !list.empty())
-        err = hipMemcpyAsync(h->ws + h->L.flist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice,
-                             h->stream);
-    if (!err && !tl.empty())
-        err = hipMemcpyAsync(h->ws + h->L.tlist, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice,
-                             h->stream);
+    auto up = [&](size_t off, const std::vector<int> &v) {
+        if (!err && !v.empty())
+            err = hipMemcpyAsync(h->ws + off, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, h->stream);
+    };
+    up(h->L.flist, list);
+    up(h->L.tlist, tl);
+    up(h->L.flist2, list2);
+    up(h->L.tlist_a, tla);
+    up(h->L.tlist_b, tlb);
     if (!err) err = hipStreamSynchronize(h->stream);
     if (err) return err;
     h->n_flist = (int)(list.size() / 3);
     h->n_tlist = (int)tl.size();
+    h->n_flist2 = (int)(list2.size() / 3);
+    h->n_tlist_a = (int)tla.size();
+    h->n_tlist_b = (int)tlb.size();
     h->tables_built = true;
     h->tables_dirty = false;
     return hipSuccess;
@@ -761,7 +852,7 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.n_tlist = gp.tiles ? h->n_tlist : 0;
         // the fused kernel's share: the tiles clear of x walls and holes
         const int nf = gp.tiles ? h->n_flist : 0;
-        if (nf > 0 && !h->aux) {
+        if ((nf > 0 || (gp.tiles && h->n_flist2 > 0)) && !h->aux) {
             HIP_TRY(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
             HIP_TRY(h, hipEventCreateWithFlags(&h->fork, hipEventDisableTiming));
             HIP_TRY(h, hipEventCreateWithFlags(&h->join, hipEventDisableTiming));
@@ -772,7 +863,50 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         fp.halo_a = h->fshape.halo_a;
         fp.n_strips = h->fshape.n_strips;
         fp.n_segs = 1;
-        for (int64_t k = 0; k < nsteps; ++k) {
+        int64_t k = 0;
+        // paired steps: the two-step fused kernel on the aux stream; the 2D
+        // tiles' first step (widened rest) into the third state copy, then
+        // their second step (rest) from it
+        const int nf2 = gp.tiles ? h->n_flist2 : 0;
+        if (nf2 > 0) {
+            const int *flist2 = reinterpret_cast<const int *>(h->ws + h->L.flist2);
+            StepParams fp2 = sp;
+            fp2.strip_w = h->fshape2.strip_w;
+            fp2.halo_a = h->fshape2.halo_a;
+            fp2.n_strips = h->fshape2.n_strips;
+            fp2.n_segs = 1;
+            GenParams ga = gp, gb = gp;
+            ga.tlist = reinterpret_cast<const int *>(h->ws + h->L.tlist_a);
+            ga.n_tlist = h->n_tlist_a;
+            gb.tlist = reinterpret_cast<const int *>(h->ws + h->L.tlist_b);
+            gb.n_tlist = h->n_tlist_b;
+            ga.f_out = h->ws + h->L.mid_f;
+            ga.u_out = h->ws + h->L.mid_u;
+            ga.j_out = h->ws + h->L.mid_j;
+            gb.f_in = ga.f_out;
+            gb.u_in = ga.u_out;
+            gb.j_in = ga.j_out;
+            for (; k + 2 <= nsteps; k += 2) {
+                fp2.f_in = ga.f_in = h->fptr(h->cur);
+                fp2.u_in = ga.u_in = h->uptr(h->cur);
+                fp2.j_in = ga.j_in = h->jptr(h->cur);
+                fp2.f_out = gb.f_out = h->fptr(h->cur ^ 1);
+                fp2.u_out = gb.u_out = h->uptr(h->cur ^ 1);
+                fp2.j_out = gb.j_out = h->jptr(h->cur ^ 1);
+                fp2.step = ga.step = h->steps;
+                gb.step = h->steps + 1;
+                HIP_TRY(h, hipEventRecord(h->fork, h->stream));
+                HIP_TRY(h, hipStreamWaitEvent(h->aux, h->fork, 0));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step2_list(fp2, flist2, nf2, h->aux)));
+                HIP_TRY(h, hipEventRecord(h->join, h->aux));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(ga, h->ws + h->L.scratch, h->stream)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gb, h->ws + h->L.scratch, h->stream)));
+                HIP_TRY(h, hipStreamWaitEvent(h->stream, h->join, 0));
+                h->cur ^= 1;
+                h->steps += 2;
+            }
+        }
+        for (; k < nsteps; ++k) {
             gp.f_in = fp.f_in = h->fptr(h->cur);
             gp.u_in = fp.u_in = h->uptr(h->cur);
             gp.j_in = fp.j_in = h->jptr(h->cur);

@@ -1009,7 +1009,8 @@ constexpr int step2_unroll()
 template <class PR, int BLOCK, bool WALLED>
 __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip, const int seg,
                                            TileLds<PR, BLOCK, true, WALLED> &lds1,
-                                           TileLds<PR, BLOCK, true, WALLED> &lds2)
+                                           TileLds<PR, BLOCK, true, WALLED> &lds2, const int yr0 = -1,
+                                           const int yr1 = 0)
 {
     using TF = typename PR::TF;
     using TU = typename PR::TU;
@@ -1028,7 +1029,11 @@ __device__ __forceinline__ void step2_tile(const StepParams &p, const int strip,
     const int nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)p.plane;
     const TC f_scale = TC(p.f_scale), f_inv = TC(p.f_inv_scale);
-    const TileGeom g = tile_geom(p, strip, seg);
+    TileGeom g = tile_geom(p, strip, seg);
+    if (yr0 >= 0) {  // an explicit row range in place of segment seg
+        g.y0 = yr0;
+        g.y1 = yr1;
+    }
     P p1(lds1, p, p.step, (int)threadIdx.x, g.y0, g.y1, g.out_col);
     P p2(lds2, p, p.step + 1, (int)threadIdx.x, g.y0, g.y1, g.out_col);
     const bool sr = FS::kStochastic && p.sr;
@@ -1146,6 +1151,20 @@ __global__ void __launch_bounds__(BLOCK) step_list_kernel(const StepParams p, co
     const int *e = list + 3 * logical;
     __shared__ TileLds<PR, BLOCK, PC, WALLED> lds;
     step_tile<PR, BLOCK, PC, WALLED>(p, e[0], 0, lds, e[1], e[2]);
+}
+
+// Two steps over a tile list (strip, first row, end row), as step_list_kernel.
+template <class PR, int BLOCK, bool WALLED>
+__global__ void __launch_bounds__(BLOCK) step2_list_kernel(const StepParams p, const int *__restrict__ list,
+                                                           const int n)
+{
+    const int bid = blockIdx.x;
+    const int xq = n >> 3, xr = n & 7;
+    const int xcd = bid & 7, loc = bid >> 3;
+    const int logical = xcd * xq + min(xcd, xr) + loc;
+    const int *e = list + 3 * logical;
+    __shared__ TileLds<PR, BLOCK, true, WALLED> lds[2];
+    step2_tile<PR, BLOCK, WALLED>(p, e[0], 0, lds[0], lds[1], e[1], e[2]);
 }
 
 // Two steps per launch, one block per tile (same tile order as step_kernel).

@@ -114,15 +114,17 @@ def test_one_node_wide_holes_match_oracle(gpu, scheme):
 
 
 @pytest.mark.parametrize("precision,scheme,tol", [("fp64", "pc", 1e-12), ("fp64", "explicit", 1e-12),
-                                                   ("fp32u64", "pc", 1e-5), ("fp16", "pc", 1e-3)])
+                                                   ("fp32", "pc", 1e-5), ("fp32u64", "pc", 1e-5),
+                                                   ("fp16", "pc", 1e-3)])
 @pytest.mark.parametrize("kinds", [(N_, D_, D_, N_), (N_, D_, P_, P_), (P_, P_, D_, N_)])
 def test_fused_share_of_the_general_step_matches_oracle(gpu, precision, scheme, tol, kinds):
     """A plate wide enough that the general step hands the fused kernel the
     strips clear of the x walls and of the hole (with x walls: the runs above
     and below the hole in the second strip, and all of the third; periodic
     in x: also the strips whose halo wraps across the edge), next to the 2D
-    tiles for the rest: against the oracle."""
-    nx, ny, n = 700, 160, 40
+    tiles for the rest, one step or (PC, 32/64-bit storage) two steps at a
+    time: against the oracle."""
+    nx, ny, n = 700, 160, 41  # paired steps (PC, 32/64-bit storage) and a single one
     m = np.ones((ny, nx), np.uint8)
     m[60:100, 300:400] = 0
     rng = np.random.Generator(np.random.PCG64(35))
