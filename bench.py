@@ -204,7 +204,9 @@ def copy_probe(mib: int, device):
 
 
 def general_source_hash() -> str:
-    return _code_hash(["general_kernels.hpp", "step_kernel.hpp", "lattice.hpp"])
+    # the host code that splits the plate between the fused kernel and the
+    # 2D tiles decides the traffic too
+    return _code_hash(["general_kernels.hpp", "step_kernel.hpp", "lattice.hpp", "lbm_solid.hip"])
 
 
 def general_traffic_for(precision: str, n: int):
@@ -279,8 +281,10 @@ def bench_hole(args):
                    "repeats": args.repeats, "window_ms": [round(w, 4) for w in windows_ms]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "general step: step_list_kernel (the share clear of walls and the hole) beside "
-                               "tile_step_kernel on a second stream, one step (traffic: HBM bytes per step)",
+                     "kernel": "general step: the fused kernel over the share clear of walls and the hole "
+                               "(step2_list_kernel, two steps per launch, with 32/64-bit populations; else "
+                               "step_list_kernel) beside tile_step_kernel on a second stream (traffic: HBM bytes "
+                               "per step)",
                      "bytes_per_material_site": per_site},
         "run": {"status": int(st), "min_J": d.min_J, "max_strain": d.max_strain},
     }

@@ -149,10 +149,12 @@ lbm_status lbm_set_boundary(lbm_solver *h, lbm_edge e, lbm_bc bc, const double v
 lbm_status lbm_set_fields(lbm_solver *h, const double *u0, const double *v0);
 
 /* Enqueue nsteps time steps on the stream and return at once. On a plate
- * with x walls or holes large enough that part of it lies clear of both,
- * each step forks that part onto a stream the library creates (default
- * priority) and joins it back with events: work enqueued on the handle's
- * stream after lbm_step still sees the whole step. */
+ * with x walls or holes large enough that part of it lies clear of every
+ * wall and hole, each step (with the predictor-corrector and 32- or
+ * 64-bit populations, each pair of steps) runs that part on the handle's
+ * stream and the rest on a stream the library creates (default priority),
+ * forked and joined with events: work enqueued on the handle's stream
+ * after lbm_step still sees the whole step. */
 lbm_status lbm_step(lbm_solver *h, int64_t nsteps);
 
 /* Read u, v = j / rho0, the first Piola-Kirchhoff stress P(H(u)) and the

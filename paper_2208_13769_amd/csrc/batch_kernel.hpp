@@ -69,6 +69,7 @@ __device__ __forceinline__ StepParams plate_step_params(const PlateDesc &pd, int
     sp.n_strips = pd.n_strips;
     sp.n_segs = pd.n_segs;
     sp.halo_a = pd.halo_a;
+    sp.x_lo = sp.x_end = 0;  // strips over the whole width
     sp.flag = pd.flag;
     sp.step = step;
     sp.sr = pd.sr;

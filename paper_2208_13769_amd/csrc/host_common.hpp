@@ -83,6 +83,7 @@ inline int stencil_halo(lbm_precision p, lbm_scheme s, int steps_per_launch)
 // Launch shape of one plate: column strips and row segments.
 struct Shape {
     int block, strip_w, n_strips, n_segs, halo_a;
+    int x_lo = 0, x_end = 0;  // strips over columns [x_lo, x_end) (x_end 0: the whole width)
 };
 
 // When the plate is wider than one block's reach, each strip's output width

@@ -246,13 +246,14 @@ lbm_status hip_fail(lbm_solver *h, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(h, e_, #call); \
     } while (0)
 
-int resident_blocks(const lbm_solver *h, int block, int spl)
+int resident_blocks(const lbm_solver *h, int block, int spl, int walled_form = -1)
 {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const bool pc = h->scheme == LBM_SCHEME_PC;
-    const bool walled = h->bc[LBM_EDGE_YMIN] != LBM_BC_PERIODIC;
+    // the kernel form of the handle's y edges, unless one is asked for
+    const bool walled = walled_form >= 0 ? walled_form != 0 : h->bc[LBM_EDGE_YMIN] != LBM_BC_PERIODIC;
     int per_cu = 0;
     switch (h->prec) {
     case LBM_FP64: per_cu = Kernels<PrecF64>::resident_per_cu(block, spl, pc, walled); break;
@@ -665,23 +666,41 @@ hipError_t build_general_tables(lbm_solver *h)
     // fused-kernel entries of a launch of spl steps: (strip, row run) pairs
     // whose outputs lie farther than the launch's stencil reach from x walls
     // and holes; `mark` receives the 2D tiles they cover
-    auto fused_list = [&](int spl, Shape &fs, std::vector<unsigned char> &mark) {
+    auto fused_list = [&](int spl, int runs, Shape &fs, std::vector<unsigned char> &mark) {
         std::vector<int> list;
         mark.assign(tiles.size(), 0);
         if (h->scheme == LBM_SCHEME_EXTRAP || !(any_mask || !perx)) return list;
         fs = make_shape(nx, ny, h->prec, h->scheme, 256, 1, spl);
         const int reach = stencil_halo(h->prec, h->scheme, spl);
-        const int seg_rows = std::max(th, (ny / 26) / th * th);
+        // row runs of at most seg_rows rows: about `runs` per strip
+        const int seg_rows = std::max(th, (ny / runs) / th * th);
         // a strip's columns start on a 2D tile's column (strips are a
         // multiple of 32 columns wide, or the whole plate)
         if (!(fs.n_strips == 1 || fs.strip_w % tw == 0)) return list;
-        for (int st = 0; st < fs.n_strips; ++st) {
-            const int x0 = st * fs.strip_w, x1 = std::min(nx, x0 + fs.strip_w);
+        // with x walls the strips start at the first tile column beyond the
+        // reach from the wall and end at the last one before the far wall,
+        // so the 2D tiles keep one tile column at each wall, not a strip
+        int n_st = fs.n_strips;
+        if (!perx) {
+            fs.x_lo = (reach + tw - 1) / tw * tw;
+            fs.x_end = (nx - reach) / tw * tw;
+            n_st = fs.x_end > fs.x_lo ? (fs.x_end - fs.x_lo + fs.strip_w - 1) / fs.strip_w : 0;
+        }
+        const int xe = fs.x_end > 0 ? fs.x_end : nx;
+        // likewise the row runs stay a tile row clear of y walls: no output
+        // of the fused share then depends on a wall rule or a ghost row, and
+        // it runs the fused kernel's periodic form (fewer registers and LDS
+        // bytes than the walled one), leaving the rows at y walls to the tiles
+        const int ylo = pery ? 0 : (reach + th - 1) / th * th;
+        const int yend = pery ? ny : (ny - reach) / th * th;
+        for (int st = 0; st < n_st; ++st) {
+            const int x0 = fs.x_lo + st * fs.strip_w, x1 = std::min(xe, x0 + fs.strip_w);
             if (!perx && (x0 - reach < 0 || x1 + reach > nx)) continue;
             int run0 = -1;
             for (int ty = 0; ty <= nby; ++ty) {
-                const bool clean = ty < nby && !holes_in(x0 - reach, x1 + reach, ty * th - reach,
-                                                         std::min(ny, ty * th + th) + reach);
+                const bool clean = ty < nby && ty * th >= ylo && std::min(ny, ty * th + th) <= yend &&
+                                   !holes_in(x0 - reach, x1 + reach, ty * th - reach,
+                                             std::min(ny, ty * th + th) + reach);
                 if (clean && run0 < 0) run0 = ty;
                 if (!clean && run0 >= 0) {
                     const int ya = run0 * th, yb = std::min(ny, ty * th);
@@ -698,8 +717,22 @@ hipError_t build_general_tables(lbm_solver *h)
         }
         return list;
     };
+    // The fused grid is sized to one wave of resident blocks of its periodic
+    // form: from 26 row runs per strip (as the default plan's segments of a
+    // periodic plate) down until the list fits; a block that waits for a
+    // second wave would double the share's time.
+    auto fused_fit = [&](int spl, Shape &fs, std::vector<unsigned char> &mark) {
+        const int slots = resident_blocks(h, 256, spl, 0);
+        int runs = 26;
+        for (;;) {
+            std::vector<int> list = fused_list(spl, runs, fs, mark);
+            const int n = (int)(list.size() / 3);
+            if (slots <= 0 || n <= slots || runs == 1) return list;
+            runs = std::max(1, std::min(runs - 1, (int)((long long)runs * slots / n)));
+        }
+    };
     std::vector<unsigned char> mark1, mark2;
-    const std::vector<int> list = fused_list(1, h->fshape, mark1);
+    const std::vector<int> list = fused_fit(1, h->fshape, mark1);
     for (size_t t = 0; t < tiles.size(); ++t)
         if (mark1[t]) tiles[t] |= TILE_FUSED;
     // the 2D tiles to launch: those with material that the fused kernel does
@@ -713,19 +746,20 @@ hipError_t build_general_tables(lbm_solver *h)
     // launches, the first over the rest widened by one tile (at least the
     // one-step reach in each direction) into a third state copy, the second
     // from it over the rest.
-    // The walled two-step fused kernel runs one wave per SIMD (one block per
-    // CU) where the one-step kernel runs two. On the 4096² plate with a hole
-    // that pays in FP64 (0.662 against 0.726 ms per step) and FP32 (0.423
-    // against 0.556 ms), not in FP32 with a double displacement (0.508
-    // against 0.452 ms), so paired steps run in FP64 and FP32.
+    // The fused share runs the periodic form, whose two-step block leaves
+    // room for a second one on a compute unit. On the 4096² plate with a
+    // hole, paired steps take 0.576 ms per step in FP64, 0.329 in FP32 and
+    // 0.429 in FP32 with a double displacement, against 0.534 one step at a
+    // time in the last (16-bit storage has no two-step kernel).
     std::vector<int> list2, tla, tlb;
-    bool pair = h->scheme == LBM_SCHEME_PC && (h->prec == LBM_FP64 || h->prec == LBM_FP32);
-    if (pair)
-        pair = (h->prec == LBM_FP64 ? Kernels<PrecF64>::step2_ok(256, !pery)
-                                    : Kernels<PrecF32>::step2_ok(256, !pery)) &&
-               th >= mg && tw >= mg;
+    bool pair = false;
+    if (h->scheme == LBM_SCHEME_PC && th >= mg && tw >= mg) {
+        if (h->prec == LBM_FP64) pair = Kernels<PrecF64>::step2_ok(256, false);
+        if (h->prec == LBM_FP32) pair = Kernels<PrecF32>::step2_ok(256, false);
+        if (h->prec == LBM_FP32_U64) pair = Kernels<PrecF32U64>::step2_ok(256, false);
+    }
     if (pair) {
-        list2 = fused_list(2, h->fshape2, mark2);
+        list2 = fused_fit(2, h->fshape2, mark2);
         std::vector<unsigned char> rest(tiles.size(), 0), wide(tiles.size(), 0);
         for (size_t t = 0; t < tiles.size(); ++t) rest[t] = (tiles[t] & TILE_MATERIAL) && !mark2[t];
         // nodes between [a0, a1) and [b0, b1) on a line or a ring of n nodes
@@ -850,7 +884,8 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.tiles = h->tiles_ptr();
         gp.tlist = gp.tiles ? reinterpret_cast<const int *>(h->ws + h->L.tlist) : nullptr;
         gp.n_tlist = gp.tiles ? h->n_tlist : 0;
-        // the fused kernel's share: the tiles clear of x walls and holes
+        // the fused kernel's share: the tiles clear of walls and holes (on
+        // the handle's stream, the 2D tiles beside it on the aux stream)
         const int nf = gp.tiles ? h->n_flist : 0;
         if ((nf > 0 || (gp.tiles && h->n_flist2 > 0)) && !h->aux) {
             HIP_TRY(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
@@ -862,11 +897,18 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         fp.strip_w = h->fshape.strip_w;
         fp.halo_a = h->fshape.halo_a;
         fp.n_strips = h->fshape.n_strips;
+        fp.x_lo = h->fshape.x_lo;
+        fp.x_end = h->fshape.x_end;
         fp.n_segs = 1;
+        fp.bc_lo = fp.bc_hi = BC_PERIODIC;  // the fused share is clear of y walls: periodic form
         int64_t k = 0;
-        // paired steps: the two-step fused kernel on the aux stream; the 2D
-        // tiles' first step (widened rest) into the third state copy, then
-        // their second step (rest) from it
+        // paired steps: the two-step fused kernel on the handle's stream; on
+        // the aux stream the 2D tiles' first step (widened rest) into the
+        // third state copy, then their second step (rest) from it. The fused
+        // grid is one wave of resident blocks, so it is enqueued first: tile
+        // blocks holding compute units when it dispatches would push part of
+        // it into a second wave (0.86 against 0.49 ms per pair on the 4096²
+        // plate with a hole).
         const int nf2 = gp.tiles ? h->n_flist2 : 0;
         if (nf2 > 0) {
             const int *flist2 = reinterpret_cast<const int *>(h->ws + h->L.flist2);
@@ -874,7 +916,10 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
             fp2.strip_w = h->fshape2.strip_w;
             fp2.halo_a = h->fshape2.halo_a;
             fp2.n_strips = h->fshape2.n_strips;
+            fp2.x_lo = h->fshape2.x_lo;
+            fp2.x_end = h->fshape2.x_end;
             fp2.n_segs = 1;
+            fp2.bc_lo = fp2.bc_hi = BC_PERIODIC;
             GenParams ga = gp, gb = gp;
             ga.tlist = reinterpret_cast<const int *>(h->ws + h->L.tlist_a);
             ga.n_tlist = h->n_tlist_a;
@@ -897,10 +942,10 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
                 gb.step = h->steps + 1;
                 HIP_TRY(h, hipEventRecord(h->fork, h->stream));
                 HIP_TRY(h, hipStreamWaitEvent(h->aux, h->fork, 0));
-                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step2_list(fp2, flist2, nf2, h->aux)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step2_list(fp2, flist2, nf2, h->stream)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(ga, h->ws + h->L.scratch, h->aux)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gb, h->ws + h->L.scratch, h->aux)));
                 HIP_TRY(h, hipEventRecord(h->join, h->aux));
-                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(ga, h->ws + h->L.scratch, h->stream)));
-                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gb, h->ws + h->L.scratch, h->stream)));
                 HIP_TRY(h, hipStreamWaitEvent(h->stream, h->join, 0));
                 h->cur ^= 1;
                 h->steps += 2;
@@ -917,11 +962,13 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
             if (nf > 0) {
                 HIP_TRY(h, hipEventRecord(h->fork, h->stream));
                 HIP_TRY(h, hipStreamWaitEvent(h->aux, h->fork, 0));
-                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step_list(fp, flist, nf, pc, h->aux)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, Kernels<PR>::step_list(fp, flist, nf, pc, h->stream)));
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gp, h->ws + h->L.scratch, h->aux)));
                 HIP_TRY(h, hipEventRecord(h->join, h->aux));
+                HIP_TRY(h, hipStreamWaitEvent(h->stream, h->join, 0));
+            } else {
+                HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gp, h->ws + h->L.scratch, h->stream)));
             }
-            HIP_TRY(h, LBM_DISPATCH(h->prec, general_step<PR>(gp, h->ws + h->L.scratch, h->stream)));
-            if (nf > 0) HIP_TRY(h, hipStreamWaitEvent(h->stream, h->join, 0));
             h->cur ^= 1;
             h->steps += 1;
         }

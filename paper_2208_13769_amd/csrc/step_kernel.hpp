@@ -74,6 +74,7 @@ struct StepParams {
     double f_scale, f_inv_scale;  // 16-bit population scaling (1 otherwise)
     int strip_w, n_strips, n_segs;
     int halo_a;             // threads left of the first output column (>= the stencil halo)
+    int x_lo, x_end;        // strips cover columns [x_lo, x_end) (x_end 0: the plate's width)
     unsigned int *flag;     // set to 1 on J <= 0 or a non-finite value
     long long step;         // index n of the input state
     int sr;                 // 16-bit populations: 1 = stochastic rounding, 0 = to nearest
@@ -772,11 +773,11 @@ __device__ __forceinline__ TileGeom tile_geom(const StepParams &p, int strip, in
 {
     TileGeom g;
     const int t = threadIdx.x;
-    const int x0 = strip * p.strip_w;
+    const int x0 = p.x_lo + strip * p.strip_w;
     const int xc = x0 - p.halo_a + t;
     g.gx = xc % p.nx;
     if (g.gx < 0) g.gx += p.nx;
-    g.out_col = (t >= p.halo_a) && (t < p.halo_a + p.strip_w) && (xc < p.nx);
+    g.out_col = (t >= p.halo_a) && (t < p.halo_a + p.strip_w) && (xc < (p.x_end > 0 ? p.x_end : p.nx));
     g.y0 = (int)((long long)seg * p.ny / p.n_segs);
     g.y1 = (int)((long long)(seg + 1) * p.ny / p.n_segs);
     return g;
