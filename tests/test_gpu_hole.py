@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
-from tests.helpers import rel_l2
+from tests.helpers import MAX_NORM_FACTOR, max_rel, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -139,6 +139,68 @@ def test_fused_share_of_the_general_step_matches_oracle(gpu, precision, scheme, 
     print(f"fused share {precision} {scheme} {kinds}: rel-L2 u {e[0]:.3e} v {e[1]:.3e} P {e[2]:.3e}", flush=True)
     assert max(e[0], e[2]) < tol
     assert np.abs(ug[:, m == 0]).max() == 0.0
+
+
+HOLE_N, HOLE_K = 4096, 5
+
+
+@pytest.fixture(scope="module")
+def hole_plate_4096():
+    """The benchmark's plate with a hole (4096 x 4096 nodes, side l = 1, a
+    centred hole of 0.4 l, traction walls with 0.02 mu on the top and bottom,
+    lam = mu = 1, tau/dt = 0.55), started from a smooth random velocity so
+    that every node moves, and the oracle's state after HOLE_K steps."""
+    from paper_2208_13769_amd import inputs
+
+    n = HOLE_N
+    h = int(round(0.4 * n))
+    a = (n - h) // 2
+    m = np.ones((n, n), np.uint8)
+    m[a:a + h, a:a + h] = 0
+    u0, v0 = inputs.filtered_random_velocity(n, n, 24.0, 41, 1e-3)
+    v0 *= m[None]
+    kinds = (N_, N_, N_, N_)
+    vals = [(0.0, 0.0), (0.0, 0.0), (0.0, -0.02), (0.0, 0.02)]
+    kw = {}
+    for e, k, v in zip(EDGES, kinds, vals):
+        kw["bc_" + e] = k
+        kw["val_" + e] = tuple(v)
+    p = O.Params(nx=n, ny=n, dx=1.0 / n, lam=1.0, mu=1.0, tau_over_dt=0.55, solid=m, **kw)
+    ref = O.Solver(p, u0, v0)
+    ref.step(HOLE_K)
+    uo, vo, Po = ref.fields()
+    del ref
+    return dict(m=m, u0=u0, v0=v0, kinds=kinds, vals=vals, uo=uo, Po=Po)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32u64", 1e-5), ("fp16", 1e-3)])
+def test_hole_plate_4096_matches_oracle(gpu, hole_plate_4096, precision, tol):
+    """The benchmark's plate with a hole at its full size, whole fields
+    against the oracle after five steps: with 32/64-bit populations two
+    pairs of steps (the two-step fused kernel over the strips and rows clear
+    of the walls and the hole, its row runs sized to one wave of resident
+    blocks, beside two launches of 2D tiles) and a single step; with 16-bit
+    storage single steps."""
+    from paper_2208_13769_amd import lbm
+
+    c = hole_plate_4096
+    n = HOLE_N
+    s = lbm.Solver(n, n, 1.0 / n, precision, "pc", walled=True)
+    s.set_material(1.0, 1.0, 1.0, 0.55)
+    for e, (k, v) in enumerate(zip(c["kinds"], c["vals"])):
+        s.set_boundary(e, k, v)
+    s.set_mask(c["m"])
+    s.set_fields(c["u0"], c["v0"])
+    s.step(HOLE_K)
+    ug, _, Pg, _, st = s.read()
+    s.close()
+    assert st == 0
+    eu, eP = rel_l2(ug, c["uo"]), rel_l2(Pg, c["Po"])
+    mu_, mP = max_rel(ug, c["uo"]), max_rel(Pg, c["Po"])
+    print(f"hole plate {n}^2 {precision}, {HOLE_K} steps: rel-L2 u {eu:.3e} P {eP:.3e}; "
+          f"max-norm u {mu_:.3e} P {mP:.3e}", flush=True)
+    assert max(eu, eP) < tol
+    assert max(mu_, mP) < MAX_NORM_FACTOR * tol
 
 
 def test_plate_with_hole_80x80_matches_oracle(gpu):
