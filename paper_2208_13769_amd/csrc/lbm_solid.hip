@@ -882,6 +882,10 @@ lbm_status lbm_step(lbm_solver *h, int64_t nsteps)
         gp.mask = h->mask_ptr();
         if (h->tables_dirty && h->ws_bytes >= h->L.total_walled) HIP_TRY(h, build_general_tables(h));
         gp.tiles = h->tiles_ptr();
+        // without holes and without a fused share the table marks every
+        // tile as material and nothing else: go without it, so that small
+        // plates may take the two-row tiles
+        if (gp.tiles && !h->has_mask && h->n_flist == 0 && h->n_flist2 == 0) gp.tiles = nullptr;
         gp.tlist = gp.tiles ? reinterpret_cast<const int *>(h->ws + h->L.tlist) : nullptr;
         gp.n_tlist = gp.tiles ? h->n_tlist : 0;
         // the fused kernel's share: the tiles clear of walls and holes (on

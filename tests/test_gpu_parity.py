@@ -61,15 +61,21 @@ def test_ragged_nonlinear_fp32(gpu, precision):
 def test_general_step_on_periodic_and_y_walled_plates(gpu, scheme):
     """The general step (2D tiles), which the autotuner picks for small
     plates, in the plain workspace: the 64 x 64 shear wave for 1000 steps
-    (lam = mu for the explicit scheme, which grows for lam > mu), and the
-    ragged 517 x 77 field with y walls, against the oracle."""
+    (lam = mu for the explicit scheme, which grows for lam > mu) and a
+    100 x 60 field with y walls (both small enough for two-row tiles), and
+    the ragged 517 x 77 field with y walls (default tiles), against the
+    oracle."""
     mat = dict(lam=0.05, mu=0.05) if scheme == "explicit" else {}
     o, g = _compare(shear_wave_64_case(), 1000, 1e-12, 1e-12, 1e-12, scheme=scheme, general=True, **mat)
     assert np.allclose(g[3].momentum, o[3]["momentum"], rtol=0, atol=1e-14)
     kw = dict(lam=0.1, mu=0.05, bc_lo=("dirichlet", (0.0, 0.0)), bc_hi=("neumann", (0.0, 2e-4)))
+    _compare(random_case(100, 60, 11, 0.05), 60, 1e-12, 1e-12, 1e-12, scheme=scheme, general=True, **kw)
     _compare(random_case(517, 77, 7, 0.05), 60, 1e-12, 1e-12, 1e-12, scheme=scheme, general=True, **kw)
     _compare(random_case(517, 77, 8, 0.05), 60, 1e-5, 1e-5, precision="fp32u64", scheme=scheme, general=True,
              **kw)
+    if scheme == "pc":  # 16-bit storage, two-row tiles
+        _compare(random_case(96, 64, 13, 0.05), 60, 1e-3, 1e-3, precision="fp16", scheme=scheme, general=True,
+                 **kw)
 
 
 def test_small_block_widths(gpu):
