@@ -5,7 +5,8 @@ the fused step kernel's shape (threads per block = columns per strip + halo,
 row segments per strip, one or two steps per launch), or the general step
 (2D tiles whose stages run in parallel, the faster one on small plates). For
 a plate size, precision and scheme the tuner times a short run of each
-candidate with HIP events on the solver's stream and keeps the fastest.
+candidate with HIP events on the solver's stream, times the fastest few
+again over longer runs, and keeps the fastest of those.
 Results are cached in a JSON file (``$LBM_AUTOTUNE_CACHE``, default
 ``~/.cache/lbm_solid/autotune.json``) keyed by device name and problem.
 
@@ -111,32 +112,56 @@ def apply_tiling(solver, tiling) -> None:
     solver.set_tiling(block, segs)
 
 
-def tune(solver, nx: int, ny: int, precision: str, scheme: str, steps: int = 6):
-    """Time every candidate; returns ((block, segs, steps per launch), ms per step, table)."""
+def _time(solver, stream, steps: int) -> float:
+    """ms per step of `steps` steps with HIP events on the solver's stream."""
     import torch
 
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(solver, nx: int, ny: int, precision: str, scheme: str, window_ms: float = 2.0, finalists: int = 3):
+    """Time every candidate; returns ((block, segs, steps per launch), ms per
+    step, table). The device is first kept busy for a while on the first
+    candidate (its clocks ramp up over the first milliseconds of work), each
+    candidate then runs a window of about `window_ms` (at least 6 steps),
+    and the `finalists` fastest run again over four such windows: the
+    fastest of those wins. Short single windows ranked shapes within a few
+    per cent of each other by noise."""
     stream = solver.stream
-    best, best_ms, table = None, float("inf"), []
-    for block, segs, spl in candidates(solver, nx, ny, precision, scheme):
-        apply_tiling(solver, (block, segs, spl))
+    cands = candidates(solver, nx, ny, precision, scheme)
+    apply_tiling(solver, cands[0])
+    solver.step(2)
+    t0 = _time(solver, stream, 4)
+    steps = max(6, min(400, int(window_ms / max(t0, 1e-4)) + 1))
+    _time(solver, stream, max(1, int(20.0 / max(t0, 1e-4))))  # about 20 ms of work
+    table = []
+    for c in cands:
+        apply_tiling(solver, c)
         solver.step(2)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        solver.step(steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        table.append([block, segs, spl, ms])
+        table.append([*c, _time(solver, stream, steps)])
+    table.sort(key=lambda r: r[3])
+    best, best_ms = None, float("inf")
+    for r in table[:finalists]:
+        c = tuple(r[:3])
+        apply_tiling(solver, c)
+        solver.step(2)
+        ms = _time(solver, stream, 4 * steps)
+        r.append(ms)
         if ms < best_ms:
-            best, best_ms = (block, segs, spl), ms
+            best, best_ms = c, ms
     return best, best_ms, table
 
 
 def best_tiling(solver, nx: int, ny: int, precision: str, scheme: str):
     import torch
 
-    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v6"
+    key = f"{torch.cuda.get_device_name(solver.device)}|{nx}x{ny}|{precision}|{scheme}|v7"
     cache = _load_cache()
     if key in cache:
         return tuple(cache[key]["tiling"])
