@@ -139,7 +139,7 @@ enum : unsigned char { SITE_NODE = 1, SITE_HOLE = 2, SITE_GHOST = 4 };
 
 // Bits of a tile's entry in the tile table (built on the host): the window
 // holds a hole node; the tile holds a material node; the fused step kernel
-// computes the tile (it lies clear of x walls and holes).
+// computes the tile (it lies clear of walls and holes).
 enum : unsigned char { TILE_HOLES = 1, TILE_MATERIAL = 2, TILE_FUSED = 4 };
 
 template <class PR, int MODE, bool SMALL = false>

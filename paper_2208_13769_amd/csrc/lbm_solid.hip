@@ -122,9 +122,9 @@ struct lbm_solver {
     int n_flist2 = 0, n_tlist_a = 0, n_tlist_b = 0;  // paired steps (n_flist2 = 0: none)
     Shape fshape2{};             // the two-step fused list's launch shape
     Shape fshape{};              // the fused list's launch shape (256 threads, one step)
-    // The fused share runs on a second stream beside the 2D tiles (forked
-    // from and joined back into the handle's stream each step); created on
-    // first use, default priority.
+    // The 2D tiles run on a second stream beside the fused share (forked
+    // from and joined back into the handle's stream each step or pair);
+    // created on first use, default priority.
     hipStream_t aux = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     ~lbm_solver()
@@ -585,9 +585,9 @@ namespace {
 // that holds a material node, and that the fused kernel computes instead.
 // The fused list: on a plate with x walls or holes, the tiles of the fused
 // step kernel (256-thread strips, row runs aligned to the 2D tiles' rows)
-// whose outputs lie farther than the stencil's reach from both. There the
-// fused kernel's periodic-x arithmetic is the general rules' arithmetic, and
-// it runs those sites at the fused kernel's rate.
+// whose outputs lie farther than the stencil's reach from every wall and
+// hole. There the fused kernel's periodic arithmetic is the general rules'
+// arithmetic, and it runs those sites at the fused kernel's rate.
 hipError_t build_general_tables(lbm_solver *h)
 {
     const int nx = h->nx, ny = h->ny;
