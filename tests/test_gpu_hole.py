@@ -141,6 +141,26 @@ def test_fused_share_of_the_general_step_matches_oracle(gpu, precision, scheme, 
     assert np.abs(ug[:, m == 0]).max() == 0.0
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32u64", 1e-5), ("fp16", 1e-3)])
+def test_fused_share_without_holes_matches_oracle(gpu, precision, tol):
+    """Walls on all four edges and no mask (the loaded block of Sec. 7.1 at
+    a size with a fused share): the fused kernel over the strips and rows
+    clear of the walls, the 2D tiles for one tile column and row at each
+    wall, paired and single steps, against the oracle."""
+    nx, ny, n = 700, 160, 41
+    rng = np.random.Generator(np.random.PCG64(36))
+    u0 = 0.002 * rng.standard_normal((2, ny, nx))
+    v0 = 0.002 * rng.standard_normal((2, ny, nx))
+    kinds = (N_, D_, D_, N_)
+    vals = [(0.0, 0.0), (0.0001, 0.0), (0.0, 0.0), (0.0, 2e-4)]
+    uo, vo, Po, so, do = _oracle(nx, ny, u0, v0, n, kinds, vals, None)
+    ug, vg, Pg, sg, dg, st, _ = _gpu(nx, ny, u0, v0, n, kinds, vals, None, precision=precision)
+    assert st == 0
+    e = [rel_l2(ug, uo), rel_l2(Pg, Po)]
+    print(f"fused share, walls only, {precision}: rel-L2 u {e[0]:.3e} P {e[1]:.3e}", flush=True)
+    assert max(e) < tol
+
+
 HOLE_N, HOLE_K = 4096, 5
 
 
